@@ -1,0 +1,260 @@
+"""Pins of the FP64 CPU oracle against what the paper and the mathematics fix.
+
+None of these re-types the oracle's formulas.  The anchors are:
+  * the dense L2-projection characterisation (tests/dense_l2.py): quadrature
+    Gram matrices, np.interp basis functions, dense solves;
+  * closed forms: the quadratic hierarchy (the paper's 1-D example function,
+    Fig. 1 caption) and exactness on multilinear fields;
+  * invariants: round trip, linearity, separability, affine coordinates;
+  * mutation checks: plausible slips planted in a copy of the oracle source
+    must make a pin fail.
+"""
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from dense_l2 import coarse_positions, dense_decompose, level_coords, projection_residual
+from paper_2105_12764_amd.synth import make_input
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+# ------------------------------------------------------------------ dense L2
+
+DENSE_CASES = [
+    ((9, 9, 9), 3, False),      # dyadic cube, full depth to 2^3
+    ((9, 9, 9), 2, True),       # non-uniform coords, partial depth
+    ((6, 7, 10), 2, True),      # non-dyadic, even and odd sizes
+    ((5, 2, 9), 2, True),       # a size-2 dimension (never coarsened)
+    ((17, 12), 4, True),        # 2-D, unequal depths
+    ((33,), 5, False),          # 1-D full depth
+    ((40,), 6, True),           # 1-D even size, non-uniform
+    ((3, 4, 3), 1, True),       # smallest coarsenable sizes
+]
+
+
+@pytest.mark.parametrize("shape,nlev,nonuni", DENSE_CASES)
+def test_oracle_matches_dense_projection(shape, nlev, nonuni):
+    u, c = make_input(shape, 11 + len(shape), nonuniform=nonuni)
+    got = oracle.decompose(u, c, nlev)
+    ref = dense_decompose(u, c, nlev)
+    assert rel(got, ref) < 1e-13
+
+
+@pytest.mark.parametrize("shape,nlev,nonuni", DENSE_CASES[:5])
+def test_oracle_coarse_is_orthogonal_projection(shape, nlev, nonuni):
+    """(u_h - q, phi_J) = 0 for every coarsest hat phi_J (Sec. II-A.2)."""
+    u, c = make_input(shape, 5, nonuniform=nonuni)
+    got = oracle.decompose(u, c, nlev)
+    coords = c if c is not None else [np.arange(n, dtype=float) for n in shape]
+    idx = []
+    for k, n in enumerate(shape):
+        lev = np.arange(n)
+        for _ in range(nlev):
+            lev = lev[coarse_positions(len(lev))]
+        idx.append(lev)
+    q = got[np.ix_(*idx)]
+    scale = np.max(np.abs(u)) * np.prod([coords[k][-1] - coords[k][0] for k in range(len(shape))])
+    assert projection_residual(u, q, coords, nlev) < 1e-13 * scale
+
+
+# ------------------------------------------------------------- closed forms
+
+def test_golden_quadratic_example():
+    """Hand-derived hierarchy of y = x^2 - 5x + 6 (paper Fig. 1 caption)."""
+    rows = np.loadtxt(os.path.join(HERE, "golden", "quadratic_1d.txt"))
+    x, u, want = rows[:, 0], rows[:, 1], rows[:, 2]
+    assert np.allclose(u, x * x - 5 * x + 6)
+    got = oracle.decompose(u, [x], 2)
+    assert np.max(np.abs(got - want)) < 1e-14
+
+
+@pytest.mark.parametrize("L,h", [(6, 1.0), (5, 0.25)])
+def test_quadratic_hierarchy_closed_form(L, h):
+    """u = a x^2 + b x + c on a uniform dyadic grid: the class dropped at step s
+    (fine spacing h_s) is exactly -a h_s^2, and the coarsest nodes hold
+    u - (a/2) sum_s h_s^2."""
+    rng = np.random.default_rng(3)
+    a, b, c0 = rng.uniform(-2, 2, 3)
+    n = 2 ** L + 1
+    x = h * np.arange(n)
+    u = a * x * x + b * x + c0
+    got = oracle.decompose(u, [x], L)
+    pos = np.arange(n)
+    shift = 0.0
+    for s in range(L):
+        hs = h * 2 ** s
+        fine = pos[(pos % 2 ** s == 0) & ((pos // 2 ** s) % 2 == 1)]
+        assert np.allclose(got[fine], -a * hs * hs, rtol=0, atol=1e-12 * (abs(a) * hs * hs + 1))
+        shift += hs * hs
+    ends = np.array([0, n - 1])
+    assert np.allclose(got[ends], u[ends] - 0.5 * a * shift, rtol=0, atol=1e-11)
+
+
+def _multilinear_from_coarse(shape, coords, nlev, rng):
+    """A field that is piecewise multilinear on the final coarse grid."""
+    xs = [level_coords(coords[k], nlev) for k in range(len(shape))]
+    cshape = [len(xs[k][nlev]) for k in range(len(shape))]
+    q = rng.standard_normal(cshape)
+    f = q
+    for k in range(len(shape)):
+        f = np.apply_along_axis(lambda v: np.interp(xs[k][0], xs[k][nlev], v), k, f)
+    return f, q
+
+
+@pytest.mark.parametrize("shape,nlev,nonuni", [((17, 17, 17), 3, False), ((12, 9, 14), 2, True),
+                                                ((65, 33), 4, True), ((100,), 6, True)])
+def test_multilinear_field_has_zero_coefficients(shape, nlev, nonuni):
+    rng = np.random.default_rng(21)
+    _, c = make_input(shape, 2, nonuniform=nonuni)
+    coords = c if c is not None else [np.arange(n, dtype=float) for n in shape]
+    u, q = _multilinear_from_coarse(shape, coords, nlev, rng)
+    got = oracle.decompose(u, coords, nlev)
+    idx = []
+    for n in shape:
+        lev = np.arange(n)
+        for _ in range(nlev):
+            lev = lev[coarse_positions(len(lev))]
+        idx.append(lev)
+    mask = np.ones(shape, bool)
+    mask[np.ix_(*idx)] = False
+    assert np.max(np.abs(got[mask])) < 1e-13 * np.max(np.abs(q))
+    assert np.max(np.abs(got[np.ix_(*idx)] - q)) < 1e-13 * np.max(np.abs(q))
+    # recompose of all-zero coefficients is the multilinear interpolant
+    z = np.zeros(shape)
+    z[np.ix_(*idx)] = q
+    assert rel(oracle.recompose(z, coords, nlev), u) < 1e-13
+
+
+# --------------------------------------------------------------- invariants
+
+@pytest.mark.parametrize("shape,nlev,nonuni", [((65, 65, 65), 5, False), ((40, 30, 25), 5, True),
+                                                ((129, 70), 7, True), ((1000,), 9, True)])
+def test_round_trip(shape, nlev, nonuni):
+    u, c = make_input(shape, 1001, nonuniform=nonuni)
+    d = oracle.decompose(u, c, nlev)
+    assert rel(oracle.recompose(d, c, nlev), u) < 1e-12
+
+
+def test_linearity():
+    u, c = make_input((20, 15, 18), 4, nonuniform=True)
+    w, _ = make_input((20, 15, 18), 5, nonuniform=True)
+    a, b = 1.75, -0.3
+    lhs = oracle.decompose(a * u + b * w, c, 3)
+    rhs = a * oracle.decompose(u, c, 3) + b * oracle.decompose(w, c, 3)
+    assert rel(lhs, rhs) < 1e-13
+
+
+def test_affine_coordinates():
+    u, c = make_input((17, 10, 13), 6, nonuniform=True)
+    c2 = [3.5 * x - 7.0 for x in c]
+    assert rel(oracle.decompose(u, c2, 3), oracle.decompose(u, c, 3)) < 1e-12
+
+
+def test_separable_field_coarsest_is_outer_product():
+    """Q = Q^x (x) Q^y (x) Q^z on tensor grids, so the coarsest values of a
+    separable field are the outer product of the 1-D coarsest values."""
+    rng = np.random.default_rng(8)
+    shape, nlev = (33, 17, 21), 4
+    coords = [np.cumsum(rng.uniform(0.5, 1.5, n)) for n in shape]
+    g = [rng.standard_normal(n) for n in shape]
+    u = np.einsum("i,j,k->ijk", *g)
+    full = oracle.decompose(u, coords, nlev)
+    idx, ones = [], []
+    for k, n in enumerate(shape):
+        lev = np.arange(n)
+        for _ in range(nlev):
+            lev = lev[coarse_positions(len(lev))]
+        idx.append(lev)
+        ones.append(oracle.decompose(g[k], [coords[k]], nlev)[lev])
+    want = np.einsum("i,j,k->ijk", *ones)
+    assert rel(full[np.ix_(*idx)], want) < 1e-12
+
+
+def test_max_levels_and_rejections():
+    assert oracle.max_levels((513, 513, 513)) == 9
+    assert oracle.max_levels((65, 65, 65)) == 6
+    assert oracle.max_levels((400, 300, 250)) == 9
+    assert oracle.max_levels((2, 2)) == 0
+    with pytest.raises(ValueError):
+        oracle.decompose(np.zeros((5, 5)), None, 4)
+    with pytest.raises(ValueError):
+        oracle.decompose(np.zeros(5), [np.array([0, 1, 1, 2, 3.0])], 1)
+
+
+# ------------------------------------------------------------ mutation checks
+
+# Each entry plants one plausible slip in a copy of the oracle's C source.
+MUTANTS = {
+    "mass_diag_scale": ("double diag = (hl + hr) / 3.0", "double diag = (hl + hr) / 2.0"),
+    "mass_offdiag_index": ("lo = hl / 6.0, up = hr / 6.0", "lo = hr / 6.0, up = hl / 6.0"),
+    "correction_sign": ("v[off] = Uc[cf] + z[cf];", "v[off] = Uc[cf] - z[cf];"),
+    "interp_weights_swapped": (
+        "for (int64_t t = 0; t < inner; ++t) d[t] = wl * sl[t] + wr * sr[t];",
+        "for (int64_t t = 0; t < inner; ++t) d[t] = wr * sl[t] + wl * sr[t];"),
+    "restrict_weight_dropped": ("dr[t] += wr * s[t];", "dr[t] += 0.0 * s[t];"),
+    "thomas_back_sign": ("line[i * inner] - cp[i] * line[(i + 1) * inner]",
+                          "line[i * inner] + cp[i] * line[(i + 1) * inner]"),
+    "solve_on_fine_coords": ("thomas_axis(cur, sh, nd, k, H->x[s + 1][k]);",
+                              "thomas_axis(cur, sh, nd, k, H->x[s][k]);"),
+    "last_even_node_index": ("return (i == m - 1) ? coarse_count(m) - 1 : i / 2;",
+                              "return i / 2;"),
+}
+
+
+def _build_mutant(tmp_path, name):
+    src = open(os.path.join(os.path.dirname(oracle.__file__), "mgr_oracle.c")).read()
+    old, new = MUTANTS[name]
+    assert src.count(old) == 1, name
+    path = tmp_path / f"{name}.c"
+    path.write_text(src.replace(old, new))
+    so = tmp_path / f"{name}.so"
+    subprocess.run(["gcc", "-O1", "-fPIC", "-shared", "-std=c11", "-o", str(so), str(path), "-lm"],
+                   check=True)
+    return so
+
+
+# The mutant runs in a child process: a planted indexing slip may crash it,
+# which also counts as caught.
+_CHILD = r"""
+import ctypes, sys
+import numpy as np
+so, inp, outp = sys.argv[1:4]
+data = np.load(inp)
+u = np.ascontiguousarray(data["u"])
+coords = [np.ascontiguousarray(data[f"c{k}"]) for k in range(u.ndim)]
+lib = ctypes.CDLL(so)
+dp = ctypes.POINTER(ctypes.c_double)
+lib.oracle_decompose.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int64),
+                                 ctypes.POINTER(dp), ctypes.c_int, dp, dp]
+out = np.empty_like(u)
+sh = (ctypes.c_int64 * u.ndim)(*u.shape)
+arr = (dp * u.ndim)(*[x.ctypes.data_as(dp) for x in coords])
+rc = lib.oracle_decompose(u.ndim, sh, arr, int(data["nlev"]), u.ctypes.data_as(dp),
+                          out.ctypes.data_as(dp))
+np.save(outp, out if rc == 0 else np.full_like(u, np.nan))
+"""
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_planted_mistake_is_caught(tmp_path, name):
+    so = _build_mutant(tmp_path, name)
+    u, c = make_input((6, 7, 10), 17, nonuniform=True)
+    inp, outp = tmp_path / "in.npz", tmp_path / "out.npy"
+    np.savez(inp, u=u, nlev=2, **{f"c{k}": x for k, x in enumerate(c)})
+    r = subprocess.run([sys.executable, "-c", _CHILD, str(so), str(inp), str(outp)],
+                       capture_output=True, timeout=60)
+    if r.returncode != 0:
+        return  # crashed: caught
+    got = np.load(outp)
+    ref = dense_decompose(u, c, 2)
+    err = rel(got, ref)
+    assert not (err < 1e-8), f"mutant {name} slipped through the dense pin"  # NaN counts as caught
