@@ -1,0 +1,185 @@
+#!/usr/bin/env python3
+"""Decompose + recompose throughput of the multigrid refactoring on one MI355X.
+
+A step is one full decomposition followed by one full recomposition of the
+workload (every level, every kernel of the path), inputs resident in HBM.
+Prints one JSON line:
+  value        refactoring throughput, the paper's unit (Sec. V-D): bytes of
+               field decomposed plus bytes recomposed per second,
+               2 * n * sizeof(dtype) / (t_decompose + t_recompose), in GB/s;
+  roofline     the dominant kernel's algorithmic bytes per launch / its mean
+               launch time from HIP events recorded on the launch stream over
+               the timed region, against the 8 TB/s HBM peak;
+  cpu_baseline the FP64 CPU oracle on the same workload (one step), GB/s in
+               the same unit, with the number of threads it used.
+Extra keys: the algorithmic-byte rate of the whole step, per-kernel totals,
+the FP32 mode on the same grid, and the round-trip error of the timed data.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "decompose+recompose GB/s at 513^3 FP64/FP32 (% HBM peak); batched p50/p99 ms"
+
+
+def _log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def run_gpu(name: str, steps: int, warmup: int):
+    import torch
+
+    from paper_2105_12764_amd import mgr
+    from paper_2105_12764_amd.synth import WORKLOADS, make_input
+
+    shape, seed, nonuni, dtype, nlev = WORKLOADS[name]
+    _log(f"[bench] {name}: generating {shape} {np.dtype(dtype).name}")
+    u, coords = make_input(shape, seed, nonuniform=nonuni, dtype=dtype)
+    dev = torch.device("cuda:0")
+    x = torch.from_numpy(u).to(dev)
+    d = torch.empty_like(x)
+    r = torch.empty_like(x)
+    ws = mgr.alloc_workspace(shape, x.dtype, nlev, device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def step(ev=None):
+        mgr.decompose(x, coords, nlev, out=d, workspace=ws, stream=stream)
+        if ev is not None:
+            ev.record(stream)
+        mgr.recompose(d, coords, nlev, out=r, workspace=ws, stream=stream)
+
+    _log(f"[bench] {name}: warmup {warmup}")
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+
+    mgr.timing_reset()
+    mgr.timing_enable(True)
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    mids = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        starts[i].record(stream)
+        step(mids[i])
+        ends[i].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    mgr.timing_enable(False)
+    totals = mgr.timing_totals()
+    t_dec = sum(starts[i].elapsed_time(mids[i]) for i in range(steps)) / steps
+    t_rec = sum(mids[i].elapsed_time(ends[i]) for i in range(steps)) / steps
+    _log(f"[bench] {name}: {steps} steps, dec {t_dec:.3f} ms, rec {t_rec:.3f} ms")
+
+    rt_err = float((r.double() - x.double()).abs().max() / x.double().abs().max())
+    n = int(np.prod(shape))
+    esz = np.dtype(dtype).itemsize
+    ms_step = wall * 1e3 / steps
+    value = 2.0 * n * esz / ((t_dec + t_rec) * 1e-3) / 1e9
+    alg_bytes_step = sum(b for (_, _, b) in totals.values()) / steps
+    kernels = {k: {"launches_per_step": v[0] / steps, "ms_per_step": v[1] / steps,
+                   "alg_GBps": (v[2] / (v[1] * 1e-3) / 1e9) if v[1] > 0 else None}
+               for k, v in sorted(totals.items(), key=lambda kv: -kv[1][1])}
+    dom_name, (dom_n, dom_ms, dom_b) = max(totals.items(), key=lambda kv: kv[1][1])
+    achieved = dom_b / (dom_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom_name,
+                "alg_bytes_per_launch": dom_b / dom_n, "mean_launch_us": dom_ms * 1e3 / dom_n}
+    res = {
+        "workload": name, "shape": list(shape), "dtype": np.dtype(dtype).name, "nlevels": nlev,
+        "t_dec_ms": t_dec, "t_rec_ms": t_rec, "ms_per_step": ms_step, "value": value,
+        "alg_GB_per_step": alg_bytes_step / 1e9,
+        "alg_GBps": alg_bytes_step / ((t_dec + t_rec) * 1e-3) / 1e9,
+        "roundtrip_max_rel_err": rt_err, "kernels": kernels, "roofline": roofline,
+    }
+    del x, d, r, ws
+    torch.cuda.empty_cache()
+    return res, u, coords, nlev
+
+
+def cpu_baseline(u, coords, nlev):
+    import oracle
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
+    os.environ["OMP_NUM_THREADS"] = str(threads)
+    u64 = np.ascontiguousarray(u, dtype=np.float64)
+    _log(f"[bench] cpu baseline: oracle decompose+recompose, {threads} threads")
+    t0 = time.perf_counter()
+    d = oracle.decompose(u64, coords, nlev)
+    oracle.recompose(d, coords, nlev)
+    dt = time.perf_counter() - t0
+    n = u.size
+    return {"value": round(2.0 * n * u.dtype.itemsize / dt / 1e9, 4), "unit": "GB/s",
+            "cores": threads, "kind": "oracle",
+            "sample": f"one decompose+recompose of the full {'x'.join(map(str, u.shape))} "
+                      f"workload ({dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="cube513_f64")
+    ap.add_argument("--fp32-workload", default="cube513_f32")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported "
+              "(this refactoring path runs on a single MI355X)", file=sys.stderr)
+        sys.exit(2)
+
+    res, u, coords, nlev = run_gpu(args.workload, args.steps, args.warmup)
+    fp32 = None
+    if not args.no_fp32 and args.fp32_workload:
+        r32, _, _, _ = run_gpu(args.fp32_workload, args.steps, args.warmup)
+        fp32 = {k: r32[k] for k in ("workload", "value", "t_dec_ms", "t_rec_ms", "alg_GBps",
+                                     "roundtrip_max_rel_err", "roofline")}
+    cpu = None if args.no_cpu_baseline else cpu_baseline(u, coords, nlev)
+
+    line = {
+        "metric": METRIC,
+        "value": round(res["value"], 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(res["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if res["dtype"] == "float64" else "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{res['workload']}: {'x'.join(map(str, res['shape']))} "
+                               f"{res['dtype']}, {res['nlevels']} levels, one decompose + one "
+                               "recompose per step",
+                   "shape": res["shape"], "nlevels": res["nlevels"]},
+        "t_dec_ms": round(res["t_dec_ms"], 4),
+        "t_rec_ms": round(res["t_rec_ms"], 4),
+        "alg_GBps": round(res["alg_GBps"], 1),
+        "pct_hbm_peak": round(100.0 * res["alg_GBps"] / HBM_PEAK_GBS, 2),
+        "roundtrip_max_rel_err": res["roundtrip_max_rel_err"],
+        "roofline": res["roofline"],
+        "cpu_baseline": cpu,
+        "kernels": res["kernels"],
+        "fp32": fp32,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,144 @@
+/*
+ * mgr.h -- C ABI of libmgr: multigrid hierarchical decomposition (refactor)
+ * and recomposition of structured N-D floating-point fields on an AMD
+ * MI355X (gfx950) GPU.
+ *
+ * Method: Chen et al., "Scalable Multigrid-based Hierarchical Scientific
+ * Data Refactoring on GPUs" (arXiv 2105.12764), Sec. II-A.  One
+ * decomposition step takes the level-l grid N_l to N_{l-1}:
+ *   1. coefficients: every node of N_l \ N_{l-1} gets its value minus the
+ *      multilinear interpolant from N_{l-1} (Sec. II-A.1);
+ *   2. load vector f_{l-1} = R_l M_l vec(C_l), applied one dimension at a
+ *      time (Sec. II-A.2, mass and transfer matrices of Sec. III-A.2);
+ *   3. correction z_{l-1} = M_{l-1}^{-1} f_{l-1}, tridiagonal solves along
+ *      each dimension (Sec. II-A.2, Thomas algorithm of Sec. III-A.3);
+ *   4. the correction is added to the N_{l-1} nodes (Eq. 1).
+ * Recomposition runs the steps in reverse, coarsest to finest (Sec. II-A,
+ * "Overall decomposition/recomposition process").
+ *
+ * Conventions where the paper is silent:
+ *   - arrays are C order (dimension 0 slowest, ndim-1 contiguous);
+ *   - along a dimension with m >= 3 level nodes the next coarser grid keeps
+ *     positions 0, 2, 4, ... and m-1; a dimension with m = 2 is no longer
+ *     coarsened.  For m = 2^k + 1 this is the paper's dyadic hierarchy;
+ *   - output layout is NODAL: same shape as the input; a node dropped at a
+ *     level holds its coefficient, the final coarsest nodes hold the
+ *     corrected coarse values Q u.  nlevels = 0 is a copy;
+ *   - coordinates default to 0, 1, ..., n-1.
+ *
+ * Precision: MGR_FLOAT64 computes everything in FP64.  MGR_FLOAT32 stores
+ * FP32 (input, output, coarse grids) and evaluates every step in FP64
+ * registers, with the load vector and the tridiagonal solves held in FP64
+ * workspace; values are rounded to FP32 once, where they are stored.
+ *
+ * Threading: every entry point is thread-safe.  Calls are stream-ordered
+ * and asynchronous: they return after enqueuing work on `stream`.
+ */
+#ifndef MGR_H
+#define MGR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MGR_OK = 0,
+  MGR_ERR_INVALID_ARG = 1,   /* bad ndim/shape/coords/nlevels/pointer/overlap */
+  MGR_ERR_UNSUPPORTED = 2,   /* valid request this build does not handle */
+  MGR_ERR_WORKSPACE = 3,     /* workspace NULL or smaller than required */
+  MGR_ERR_OUT_OF_MEMORY = 4, /* plan tables could not be allocated */
+  MGR_ERR_DEVICE = 5         /* a HIP call or kernel launch failed */
+} mgr_status;
+
+typedef enum { MGR_FLOAT32 = 0, MGR_FLOAT64 = 1 } mgr_dtype;
+
+/* Largest valid level count for `shape`: the number of coarsening steps of
+ * its deepest dimension (a dimension of m >= 3 nodes goes to m/2 + 1).
+ * ndim in 1..3, every shape[k] >= 2.  Returns -MGR_ERR_INVALID_ARG on a bad
+ * shape.  Host only, no GPU needed. */
+int mgr_max_levels(int ndim, const int64_t *shape);
+
+/* Bytes of device workspace that mgr_decompose / mgr_recompose need for this
+ * request (0 when nlevels == 0).  Host only, no GPU needed.  Returns
+ * MGR_ERR_INVALID_ARG for a bad shape, dtype or level count. */
+mgr_status mgr_workspace_size(int ndim, const int64_t *shape, mgr_dtype dtype,
+                              int nlevels, size_t *bytes);
+
+/* Decompose `in` into its nodal multilevel representation `out`.
+ *   ndim, shape : 1..3 dimensions, each >= 2 nodes, C order.
+ *   coords      : host pointer to ndim host arrays of shape[k] doubles,
+ *                 strictly increasing and finite; coords == NULL or
+ *                 coords[k] == NULL selects 0..shape[k]-1.  Read during the
+ *                 call only (the library keeps its own tables).
+ *   dtype       : element type of in and out.
+ *   nlevels     : 0 .. mgr_max_levels(ndim, shape).
+ *   in, out     : device pointers, prod(shape) elements each, caller-owned,
+ *                 not overlapping.  `in` must stay unchanged until the
+ *                 stream reaches this call's work.
+ *   workspace   : device pointer, caller-owned, >= mgr_workspace_size bytes,
+ *                 256-byte aligned; contents on entry are ignored.  Not
+ *                 shared by calls that may run concurrently.
+ *   stream      : hipStream_t to enqueue on (NULL = the null stream).
+ * All argument checks happen before anything is enqueued; on any error
+ * nothing is launched and `out` is untouched.  The first call for a new
+ * (shape, coords, nlevels) on a device builds FP64 tables on the host and
+ * uploads them (one synchronous allocation and copy); later calls reuse
+ * them. */
+mgr_status mgr_decompose(int ndim, const int64_t *shape,
+                         const double *const *coords, mgr_dtype dtype,
+                         int nlevels, const void *in, void *out,
+                         void *workspace, size_t workspace_bytes,
+                         void *stream);
+
+/* Recompose the field from its nodal multilevel representation: the inverse
+ * of mgr_decompose with the same shape, coords and nlevels.  Arguments,
+ * ownership and errors as for mgr_decompose (here `in` is the
+ * representation and `out` the field). */
+mgr_status mgr_recompose(int ndim, const int64_t *shape,
+                         const double *const *coords, mgr_dtype dtype,
+                         int nlevels, const void *in, void *out,
+                         void *workspace, size_t workspace_bytes,
+                         void *stream);
+
+/* Static English name of a status code. */
+const char *mgr_status_string(mgr_status s);
+
+/* Detail of the calling thread's last failure ("" if none).  The pointer is
+ * valid until the thread's next libmgr call. */
+const char *mgr_last_error(void);
+
+/* Drop every cached plan and free its device tables.  The caller must make
+ * sure no enqueued libmgr work is still pending. */
+void mgr_release_caches(void);
+
+/* ---- Instrumentation (benchmarking only; not part of the method) --------
+ * While enabled, every kernel launch of later calls is bracketed by a pair of
+ * HIP events recorded on the launch's own stream, and its algorithmic
+ * traffic (the bytes the method must move for that launch: each input read
+ * once, each output written once) is accumulated per kernel name.  Intended
+ * for one thread driving the library. */
+
+/* Turn event recording on (on != 0) or off.  Always MGR_OK. */
+mgr_status mgr_timing_enable(int on);
+
+/* Wait for the recorded events and drop all totals. */
+void mgr_timing_reset(void);
+
+/* Wait for the recorded events; number of distinct kernels with totals. */
+int mgr_timing_count(void);
+
+/* Totals of kernel `index` (0 .. mgr_timing_count()-1): its name (static
+ * until the next reset), launches, summed event time in milliseconds and
+ * summed algorithmic bytes.  Any output pointer may be NULL.  Returns
+ * MGR_ERR_INVALID_ARG for an index out of range. */
+mgr_status mgr_timing_get(int index, const char **name, int64_t *launches,
+                          double *total_ms, double *alg_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MGR_H */

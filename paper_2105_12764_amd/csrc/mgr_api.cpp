@@ -1,0 +1,242 @@
+// mgr_api.cpp -- the extern "C" boundary of libmgr (declared in include/mgr.h):
+// argument validation, the per-device plan cache and dispatch to the HIP
+// kernels.  No exception crosses the boundary.
+#include <hip/hip_runtime_api.h>
+
+#include <cmath>
+#include <cstring>
+#include <list>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/mgr.h"
+#include "mgr_kernels.hpp"
+#include "mgr_plan.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+mgr_status fail(mgr_status s, const std::string &msg) {
+  g_last_error = msg;
+  return s;
+}
+
+struct CacheEntry {
+  int device;
+  int ndim;
+  int64_t n[mgr::kDims];
+  int nlev;
+  std::vector<std::vector<double>> coords;
+  std::shared_ptr<mgr::Plan> plan;
+};
+
+std::mutex g_mu;
+std::list<CacheEntry> g_cache;  // most recently used first
+constexpr size_t kCacheMax = 64;
+
+// Pads the caller's shape to rank 3 with leading 1s.
+bool pad_shape(int ndim, const int64_t *shape, int64_t n[mgr::kDims], std::string &why) {
+  if (ndim < 1 || ndim > 3) {
+    why = "ndim must be 1, 2 or 3 (got " + std::to_string(ndim) + ")";
+    return false;
+  }
+  if (!shape) {
+    why = "shape is NULL";
+    return false;
+  }
+  for (int k = 0; k < mgr::kDims; ++k) n[k] = 1;
+  for (int k = 0; k < ndim; ++k) {
+    if (shape[k] < 2) {
+      why = "shape[" + std::to_string(k) + "] must be >= 2";
+      return false;
+    }
+    if (shape[k] > (int64_t)1 << 31) {
+      why = "shape[" + std::to_string(k) + "] too large";
+      return false;
+    }
+    n[mgr::kDims - ndim + k] = shape[k];
+  }
+  const int64_t total = n[0] * n[1] * n[2];
+  if (total <= 0 || total > ((int64_t)1 << 40)) {
+    why = "total element count out of range";
+    return false;
+  }
+  return true;
+}
+
+mgr_status validate(int ndim, const int64_t *shape, const double *const *coords, int dtype,
+                    int nlevels, const void *in, void *out, void *ws, size_t ws_bytes,
+                    int64_t n[mgr::kDims], std::vector<std::vector<double>> &cx) {
+  std::string why;
+  if (!pad_shape(ndim, shape, n, why)) return fail(MGR_ERR_INVALID_ARG, why);
+  if (dtype != MGR_FLOAT32 && dtype != MGR_FLOAT64)
+    return fail(MGR_ERR_INVALID_ARG, "dtype must be MGR_FLOAT32 or MGR_FLOAT64");
+  const int ml = mgr::max_levels3(n);
+  if (nlevels < 0 || nlevels > ml)
+    return fail(MGR_ERR_INVALID_ARG, "nlevels must be in [0, " + std::to_string(ml) + "]");
+  if (nlevels > mgr::kMaxLevels) return fail(MGR_ERR_UNSUPPORTED, "too many levels");
+  if (!in || !out) return fail(MGR_ERR_INVALID_ARG, "in and out must be non-NULL device pointers");
+  const size_t esz = dtype == MGR_FLOAT64 ? 8 : 4;
+  const size_t bytes = (size_t)(n[0] * n[1] * n[2]) * esz;
+  const char *a = (const char *)in, *b = (const char *)out;
+  if (a < b + bytes && b < a + bytes) return fail(MGR_ERR_INVALID_ARG, "in and out overlap");
+  cx.assign(mgr::kDims, {});
+  for (int k = 0; k < mgr::kDims; ++k) {
+    const int uk = k - (mgr::kDims - ndim);
+    const double *src = (uk >= 0 && coords) ? coords[uk] : nullptr;
+    cx[k].resize(n[k]);
+    for (int64_t i = 0; i < n[k]; ++i) {
+      const double v = src ? src[i] : (double)i;
+      if (!std::isfinite(v))
+        return fail(MGR_ERR_INVALID_ARG, "coords[" + std::to_string(uk) + "] has a non-finite value");
+      if (i > 0 && !(v > cx[k][i - 1]))
+        return fail(MGR_ERR_INVALID_ARG,
+                    "coords[" + std::to_string(uk) + "] is not strictly increasing");
+      cx[k][i] = v;
+    }
+  }
+  const size_t need = mgr::workspace_bytes(n, nlevels, esz);
+  if (need > 0) {
+    if (!ws) return fail(MGR_ERR_WORKSPACE, "workspace is NULL");
+    if (ws_bytes < need)
+      return fail(MGR_ERR_WORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+    if ((uintptr_t)ws % 256 != 0) return fail(MGR_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    const char *w = (const char *)ws;
+    if ((w < a + bytes && a < w + need) || (w < b + bytes && b < w + need))
+      return fail(MGR_ERR_INVALID_ARG, "workspace overlaps in or out");
+  }
+  return MGR_OK;
+}
+
+mgr_status get_plan(const int64_t n[mgr::kDims], int ndim, int nlevels,
+                    const std::vector<std::vector<double>> &cx, std::shared_ptr<mgr::Plan> &out) {
+  int dev = -1;
+  hipError_t he = hipGetDevice(&dev);
+  if (he != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(MGR_ERR_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(he));
+  }
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (auto it = g_cache.begin(); it != g_cache.end(); ++it) {
+    if (it->device != dev || it->ndim != ndim || it->nlev != nlevels) continue;
+    if (std::memcmp(it->n, n, sizeof(it->n)) != 0) continue;
+    if (it->coords != cx) continue;
+    out = it->plan;
+    g_cache.splice(g_cache.begin(), g_cache, it);
+    return MGR_OK;
+  }
+  std::string err;
+  int st = 0;
+  std::unique_ptr<mgr::Plan> p;
+  try {
+    p = mgr::build_plan(ndim, n, cx, nlevels, err, st);
+  } catch (const std::bad_alloc &) {
+    return fail(MGR_ERR_OUT_OF_MEMORY, "host allocation failed while building the plan");
+  } catch (...) {
+    return fail(MGR_ERR_DEVICE, "unexpected failure while building the plan");
+  }
+  if (!p) return fail((mgr_status)st, err);
+  CacheEntry e;
+  e.device = dev;
+  e.ndim = ndim;
+  std::memcpy(e.n, n, sizeof(e.n));
+  e.nlev = nlevels;
+  e.coords = cx;
+  e.plan = std::shared_ptr<mgr::Plan>(p.release());
+  out = e.plan;
+  g_cache.push_front(std::move(e));
+  while (g_cache.size() > kCacheMax) g_cache.pop_back();
+  return MGR_OK;
+}
+
+mgr_status run(bool dec, int ndim, const int64_t *shape, const double *const *coords, int dtype,
+               int nlevels, const void *in, void *out, void *ws, size_t ws_bytes, void *stream) {
+  g_last_error.clear();
+  try {
+    int64_t n[mgr::kDims];
+    std::vector<std::vector<double>> cx;
+    mgr_status s = validate(ndim, shape, coords, dtype, nlevels, in, out, ws, ws_bytes, n, cx);
+    if (s != MGR_OK) return s;
+    std::shared_ptr<mgr::Plan> plan;
+    s = get_plan(n, ndim, nlevels, cx, plan);
+    if (s != MGR_OK) return s;
+    std::string err;
+    const bool f64 = dtype == MGR_FLOAT64;
+    const bool ok = dec ? mgr::enqueue_decompose(*plan, f64, in, out, ws, stream, err)
+                        : mgr::enqueue_recompose(*plan, f64, in, out, ws, stream, err);
+    if (!ok) return fail(MGR_ERR_DEVICE, err);
+    return MGR_OK;
+  } catch (const std::bad_alloc &) {
+    return fail(MGR_ERR_OUT_OF_MEMORY, "host allocation failed");
+  } catch (...) {
+    return fail(MGR_ERR_DEVICE, "unexpected internal failure");
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int mgr_max_levels(int ndim, const int64_t *shape) {
+  int64_t n[mgr::kDims];
+  std::string why;
+  if (!pad_shape(ndim, shape, n, why)) {
+    g_last_error = why;
+    return -MGR_ERR_INVALID_ARG;
+  }
+  return mgr::max_levels3(n);
+}
+
+mgr_status mgr_workspace_size(int ndim, const int64_t *shape, mgr_dtype dtype, int nlevels,
+                              size_t *bytes) {
+  g_last_error.clear();
+  int64_t n[mgr::kDims];
+  std::string why;
+  if (!bytes) return fail(MGR_ERR_INVALID_ARG, "bytes is NULL");
+  if (!pad_shape(ndim, shape, n, why)) return fail(MGR_ERR_INVALID_ARG, why);
+  if (dtype != MGR_FLOAT32 && dtype != MGR_FLOAT64)
+    return fail(MGR_ERR_INVALID_ARG, "dtype must be MGR_FLOAT32 or MGR_FLOAT64");
+  const int ml = mgr::max_levels3(n);
+  if (nlevels < 0 || nlevels > ml)
+    return fail(MGR_ERR_INVALID_ARG, "nlevels must be in [0, " + std::to_string(ml) + "]");
+  *bytes = mgr::workspace_bytes(n, nlevels, dtype == MGR_FLOAT64 ? 8 : 4);
+  return MGR_OK;
+}
+
+mgr_status mgr_decompose(int ndim, const int64_t *shape, const double *const *coords,
+                         mgr_dtype dtype, int nlevels, const void *in, void *out, void *workspace,
+                         size_t workspace_bytes, void *stream) {
+  return run(true, ndim, shape, coords, (int)dtype, nlevels, in, out, workspace, workspace_bytes,
+             stream);
+}
+
+mgr_status mgr_recompose(int ndim, const int64_t *shape, const double *const *coords,
+                         mgr_dtype dtype, int nlevels, const void *in, void *out, void *workspace,
+                         size_t workspace_bytes, void *stream) {
+  return run(false, ndim, shape, coords, (int)dtype, nlevels, in, out, workspace, workspace_bytes,
+             stream);
+}
+
+const char *mgr_status_string(mgr_status s) {
+  switch (s) {
+    case MGR_OK: return "ok";
+    case MGR_ERR_INVALID_ARG: return "invalid argument";
+    case MGR_ERR_UNSUPPORTED: return "unsupported request";
+    case MGR_ERR_WORKSPACE: return "workspace missing or too small";
+    case MGR_ERR_OUT_OF_MEMORY: return "out of memory";
+    case MGR_ERR_DEVICE: return "device error";
+  }
+  return "unknown status";
+}
+
+const char *mgr_last_error(void) { return g_last_error.c_str(); }
+
+void mgr_release_caches(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_cache.clear();
+}
+
+}  // extern "C"

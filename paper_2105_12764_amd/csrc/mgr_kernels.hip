@@ -1,0 +1,818 @@
+// mgr_kernels.hip -- CDNA4 (gfx950) kernels of the multigrid refactoring
+// hot path and the host code that enqueues one decomposition or
+// recomposition (arXiv 2105.12764, Sec. II-A; kernel roles of Sec. III-A).
+//
+// One step l -> l-1 of the decomposition is three launches:
+//   k_loadvec   reads the level grid once.  Per plane along dimension 0 it
+//               stages a (rows x columns) tile with a two-node halo in LDS,
+//               forms the coefficients (value minus the multilinear
+//               interpolant, Sec. II-A.1), writes them to their nodal
+//               positions, keeps the coarse values compactly (the paper's
+//               reordered layout, Sec. III-C) and applies the load-vector
+//               operator P^T M along dimensions 2 and 1 in LDS.  Along
+//               dimension 0 it keeps a five-plane ring and emits each coarse
+//               plane of f = R M C as soon as its taps are complete.  This
+//               fuses the paper's coefficient and mass-transfer kernels
+//               (GPK, LPK) into one pass over the data.
+//   k_solve_*   the correction solves M_{l-1} z = f along each coarsened
+//               dimension (Sec. II-A.2; IPK role).  Each line is held in
+//               registers, cut into partitions solved independently plus a
+//               small separator system (exact, see mgr_plan.cpp), so every
+//               solve reads and writes the coarse grid once.  Strided
+//               dimensions put 64 adjacent lines on the 64 lanes of a wave
+//               (coalesced); the contiguous dimension stages rows through LDS.
+//               The last solve of a step applies the correction in its store
+//               (coarse <- coarse + z), so no separate pass adds it.
+// Recomposition runs the same load-vector and solve kernels on the stored
+// coefficients, subtracts z, and k_reconstruct adds the interpolant back.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <string>
+
+#include "mgr_kernels.hpp"
+#include "mgr_plan.hpp"
+#include "mgr_timing.hpp"
+
+namespace mgr {
+
+namespace {
+
+// ------------------------------------------------------------ addressing
+
+// Offset of level node (i, j, k) in an array: per-dimension offset tables
+// (nodal positions in the finest array) or plain strides (compact grids).
+struct Map3 {
+  const int64_t *t0, *t1, *t2;
+  int64_t s0, s1;
+};
+
+__host__ Map3 compact_map(int64_t m1, int64_t m2) { return Map3{nullptr, nullptr, nullptr, m1 * m2, m2}; }
+__host__ Map3 nodal_map(const Level &L) { return Map3{L.d[0].nodal, L.d[1].nodal, L.d[2].nodal, 0, 0}; }
+
+__device__ __forceinline__ int64_t moff(const Map3 &m, int64_t i, int64_t j, int64_t k) {
+  return m.t0 ? (m.t0[i] + m.t1[j] + m.t2[k]) : (i * m.s0 + j * m.s1 + k);
+}
+
+// Linear interpolation between a (left) and b (right) with the weight r of
+// the right node, in the paper's FMA form (Sec. III-E, Table II).
+__device__ __forceinline__ double lerp(double a, double b, double r) { return fma(r, b, fma(-r, a, a)); }
+
+template <bool CO>
+__device__ __forceinline__ bool coarse_pos(int64_t g, int64_t m) {
+  return !CO || (g % 2 == 0) || (g == m - 1);
+}
+template <bool CO>
+__device__ __forceinline__ int64_t coarse_idx(int64_t g, int64_t m, int64_t c) {
+  return !CO ? g : (g == m - 1 ? c - 1 : g / 2);
+}
+
+// ------------------------------------------------------- load-vector kernel
+
+constexpr int TJ = 8;        // coarse rows (dim 1) per tile
+constexpr int TK = 32;       // coarse columns (dim 2) per tile
+constexpr int NTHR = TJ * TK;
+
+template <typename T>
+struct LoadArgs {
+  const T *src;   // level grid: field values (decompose) or stored coefficients (recompose)
+  Map3 smap;
+  T *out;         // decompose: coefficient destination (nodal positions)
+  Map3 omap;
+  T *uc;          // decompose: coarse values, compact next-level grid
+  double *F;      // load vector, compact next-level grid (FP64)
+  int64_t m0, m1, m2, c0, c1, c2;
+  const double *r0, *r1, *r2;
+  const double *W0, *W1, *W2;
+  int64_t TI;     // coarse planes per workgroup along dim 0
+};
+
+template <typename T, bool DEC, bool CO0, bool CO1, bool CO2>
+__global__ void __launch_bounds__(NTHR) k_loadvec(LoadArgs<T> a) {
+  constexpr int SI = CO0 ? 2 : 1, HI = CO0 ? 2 : 0;
+  constexpr int SJ = CO1 ? 2 : 1, HJ = CO1 ? 2 : 0;
+  constexpr int SK = CO2 ? 2 : 1, HK = CO2 ? 2 : 0;
+  constexpr int NJ = SJ * (TJ - 1) + 1 + 2 * HJ;
+  constexpr int NK = SK * (TK - 1) + 1 + 2 * HK;
+  constexpr int NPI = DEC ? (CO0 ? 2 : 1) : 0;
+  __shared__ double sC[NJ * NK];
+  __shared__ double sPi[NPI > 0 ? NPI * NJ * NK : 1];
+  __shared__ double sG[NJ * TK];
+  __shared__ double sH[5 * TJ * TK];
+
+  const int tid = threadIdx.x;
+  const int64_t J0 = (int64_t)blockIdx.y * TJ, K0 = (int64_t)blockIdx.x * TK;
+  const int64_t I0 = (int64_t)blockIdx.z * a.TI;
+  const int64_t I1 = min(I0 + a.TI, a.c0);
+  const int64_t fj0 = SJ * J0 - HJ, fk0 = SK * K0 - HK;
+  const bool lastJ = J0 + TJ >= a.c1, lastK = K0 + TK >= a.c2, lastI = I1 >= a.c0;
+  const int64_t ojb = SJ * J0, oje = lastJ ? a.m1 : SJ * (J0 + TJ);
+  const int64_t okb = SK * K0, oke = lastK ? a.m2 : SK * (K0 + TK);
+  const int64_t oib = SI * I0, oie = lastI ? a.m0 : SI * I1;
+  const int64_t pbeg = max<int64_t>(0, SI * I0 - HI);
+  const int64_t pend = min<int64_t>(a.m0 - 1, SI * (I1 - 1) + HI);
+
+  // ring / emission ownership: one (J, K) per thread
+  const int hJ = tid / TK, hK = tid % TK;
+  const int64_t gJ = J0 + hJ, gK = K0 + hK;
+  const bool hOK = gJ < a.c1 && gK < a.c2;
+
+  double *piPrev = sPi, *piNext = sPi + (NPI > 1 ? NJ * NK : 0);
+
+  auto load_plane = [&](int64_t p, bool plane_coarse) {
+    for (int e = tid; e < NJ * NK; e += NTHR) {
+      const int j = e / NK, k = e % NK;
+      const int64_t gj = fj0 + j, gk = fk0 + k;
+      double v = 0.0;
+      if (gj >= 0 && gj < a.m1 && gk >= 0 && gk < a.m2) {
+        v = (double)a.src[moff(a.smap, p, gj, gk)];
+        if (!DEC && plane_coarse && coarse_pos<CO1>(gj, a.m1) && coarse_pos<CO2>(gk, a.m2))
+          v = 0.0;  // stored coarse values are not coefficients
+      }
+      sC[e] = v;
+    }
+  };
+
+  // bilinear interpolant (dims 1, 2) of a plane held in sC, into pi
+  auto interp_plane = [&](double *pi) {
+    for (int e = tid; e < NJ * NK; e += NTHR) {
+      const int j = e / NK, k = e % NK;
+      const int64_t gj = fj0 + j, gk = fk0 + k;
+      double v = 0.0;
+      if (gj >= 0 && gj < a.m1 && gk >= 0 && gk < a.m2 && coarse_pos<CO1>(gj, a.m1)) {
+        v = coarse_pos<CO2>(gk, a.m2) ? sC[e] : lerp(sC[e - 1], sC[e + 1], a.r2[gk]);
+      }
+      pi[e] = v;
+    }
+    __syncthreads();
+    if (CO1) {
+      for (int e = tid; e < NJ * NK; e += NTHR) {
+        const int j = e / NK, k = e % NK;
+        const int64_t gj = fj0 + j, gk = fk0 + k;
+        if (gj >= 0 && gj < a.m1 && gk >= 0 && gk < a.m2 && !coarse_pos<CO1>(gj, a.m1))
+          pi[e] = lerp(pi[e - NK], pi[e + NK], a.r1[gj]);
+      }
+      __syncthreads();
+    }
+  };
+
+  // coefficients of plane p (sC holds U); writes owned outputs
+  auto coeff_plane = [&](int64_t p, bool plane_coarse, const double *pa, const double *pb,
+                         double r) {
+    const bool own_p = p >= oib && p < oie;
+    const int64_t ci0 = coarse_idx<CO0>(p, a.m0, a.c0);
+    for (int e = tid; e < NJ * NK; e += NTHR) {
+      const int j = e / NK, k = e % NK;
+      const int64_t gj = fj0 + j, gk = fk0 + k;
+      if (!(gj >= 0 && gj < a.m1 && gk >= 0 && gk < a.m2)) continue;
+      const double u = sC[e];
+      const bool c12 = coarse_pos<CO1>(gj, a.m1) && coarse_pos<CO2>(gk, a.m2);
+      double c;
+      if (plane_coarse) {
+        c = c12 ? 0.0 : u - pa[e];
+      } else {
+        c = u - lerp(pa[e], pb[e], r);
+      }
+      if (own_p && gj >= ojb && gj < oje && gk >= okb && gk < oke) {
+        if (plane_coarse && c12) {
+          const int64_t ci1 = coarse_idx<CO1>(gj, a.m1, a.c1), ci2 = coarse_idx<CO2>(gk, a.m2, a.c2);
+          a.uc[(ci0 * a.c1 + ci1) * a.c2 + ci2] = (T)u;
+        } else {
+          a.out[moff(a.omap, p, gj, gk)] = (T)c;
+        }
+      }
+      sC[e] = c;
+    }
+  };
+
+  // P^T M along dims 2 and 1 of the coefficient plane in sC -> ring slot
+  auto reduce_plane = [&](int64_t p) {
+    __syncthreads();
+    for (int e = tid; e < NJ * TK; e += NTHR) {
+      const int j = e / TK, K = e % TK;
+      const int64_t gk2 = K0 + K;
+      double g = 0.0;
+      if (gk2 < a.c2) {
+        if (CO2) {
+          const double *w = a.W2 + gk2 * 5;
+          const double *row = sC + j * NK + 2 * K;
+#pragma unroll
+          for (int o = 0; o < 5; ++o) g = fma(w[o], row[o], g);
+        } else {
+          g = sC[j * NK + K];
+        }
+      }
+      sG[e] = g;
+    }
+    __syncthreads();
+    double h = 0.0;
+    if (hOK) {
+      if (CO1) {
+        const double *w = a.W1 + gJ * 5;
+#pragma unroll
+        for (int o = 0; o < 5; ++o) h = fma(w[o], sG[(2 * hJ + o) * TK + hK], h);
+      } else {
+        h = sG[hJ * TK + hK];
+      }
+    }
+    sH[(int)(p % 5) * NTHR + tid] = h;
+  };
+
+  auto emit = [&](int64_t I) {
+    if (!hOK) return;
+    double f = 0.0;
+    if (CO0) {
+      const double *w = a.W0 + I * 5;
+#pragma unroll
+      for (int o = 0; o < 5; ++o) {
+        const int64_t q = 2 * I - 2 + o;
+        if (q >= 0 && q < a.m0) f = fma(w[o], sH[(int)(q % 5) * NTHR + tid], f);
+      }
+    } else {
+      f = sH[(int)(I % 5) * NTHR + tid];
+    }
+    a.F[(I * a.c1 + gJ) * a.c2 + gK] = f;
+  };
+
+  int64_t nextI = I0;
+  auto emit_ready = [&](int64_t done) {
+    while (nextI < I1 && min<int64_t>(SI * nextI + HI, a.m0 - 1) <= done) emit(nextI++);
+  };
+
+  int64_t p = pbeg;
+  while (p <= pend) {
+    const bool pc = coarse_pos<CO0>(p, a.m0);
+    if (pc) {
+      load_plane(p, true);
+      if (DEC) {
+        __syncthreads();
+        interp_plane(piNext);
+        coeff_plane(p, true, piNext, nullptr, 0.0);
+        double *t = piPrev; piPrev = piNext; piNext = t;
+      }
+      reduce_plane(p);
+      emit_ready(p);
+      __syncthreads();
+      p += 1;
+    } else {
+      // a fine plane needs the interpolant of the coarse plane after it
+      load_plane(p + 1, true);
+      if (DEC) {
+        __syncthreads();
+        interp_plane(piNext);
+        coeff_plane(p + 1, true, piNext, nullptr, 0.0);
+      }
+      reduce_plane(p + 1);
+      __syncthreads();
+      load_plane(p, false);
+      if (DEC) {
+        __syncthreads();
+        coeff_plane(p, false, piPrev, piNext, a.r0[p]);
+        double *t = piPrev; piPrev = piNext; piNext = t;
+      }
+      reduce_plane(p);
+      emit_ready(p + 1);
+      __syncthreads();
+      p += 2;
+    }
+  }
+}
+
+// ------------------------------------------------------------ correction solves
+
+struct SolveDev {
+  const double *sub, *sup, *w, *invb, *Ls, *Rs, *wr, *invbr, *gam;
+};
+SolveDev solve_dev(const DimTabs &d) {
+  return SolveDev{d.sub, d.sup, d.w, d.invb, d.Ls, d.Rs, d.wr, d.invbr, d.gam};
+}
+
+// What the last solve of a step does with z when it stores it.
+enum EpiMode { EPI_Z = 0, EPI_ADD_COMPACT = 1, EPI_ADD_NODAL = 2, EPI_SUB_COMPACT = 3 };
+
+template <typename T>
+struct Epi {
+  int mode;
+  T *base;       // coarse grid values (compact): coarse values (decompose) / stored grid (recompose)
+  T *dst;        // EPI_ADD_NODAL: output array
+  Map3 nmap;     // EPI_ADD_NODAL: nodal map of the coarse grid
+};
+
+template <typename T>
+__device__ __forceinline__ void epi_store(const Epi<T> &e, double *F, int64_t idx, int64_t i,
+                                          int64_t j, int64_t k, double z) {
+  switch (e.mode) {
+    case EPI_Z: F[idx] = z; break;
+    case EPI_ADD_COMPACT: e.base[idx] = (T)((double)e.base[idx] + z); break;
+    case EPI_ADD_NODAL: e.dst[moff(e.nmap, i, j, k)] = (T)((double)e.base[idx] + z); break;
+    default: e.base[idx] = (T)((double)e.base[idx] - z); break;
+  }
+}
+
+// Interior solve of one partition held in x[0..S): forward elimination and
+// back substitution with the block factors; positions f .. f+nint-1.
+template <int S>
+__device__ __forceinline__ void partition_solve(double (&x)[S], const SolveDev &tb, int64_t f, int nint) {
+#pragma unroll
+  for (int q = 1; q < S; ++q)
+    if (q < nint) x[q] = fma(-tb.w[f + q], x[q - 1], x[q]);
+#pragma unroll
+  for (int q = S - 1; q >= 0; --q) {
+    if (q == nint - 1) {
+      x[q] *= tb.invb[f + q];
+    } else if (q < nint - 1) {
+      x[q] = fma(-tb.sup[f + q], x[q + 1], x[q]) * tb.invb[f + q];
+    }
+  }
+}
+
+template <int S>
+__device__ __forceinline__ double pick(const double (&x)[S], int q) {
+  double v = 0.0;
+#pragma unroll
+  for (int i = 0; i < S; ++i)
+    if (i == q) v = x[i];
+  return v;
+}
+
+// Separator system of one line: rhs_p = Fs_p - a_s yL_p - e_s yF_{p+1};
+// Thomas with the precomputed factors.  Arrays are strided by `ld`.
+__device__ __forceinline__ void separator_solve(const SolveDev &tb, int S, int P, const double *yF,
+                                                const double *yL, const double *Fs, double *t,
+                                                int ld) {
+  double g = 0.0;
+  for (int sp = 0; sp < P - 1; ++sp) {
+    const int64_t s = (int64_t)(sp + 1) * S - 1;
+    double rhs = Fs[sp * ld] - tb.sub[s] * yL[sp * ld] - tb.sup[s] * yF[(sp + 1) * ld];
+    g = fma(-tb.wr[sp], g, rhs);
+    t[sp * ld] = g;
+  }
+  double nxt = 0.0;
+  for (int sp = P - 2; sp >= 0; --sp) {
+    nxt = fma(-tb.gam[sp], nxt, t[sp * ld]) * tb.invbr[sp];
+    t[sp * ld] = nxt;
+  }
+}
+
+// Lines along dim 0 or 1: lane = position along the contiguous dim 2,
+// wave = partition.  Element q of partition p of line (outer, k) sits at
+// F[outer * so + k + (p*S + q) * sp].
+template <typename T, int S>
+__global__ void __launch_bounds__(1024) k_solve_strided(double *F, int64_t c, int P, int64_t nk,
+                                                        int64_t sp_, int64_t so, int axis,
+                                                        int64_t c1, int64_t c2, SolveDev tb,
+                                                        Epi<T> ep) {
+  extern __shared__ double xs[];
+  const int lane = threadIdx.x & 63;
+  const int p = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t k = (int64_t)blockIdx.x * 64 + lane;
+  const int64_t outer = blockIdx.y;
+  const bool active = k < nk;
+  const int64_t base = outer * so + k;
+  const int64_t f = (int64_t)p * S;
+  const int nload = p < P - 1 ? S : (int)(c - f);
+  const int nint = p < P - 1 ? S - 1 : nload;
+
+  double x[S];
+#pragma unroll
+  for (int q = 0; q < S; ++q) x[q] = (active && q < nload) ? F[base + (f + q) * sp_] : 0.0;
+  partition_solve<S>(x, tb, f, nint);
+
+  double *yF = xs, *yL = xs + P * 64, *Fs = xs + 2 * P * 64, *tt = xs + 3 * P * 64;
+  if (P > 1) {
+    yF[p * 64 + lane] = x[0];
+    yL[p * 64 + lane] = pick<S>(x, nint - 1);
+    Fs[p * 64 + lane] = x[S - 1];
+    __syncthreads();
+    if (p == 0) separator_solve(tb, S, P, yF + lane, yL + lane, Fs + lane, tt + lane, 64);
+    __syncthreads();
+    const double tl = p > 0 ? tt[(p - 1) * 64 + lane] : 0.0;
+    const double tr = p < P - 1 ? tt[p * 64 + lane] : 0.0;
+#pragma unroll
+    for (int q = 0; q < S; ++q)
+      if (q < nint) x[q] = fma(-tl, tb.Ls[f + q], fma(-tr, tb.Rs[f + q], x[q]));
+    if (p < P - 1) x[S - 1] = tr;
+  }
+  if (!active) return;
+#pragma unroll
+  for (int q = 0; q < S; ++q) {
+    if (q < nload) {
+      const int64_t pos = f + q;
+      const int64_t idx = base + pos * sp_;
+      const int64_t i = axis == 0 ? pos : outer;
+      const int64_t j = axis == 0 ? outer : pos;
+      epi_store(ep, F, idx, i, j, k, x[q]);
+    }
+  }
+}
+
+// Lines along the contiguous dim 2: a workgroup stages R consecutive rows in
+// LDS (coalesced), thread (r, p) solves partition p of row r in registers.
+template <typename T, int S>
+__global__ void __launch_bounds__(1024) k_solve_rows(double *F, int64_t nrows, int c, int P, int R,
+                                                     int pitch, int64_t c1, SolveDev tb, Epi<T> ep) {
+  extern __shared__ double sm[];
+  const int t = threadIdx.x, nt = blockDim.x;
+  const int r = t % R, p = t / R;
+  const int64_t row0 = (int64_t)blockIdx.x * R;
+  const int nr = (int)min<int64_t>(R, nrows - row0);
+  const int64_t gbase = row0 * c;
+  for (int e = t; e < nr * c; e += nt) sm[(e / c) * pitch + e % c] = F[gbase + e];
+  __syncthreads();
+  const bool active = r < nr;
+  const int64_t f = (int64_t)p * S;
+  const int nload = p < P - 1 ? S : (int)(c - f);
+  const int nint = p < P - 1 ? S - 1 : nload;
+  double x[S];
+  const double *rowp = sm + r * pitch + f;
+#pragma unroll
+  for (int q = 0; q < S; ++q) x[q] = (active && q < nload) ? rowp[q] : 0.0;
+  partition_solve<S>(x, tb, f, nint);
+  if (P > 1) {
+    double *ex = sm + R * pitch;
+    double *yF = ex, *yL = ex + P * R, *Fs = ex + 2 * P * R, *tt = ex + 3 * P * R;
+    yF[p * R + r] = x[0];
+    yL[p * R + r] = pick<S>(x, nint - 1);
+    Fs[p * R + r] = x[S - 1];
+    __syncthreads();
+    if (p == 0) separator_solve(tb, S, P, yF + r, yL + r, Fs + r, tt + r, R);
+    __syncthreads();
+    const double tl = p > 0 ? tt[(p - 1) * R + r] : 0.0;
+    const double tr = p < P - 1 ? tt[p * R + r] : 0.0;
+#pragma unroll
+    for (int q = 0; q < S; ++q)
+      if (q < nint) x[q] = fma(-tl, tb.Ls[f + q], fma(-tr, tb.Rs[f + q], x[q]));
+    if (p < P - 1) x[S - 1] = tr;
+  }
+  __syncthreads();
+  if (active) {
+    double *roww = sm + r * pitch + f;
+#pragma unroll
+    for (int q = 0; q < S; ++q)
+      if (q < nload) roww[q] = x[q];
+  }
+  __syncthreads();
+  for (int e = t; e < nr * c; e += nt) {
+    const int rr = e / c, cc = e % c;
+    const int64_t row = row0 + rr;
+    epi_store(ep, F, gbase + e, row / c1, row % c1, cc, sm[rr * pitch + cc]);
+  }
+}
+
+// Sequential Thomas per line (lines longer than 16 partitions of 64): one
+// thread per line, elimination in place in F.
+template <typename T>
+__global__ void k_solve_seq(double *F, int64_t nlines, int64_t c, int axis, int64_t c1, int64_t c2,
+                            SolveDev tb, Epi<T> ep) {
+  const int64_t L = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (L >= nlines) return;
+  int64_t base, step, o1, o2;  // o1, o2: the two fixed coordinates
+  if (axis == 2) { base = L * c; step = 1; o1 = L / c1; o2 = L % c1; }
+  else if (axis == 1) { o1 = L / c2; o2 = L % c2; base = o1 * c1 * c2 + o2; step = c2; }
+  else { o1 = L / c2; o2 = L % c2; base = o1 * c2 + o2; step = c1 * c2; }
+  double prev = F[base];
+  for (int64_t q = 1; q < c; ++q) {
+    double v = fma(-tb.w[q], prev, F[base + q * step]);
+    F[base + q * step] = v;
+    prev = v;
+  }
+  double nxt = 0.0;
+  for (int64_t q = c - 1; q >= 0; --q) {
+    double v = (q == c - 1) ? F[base + q * step] * tb.invb[q]
+                            : fma(-tb.sup[q], nxt, F[base + q * step]) * tb.invb[q];
+    nxt = v;
+    int64_t i, j, k;
+    if (axis == 2) { i = o1; j = o2; k = q; }
+    else if (axis == 1) { i = o1; j = q; k = o2; }
+    else { i = q; j = o1; k = o2; }
+    epi_store(ep, F, base + q * step, i, j, k, v);
+  }
+}
+
+// --------------------------------------------------- recomposition kernels
+
+template <typename T, bool CO0, bool CO1, bool CO2>
+__global__ void __launch_bounds__(256) k_reconstruct(const T *coef, Map3 cmap, const T *uc, T *dst,
+                                                     Map3 dmap, int64_t m0, int64_t m1, int64_t m2,
+                                                     int64_t c0, int64_t c1, int64_t c2,
+                                                     const double *r0, const double *r1,
+                                                     const double *r2) {
+  const int64_t n = m0 * m1 * m2;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t k = e % m2, row = e / m2, j = row % m1, i = row / m1;
+    const bool f0 = !coarse_pos<CO0>(i, m0), f1 = !coarse_pos<CO1>(j, m1), f2 = !coarse_pos<CO2>(k, m2);
+    const int64_t a0 = f0 ? (i - 1) / 2 : coarse_idx<CO0>(i, m0, c0), b0 = f0 ? a0 + 1 : a0;
+    const int64_t a1 = f1 ? (j - 1) / 2 : coarse_idx<CO1>(j, m1, c1), b1 = f1 ? a1 + 1 : a1;
+    const int64_t a2 = f2 ? (k - 1) / 2 : coarse_idx<CO2>(k, m2, c2), b2 = f2 ? a2 + 1 : a2;
+    const double w2 = f2 ? r2[k] : 0.0, w1 = f1 ? r1[j] : 0.0, w0 = f0 ? r0[i] : 0.0;
+    auto V = [&](int64_t x, int64_t y, int64_t z) { return (double)uc[(x * c1 + y) * c2 + z]; };
+    auto along2 = [&](int64_t x, int64_t y) { return f2 ? lerp(V(x, y, a2), V(x, y, b2), w2) : V(x, y, a2); };
+    auto along1 = [&](int64_t x) { return f1 ? lerp(along2(x, a1), along2(x, b1), w1) : along2(x, a1); };
+    const double pi = f0 ? lerp(along1(a0), along1(b0), w0) : along1(a0);
+    double v = pi;
+    if (f0 || f1 || f2) v += (double)coef[moff(cmap, i, j, k)];
+    dst[moff(dmap, i, j, k)] = (T)v;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_gather(const T *src, Map3 smap, T *dst, int64_t m0, int64_t m1,
+                                                int64_t m2) {
+  const int64_t n = m0 * m1 * m2;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t k = e % m2, row = e / m2, j = row % m1, i = row / m1;
+    dst[e] = src[moff(smap, i, j, k)];
+  }
+}
+
+// ------------------------------------------------------------ host launch
+
+struct Ctx {
+  hipStream_t stream;
+  std::string *err;
+  bool ok = true;
+  void check(const char *what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess && ok) {
+      ok = false;
+      *err = std::string(what) + ": " + hipGetErrorString(e);
+    }
+  }
+};
+
+template <typename T>
+const char *tname() { return sizeof(T) == 8 ? "double" : "float"; }
+inline const char *bname(bool b) { return b ? "true" : "false"; }
+
+int64_t grid_1d(int64_t n, int64_t per) {
+  int64_t g = (n + per - 1) / per;
+  return std::min<int64_t>(std::max<int64_t>(g, 1), 1 << 20);
+}
+
+template <typename T, bool DEC, bool C0, bool C1, bool C2>
+void launch_loadvec_t(const LoadArgs<T> &a, dim3 grid, Ctx &cx) {
+  double bytes = 0.0;
+  if (timing_enabled()) {
+    const double nl = (double)a.m0 * a.m1 * a.m2, nc = (double)a.c0 * a.c1 * a.c2;
+    // decompose: read the level grid, write coefficients + coarse values, write f
+    // recompose: read the coefficients, write f
+    bytes = DEC ? 2.0 * nl * sizeof(T) + 8.0 * nc : (nl - nc) * sizeof(T) + 8.0 * nc;
+  }
+  TimedLaunch tl(cx.stream,
+                 std::string("k_loadvec<") + tname<T>() + ", " + bname(DEC) + ", " + bname(C0) + ", " +
+                     bname(C1) + ", " + bname(C2) + ">",
+                 bytes);
+  hipLaunchKernelGGL((k_loadvec<T, DEC, C0, C1, C2>), grid, dim3(NTHR), 0, cx.stream, a);
+}
+
+// Algorithmic bytes of one correction solve over nc unknowns.
+template <typename T>
+double solve_bytes(double nc, int mode) {
+  return mode == EPI_Z ? 16.0 * nc : 8.0 * nc + 2.0 * sizeof(T) * nc;
+}
+
+template <typename T, bool DEC>
+void launch_loadvec(const Level &L, LoadArgs<T> a, Ctx &cx) {
+  a.m0 = L.m[0]; a.m1 = L.m[1]; a.m2 = L.m[2];
+  a.c0 = L.c[0]; a.c1 = L.c[1]; a.c2 = L.c[2];
+  a.r0 = L.d[0].r; a.r1 = L.d[1].r; a.r2 = L.d[2].r;
+  a.W0 = L.d[0].W; a.W1 = L.d[1].W; a.W2 = L.d[2].W;
+  const int64_t gx = (a.c2 + TK - 1) / TK, gy = (a.c1 + TJ - 1) / TJ;
+  // enough workgroups to fill 256 CUs several times over; chunks of dim 0
+  const int64_t want = std::max<int64_t>(1, (2048 + gx * gy - 1) / (gx * gy));
+  int64_t TI = std::max<int64_t>(1, (a.c0 + want - 1) / want);
+  a.TI = TI;
+  const int64_t gz = (a.c0 + TI - 1) / TI;
+  dim3 grid((unsigned)gx, (unsigned)gy, (unsigned)gz);
+  const int key = (L.co[0] ? 4 : 0) | (L.co[1] ? 2 : 0) | (L.co[2] ? 1 : 0);
+  switch (key) {
+    case 0: launch_loadvec_t<T, DEC, false, false, false>(a, grid, cx); break;
+    case 1: launch_loadvec_t<T, DEC, false, false, true>(a, grid, cx); break;
+    case 2: launch_loadvec_t<T, DEC, false, true, false>(a, grid, cx); break;
+    case 3: launch_loadvec_t<T, DEC, false, true, true>(a, grid, cx); break;
+    case 4: launch_loadvec_t<T, DEC, true, false, false>(a, grid, cx); break;
+    case 5: launch_loadvec_t<T, DEC, true, false, true>(a, grid, cx); break;
+    case 6: launch_loadvec_t<T, DEC, true, true, false>(a, grid, cx); break;
+    default: launch_loadvec_t<T, DEC, true, true, true>(a, grid, cx); break;
+  }
+  cx.check("k_loadvec launch");
+}
+
+template <typename T, int S>
+void launch_strided_s(double *F, const Level &L, int axis, const Epi<T> &ep, Ctx &cx) {
+  const DimTabs &d = L.d[axis];
+  const int64_t c0 = L.c[0], c1 = L.c[1], c2 = L.c[2];
+  const int64_t c = L.c[axis];
+  int64_t sp_, so, nouter;
+  if (axis == 0) { sp_ = c1 * c2; so = c2; nouter = c1; }
+  else { sp_ = c2; so = c1 * c2; nouter = c0; }
+  dim3 grid((unsigned)((c2 + 63) / 64), (unsigned)nouter);
+  const size_t lds = (size_t)4 * d.P * 64 * sizeof(double);
+  TimedLaunch tl(cx.stream, std::string("k_solve_strided<") + tname<T>() + ", " + std::to_string(S) + ">",
+                 timing_enabled() ? solve_bytes<T>((double)c0 * c1 * c2, ep.mode) : 0.0);
+  hipLaunchKernelGGL((k_solve_strided<T, S>), grid, dim3(64 * d.P), lds, cx.stream, F, c, d.P, c2, sp_,
+                     so, axis, c1, c2, solve_dev(d), ep);
+}
+
+template <typename T, int S>
+void launch_rows_s(double *F, const Level &L, const Epi<T> &ep, Ctx &cx) {
+  const DimTabs &d = L.d[2];
+  const int64_t c = L.c[2], nrows = L.c[0] * L.c[1];
+  const int pitch = (int)(c | 1);
+  const int budget = 64 * 1024 / (int)sizeof(double);
+  int R = std::min(64, 1024 / d.P);
+  R = std::min<int64_t>(R, budget / (pitch + 4 * d.P));
+  R = std::max(R, 1);
+  const size_t lds = (size_t)(R * pitch + 4 * d.P * R) * sizeof(double);
+  dim3 grid((unsigned)((nrows + R - 1) / R));
+  TimedLaunch tl(cx.stream, std::string("k_solve_rows<") + tname<T>() + ", " + std::to_string(S) + ">",
+                 timing_enabled() ? solve_bytes<T>((double)nrows * c, ep.mode) : 0.0);
+  hipLaunchKernelGGL((k_solve_rows<T, S>), grid, dim3(R * d.P), lds, cx.stream, F, nrows, (int)c, d.P,
+                     R, pitch, L.c[1], solve_dev(d), ep);
+}
+
+template <typename T>
+void launch_solve(double *F, const Level &L, int axis, const Epi<T> &ep, Ctx &cx) {
+  const DimTabs &d = L.d[axis];
+  if (d.S == 0) {
+    const int64_t nlines = L.c[0] * L.c[1] * L.c[2] / L.c[axis];
+    TimedLaunch tl(cx.stream, std::string("k_solve_seq<") + tname<T>() + ">",
+                   timing_enabled() ? solve_bytes<T>((double)L.c[0] * L.c[1] * L.c[2], ep.mode) : 0.0);
+    hipLaunchKernelGGL((k_solve_seq<T>), dim3((unsigned)grid_1d(nlines, 64)), dim3(64), 0, cx.stream, F,
+                       nlines, L.c[axis], axis, L.c[1], L.c[2], solve_dev(d), ep);
+  } else if (axis == 2) {
+    switch (d.S) {
+      case 8: launch_rows_s<T, 8>(F, L, ep, cx); break;
+      case 16: launch_rows_s<T, 16>(F, L, ep, cx); break;
+      case 32: launch_rows_s<T, 32>(F, L, ep, cx); break;
+      default: launch_rows_s<T, 64>(F, L, ep, cx); break;
+    }
+  } else {
+    switch (d.S) {
+      case 8: launch_strided_s<T, 8>(F, L, axis, ep, cx); break;
+      case 16: launch_strided_s<T, 16>(F, L, axis, ep, cx); break;
+      case 32: launch_strided_s<T, 32>(F, L, axis, ep, cx); break;
+      default: launch_strided_s<T, 64>(F, L, axis, ep, cx); break;
+    }
+  }
+  cx.check("correction solve launch");
+}
+
+// Solves along every coarsened dim in order 0, 1, 2; the last one applies `last`.
+template <typename T>
+void solve_all(double *F, const Level &L, const Epi<T> &last, Ctx &cx) {
+  int lastk = -1;
+  for (int k = 0; k < kDims; ++k)
+    if (L.co[k]) lastk = k;
+  for (int k = 0; k < kDims; ++k) {
+    if (!L.co[k]) continue;
+    Epi<T> ep = (k == lastk) ? last : Epi<T>{EPI_Z, nullptr, nullptr, Map3{}};
+    launch_solve<T>(F, L, k, ep, cx);
+  }
+}
+
+template <typename T>
+void launch_reconstruct(const Level &L, const T *coef, Map3 cmap, const T *uc, T *dst, Map3 dmap,
+                        Ctx &cx) {
+  const int64_t n = L.m[0] * L.m[1] * L.m[2];
+  dim3 grid((unsigned)grid_1d(n, 256 * 4));
+  const int key = (L.co[0] ? 4 : 0) | (L.co[1] ? 2 : 0) | (L.co[2] ? 1 : 0);
+  const double nl = (double)n, nc = (double)L.c[0] * L.c[1] * L.c[2];
+  // read coefficients and the coarse grid, write the level grid
+  TimedLaunch tl(cx.stream,
+                 std::string("k_reconstruct<") + tname<T>() + ", " + bname(L.co[0]) + ", " + bname(L.co[1]) +
+                     ", " + bname(L.co[2]) + ">",
+                 timing_enabled() ? ((nl - nc) + nc + nl) * sizeof(T) : 0.0);
+#define MGR_RECON(C0, C1, C2)                                                                       \
+  hipLaunchKernelGGL((k_reconstruct<T, C0, C1, C2>), grid, dim3(256), 0, cx.stream, coef, cmap, uc, \
+                     dst, dmap, L.m[0], L.m[1], L.m[2], L.c[0], L.c[1], L.c[2], L.d[0].r, L.d[1].r,  \
+                     L.d[2].r)
+  switch (key) {
+    case 0: MGR_RECON(false, false, false); break;
+    case 1: MGR_RECON(false, false, true); break;
+    case 2: MGR_RECON(false, true, false); break;
+    case 3: MGR_RECON(false, true, true); break;
+    case 4: MGR_RECON(true, false, false); break;
+    case 5: MGR_RECON(true, false, true); break;
+    case 6: MGR_RECON(true, true, false); break;
+    default: MGR_RECON(true, true, true); break;
+  }
+#undef MGR_RECON
+  cx.check("k_reconstruct launch");
+}
+
+struct Workspace {
+  void *buf[2];
+  double *F;
+};
+
+Workspace carve(const Plan &pl, void *ws, size_t elem) {
+  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t nb = al((size_t)pl.max_coarse * elem);
+  char *p = (char *)ws;
+  return Workspace{{p, p + nb}, (double *)(p + 2 * nb)};
+}
+
+template <typename T>
+bool decompose_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t stream, std::string &err) {
+  Ctx cx{stream, &err};
+  const int64_t total = pl.n[0] * pl.n[1] * pl.n[2];
+  if (pl.nlev == 0) {
+    if (hipMemcpyAsync(out, in, total * sizeof(T), hipMemcpyDeviceToDevice, stream) != hipSuccess) {
+      err = "hipMemcpyAsync failed";
+      return false;
+    }
+    return true;
+  }
+  Workspace w = carve(pl, ws, sizeof(T));
+  const T *src = in;
+  Map3 smap = compact_map(pl.n[1], pl.n[2]);
+  for (int s = 0; s < pl.nlev && cx.ok; ++s) {
+    const Level &L = pl.lev[s];
+    T *uc = (T *)w.buf[s % 2];
+    LoadArgs<T> a{};
+    a.src = src;
+    a.smap = smap;
+    a.out = out;
+    a.omap = (s == 0) ? compact_map(pl.n[1], pl.n[2]) : nodal_map(L);
+    a.uc = uc;
+    a.F = w.F;
+    launch_loadvec<T, true>(L, a, cx);
+    Epi<T> ep{};
+    if (s + 1 < pl.nlev) {
+      ep.mode = EPI_ADD_COMPACT;
+      ep.base = uc;
+    } else {
+      ep.mode = EPI_ADD_NODAL;
+      ep.base = uc;
+      ep.dst = out;
+      ep.nmap = nodal_map(pl.lev[s + 1]);
+    }
+    solve_all<T>(w.F, L, ep, cx);
+    src = uc;
+    smap = compact_map(L.c[1], L.c[2]);
+  }
+  return cx.ok;
+}
+
+template <typename T>
+bool recompose_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t stream, std::string &err) {
+  Ctx cx{stream, &err};
+  const int64_t total = pl.n[0] * pl.n[1] * pl.n[2];
+  if (pl.nlev == 0) {
+    if (hipMemcpyAsync(out, in, total * sizeof(T), hipMemcpyDeviceToDevice, stream) != hipSuccess) {
+      err = "hipMemcpyAsync failed";
+      return false;
+    }
+    return true;
+  }
+  Workspace w = carve(pl, ws, sizeof(T));
+  // coarsest grid values, gathered compactly
+  const Level &Lc = pl.lev[pl.nlev];
+  T *V = (T *)w.buf[pl.nlev % 2];
+  {
+    const int64_t n = Lc.m[0] * Lc.m[1] * Lc.m[2];
+    TimedLaunch tl(stream, std::string("k_gather<") + tname<T>() + ">", 2.0 * n * sizeof(T));
+    hipLaunchKernelGGL((k_gather<T>), dim3((unsigned)grid_1d(n, 256)), dim3(256), 0, stream, in,
+                       nodal_map(Lc), V, Lc.m[0], Lc.m[1], Lc.m[2]);
+    cx.check("k_gather launch");
+  }
+  for (int s = pl.nlev - 1; s >= 0 && cx.ok; --s) {
+    const Level &L = pl.lev[s];
+    const Map3 cmap = (s == 0) ? compact_map(pl.n[1], pl.n[2]) : nodal_map(L);
+    LoadArgs<T> a{};
+    a.src = in;
+    a.smap = cmap;
+    a.F = w.F;
+    launch_loadvec<T, false>(L, a, cx);
+    Epi<T> ep{};
+    ep.mode = EPI_SUB_COMPACT;
+    ep.base = V;
+    solve_all<T>(w.F, L, ep, cx);
+    T *dst = (s == 0) ? out : (T *)w.buf[s % 2];
+    launch_reconstruct<T>(L, in, cmap, V, dst, compact_map(L.m[1], L.m[2]), cx);
+    V = dst;
+  }
+  return cx.ok;
+}
+
+}  // namespace
+
+bool enqueue_decompose(const Plan &pl, bool f64, const void *in, void *out, void *ws, void *stream,
+                       std::string &err) {
+  hipStream_t st = (hipStream_t)stream;
+  return f64 ? decompose_t<double>(pl, (const double *)in, (double *)out, ws, st, err)
+             : decompose_t<float>(pl, (const float *)in, (float *)out, ws, st, err);
+}
+
+bool enqueue_recompose(const Plan &pl, bool f64, const void *in, void *out, void *ws, void *stream,
+                       std::string &err) {
+  hipStream_t st = (hipStream_t)stream;
+  return f64 ? recompose_t<double>(pl, (const double *)in, (double *)out, ws, st, err)
+             : recompose_t<float>(pl, (const float *)in, (float *)out, ws, st, err);
+}
+
+}  // namespace mgr

@@ -1,0 +1,18 @@
+// mgr_kernels.hpp -- enqueue entry points of the HIP kernels (host side).
+#pragma once
+
+#include <string>
+
+#include "mgr_plan.hpp"
+
+namespace mgr {
+
+// Enqueue one full decomposition / recomposition of `pl` on `stream`.
+// Arguments are assumed validated.  Returns false with `err` set when a
+// launch fails.
+bool enqueue_decompose(const Plan &pl, bool f64, const void *in, void *out, void *ws, void *stream,
+                       std::string &err);
+bool enqueue_recompose(const Plan &pl, bool f64, const void *in, void *out, void *ws, void *stream,
+                       std::string &err);
+
+}  // namespace mgr

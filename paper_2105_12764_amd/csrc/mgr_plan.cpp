@@ -1,0 +1,347 @@
+// mgr_plan.cpp -- FP64 host tables for one refactoring request.
+//
+// Everything here is plain FP64 arithmetic on the coordinates, done once per
+// (shape, coords, nlevels) and uploaded; the kernels never divide.
+//
+// Operators of one step along one dimension (arXiv 2105.12764, Sec. II-A.2
+// and the matrices of Sec. III-A.2), on level nodes x_0 < ... < x_{m-1} with
+// spacings h_i = x_{i+1} - x_i and coarse positions 0, 2, 4, ... and m-1:
+//   P (prolongation): a coarse position copies its coarse value; a fine
+//     position i takes (1 - r_i) v_left + r_i v_right with
+//     r_i = h_{i-1} / (h_{i-1} + h_i)  (the paper's r, Sec. III-A.2);
+//   M (mass matrix, scaled by 6): diagonal 2(h_{i-1} + h_i), off-diagonals
+//     h_{i-1} and h_i -- the paper's printed matrix with its spacing index
+//     read as the interval to the left / right of node i;
+//   R = P^T, and the load vector row J is (P^T M) restricted to the fine
+//     positions 2J-2 .. 2J+2 (the paper's merged "mass-trans" operator,
+//     computed here as the product instead of transcribing its garbled
+//     closed form);
+//   the correction solve uses M (scaled by 6) on the coarse coordinates; the
+//     common factor 6 cancels against the load vector.
+//
+// Solve factorisation (exact, not approximate): a line of c unknowns is cut
+// into P partitions of S positions; the last position of each partition but
+// the last is a separator.  Each partition's interior is eliminated on its
+// own (block Thomas factors w, 1/b'), which expresses it as
+//   x = y - t_left * Ls - t_right * Rs
+// with y the interior solve of the right-hand side and Ls, Rs the interior
+// responses to unit separator values.  Substituting into the separator rows
+// leaves a tridiagonal system in the P-1 separators, factorised here as well.
+#include "mgr_plan.hpp"
+
+#include <hip/hip_runtime_api.h>
+
+#include <array>
+#include <cmath>
+#include <cstring>
+
+namespace mgr {
+
+Plan::~Plan() {
+  if (dev_tables) {
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    if (cur != device) (void)hipSetDevice(device);
+    (void)hipFree(dev_tables);
+    if (cur != device && cur >= 0) (void)hipSetDevice(cur);
+  }
+}
+
+int max_levels3(const int64_t n[kDims]) {
+  int best = 0;
+  for (int k = 0; k < kDims; ++k) {
+    int steps = 0;
+    for (int64_t m = n[k]; m > 2; m = coarse_count(m)) ++steps;
+    if (steps > best) best = steps;
+  }
+  return best;
+}
+
+size_t workspace_bytes(const int64_t n[kDims], int nlev, size_t elem_size) {
+  if (nlev <= 0) return 0;
+  int64_t c1 = 1;
+  for (int k = 0; k < kDims; ++k) c1 *= coarse_count(n[k]);
+  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+  // two coarse grids in the field's type (ping-pong) + one FP64 load/correction grid
+  return 2 * al((size_t)c1 * elem_size) + al((size_t)c1 * sizeof(double));
+}
+
+namespace {
+
+// Accumulates host tables into one byte image with 16-byte aligned entries.
+struct Image {
+  std::vector<char> bytes;
+  template <typename T>
+  size_t put(const std::vector<T> &v) {
+    size_t off = (bytes.size() + 15) / 16 * 16;
+    bytes.resize(off + v.size() * sizeof(T) + 16);
+    if (!v.empty()) std::memcpy(bytes.data() + off, v.data(), v.size() * sizeof(T));
+    return off;
+  }
+};
+
+struct HostDim {
+  size_t nodal = 0, r = 0, W = 0, sub = 0, sup = 0, w = 0, invb = 0, Ls = 0, Rs = 0,
+         wr = 0, invbr = 0, gam = 0;
+  bool has_solve = false;
+};
+
+int64_t coarse_index(int64_t m, int64_t i) {
+  if (m < 3) return i;
+  return (i == m - 1) ? coarse_count(m) - 1 : i / 2;
+}
+bool is_coarse(int64_t m, int64_t i) { return m < 3 || i % 2 == 0 || i == m - 1; }
+
+// Partition length for a line of c unknowns: the smallest of 8/16/32/64 that
+// needs at most kMaxBlocks partitions; 0 selects the sequential fallback.
+int pick_partition(int64_t c) {
+  for (int S : {8, 16, 32, 64})
+    if ((c + S - 1) / S <= kMaxBlocks) return S;
+  return 0;
+}
+
+struct SolveTabs {
+  std::vector<double> sub, sup, w, invb, Ls, Rs, wr, invbr, gam;
+  int S = 0, P = 1;
+};
+
+SolveTabs solve_tables(const std::vector<double> &X) {
+  const int64_t c = (int64_t)X.size();
+  SolveTabs t;
+  t.S = pick_partition(c);
+  const int64_t S = t.S ? t.S : c;   // fallback: one partition = whole line
+  t.P = (int)((c + S - 1) / S);
+  const int P = t.P;
+  std::vector<double> a(c), b(c), e(c);
+  for (int64_t i = 0; i < c; ++i) {
+    double hl = i > 0 ? X[i] - X[i - 1] : 0.0;
+    double hr = i < c - 1 ? X[i + 1] - X[i] : 0.0;
+    a[i] = hl;
+    e[i] = hr;
+    b[i] = 2.0 * (hl + hr);
+  }
+  t.sub = a;
+  t.sup = e;
+  t.w.assign(c, 0.0);
+  t.invb.assign(c, 0.0);
+  t.Ls.assign(c, 0.0);
+  t.Rs.assign(c, 0.0);
+  // interior [f, l] of partition p
+  auto first = [&](int p) { return (int64_t)p * S; };
+  auto last = [&](int p) { return p < P - 1 ? (int64_t)(p + 1) * S - 2 : c - 1; };
+  for (int p = 0; p < P; ++p) {
+    int64_t f = first(p), l = last(p);
+    double piv = b[f];
+    t.w[f] = 0.0;
+    t.invb[f] = 1.0 / piv;
+    for (int64_t i = f + 1; i <= l; ++i) {
+      t.w[i] = a[i] / piv;
+      piv = b[i] - t.w[i] * e[i - 1];
+      t.invb[i] = 1.0 / piv;
+    }
+    // interior solve with the tables, as the kernels do it
+    auto interior_solve = [&](std::vector<double> &d) {
+      for (int64_t i = f + 1; i <= l; ++i) d[i] -= t.w[i] * d[i - 1];
+      d[l] *= t.invb[l];
+      for (int64_t i = l - 1; i >= f; --i) d[i] = (d[i] - e[i] * d[i + 1]) * t.invb[i];
+    };
+    if (p > 0) {  // left separator at f-1 couples through a_f
+      std::vector<double> d(c, 0.0);
+      d[f] = a[f];
+      interior_solve(d);
+      for (int64_t i = f; i <= l; ++i) t.Ls[i] = d[i];
+    }
+    if (p < P - 1) {  // right separator at l+1 couples through e_l
+      std::vector<double> d(c, 0.0);
+      d[l] = e[l];
+      interior_solve(d);
+      for (int64_t i = f; i <= l; ++i) t.Rs[i] = d[i];
+    }
+  }
+  // separator system
+  if (P > 1) {
+    std::vector<double> al(P - 1), be(P - 1), ga(P - 1);
+    for (int p = 0; p < P - 1; ++p) {
+      int64_t s = last(p) + 1;
+      al[p] = -a[s] * t.Ls[s - 1];
+      be[p] = b[s] - a[s] * t.Rs[s - 1] - e[s] * t.Ls[s + 1];
+      ga[p] = -e[s] * t.Rs[s + 1];
+    }
+    t.wr.assign(P - 1, 0.0);
+    t.invbr.assign(P - 1, 0.0);
+    t.gam = ga;
+    double piv = be[0];
+    t.invbr[0] = 1.0 / piv;
+    for (int p = 1; p < P - 1; ++p) {
+      t.wr[p] = al[p] / piv;
+      piv = be[p] - t.wr[p] * ga[p - 1];
+      t.invbr[p] = 1.0 / piv;
+    }
+  } else {
+    t.wr.assign(1, 0.0);
+    t.invbr.assign(1, 0.0);
+    t.gam.assign(1, 0.0);
+  }
+  return t;
+}
+
+}  // namespace
+
+std::unique_ptr<Plan> build_plan(int ndim, const int64_t n[kDims],
+                                 const std::vector<std::vector<double>> &coords,
+                                 int nlev, std::string &err, int &status) {
+  auto plan = std::make_unique<Plan>();
+  plan->ndim = ndim;
+  for (int k = 0; k < kDims; ++k) plan->n[k] = n[k];
+  plan->nlev = nlev;
+  plan->lev.resize(nlev + 1);
+
+  // level coordinates and finest indices per dim
+  std::vector<std::vector<double>> x(kDims);
+  std::vector<std::vector<int64_t>> idx(kDims);
+  for (int k = 0; k < kDims; ++k) {
+    x[k] = coords[k];
+    idx[k].resize(n[k]);
+    for (int64_t i = 0; i < n[k]; ++i) idx[k][i] = i;
+  }
+  const int64_t fstride[kDims] = {n[1] * n[2], n[2], 1};
+
+  Image img;
+  std::vector<std::array<HostDim, kDims>> hd(nlev + 1);
+  for (int s = 0; s <= nlev; ++s) {
+    Level &L = plan->lev[s];
+    for (int k = 0; k < kDims; ++k) {
+      const int64_t m = (int64_t)x[k].size();
+      const bool co = (s < nlev) && m >= 3;
+      const int64_t c = co ? coarse_count(m) : m;
+      L.m[k] = m;
+      L.c[k] = c;
+      L.co[k] = co;
+      std::vector<int64_t> nodal(m);
+      for (int64_t i = 0; i < m; ++i) nodal[i] = idx[k][i] * fstride[k];
+      hd[s][k].nodal = img.put(nodal);
+      std::vector<double> r(m, 0.0);
+      if (co)
+        for (int64_t i = 0; i < m; ++i)
+          if (!is_coarse(m, i))
+            r[i] = (x[k][i] - x[k][i - 1]) / (x[k][i + 1] - x[k][i - 1]);
+      hd[s][k].r = img.put(r);
+      if (!co) continue;
+      // load-vector taps: row J of P^T M on the fine positions 2J-2 .. 2J+2
+      std::vector<double> W((size_t)c * kTaps, 0.0);
+      auto M6 = [&](int64_t q, int64_t i) -> double {
+        double hl = q > 0 ? x[k][q] - x[k][q - 1] : 0.0;
+        double hr = q < m - 1 ? x[k][q + 1] - x[k][q] : 0.0;
+        if (i == q) return 2.0 * (hl + hr);
+        if (i == q - 1) return hl;
+        if (i == q + 1) return hr;
+        return 0.0;
+      };
+      for (int64_t q = 0; q < m; ++q) {
+        // column entries P[q][J] of fine position q
+        int64_t Js[2];
+        double ws[2];
+        int cnt = 0;
+        if (is_coarse(m, q)) {
+          Js[0] = coarse_index(m, q);
+          ws[0] = 1.0;
+          cnt = 1;
+        } else {
+          Js[0] = (q - 1) / 2;
+          ws[0] = 1.0 - r[q];
+          Js[1] = (q + 1) / 2;
+          ws[1] = r[q];
+          cnt = 2;
+        }
+        for (int a = 0; a < cnt; ++a)
+          for (int64_t i = q - 1; i <= q + 1; ++i) {
+            if (i < 0 || i >= m) continue;
+            int64_t o = i - 2 * Js[a] + 2;
+            if (o < 0 || o >= kTaps) {
+              err = "internal: load-vector tap out of range";
+              status = 2;
+              return nullptr;
+            }
+            W[(size_t)Js[a] * kTaps + o] += ws[a] * M6(q, i);
+          }
+      }
+      hd[s][k].W = img.put(W);
+      // coarse coordinates and the correction solve
+      std::vector<double> X;
+      for (int64_t i = 0; i < m; ++i)
+        if (is_coarse(m, i)) X.push_back(x[k][i]);
+      SolveTabs st = solve_tables(X);
+      HostDim &h = hd[s][k];
+      h.has_solve = true;
+      h.sub = img.put(st.sub);
+      h.sup = img.put(st.sup);
+      h.w = img.put(st.w);
+      h.invb = img.put(st.invb);
+      h.Ls = img.put(st.Ls);
+      h.Rs = img.put(st.Rs);
+      h.wr = img.put(st.wr);
+      h.invbr = img.put(st.invbr);
+      h.gam = img.put(st.gam);
+      L.d[k].S = st.S;
+      L.d[k].P = st.P;
+    }
+    // next level's coordinates and indices
+    if (s < nlev)
+      for (int k = 0; k < kDims; ++k) {
+        const int64_t m = (int64_t)x[k].size();
+        if (m < 3) continue;
+        std::vector<double> nx;
+        std::vector<int64_t> ni;
+        for (int64_t i = 0; i < m; ++i)
+          if (is_coarse(m, i)) {
+            nx.push_back(x[k][i]);
+            ni.push_back(idx[k][i]);
+          }
+        x[k] = nx;
+        idx[k] = ni;
+      }
+  }
+  plan->max_coarse = 0;
+  if (nlev > 0) plan->max_coarse = plan->lev[0].c[0] * plan->lev[0].c[1] * plan->lev[0].c[2];
+
+  // upload
+  (void)hipGetDevice(&plan->device);
+  plan->table_bytes = img.bytes.size();
+  if (hipMalloc(&plan->dev_tables, plan->table_bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    plan->dev_tables = nullptr;
+    err = "hipMalloc of plan tables failed";
+    status = 4;
+    return nullptr;
+  }
+  if (hipMemcpy(plan->dev_tables, img.bytes.data(), plan->table_bytes,
+                hipMemcpyHostToDevice) != hipSuccess) {
+    err = "upload of plan tables failed";
+    status = 5;
+    return nullptr;
+  }
+  char *base = (char *)plan->dev_tables;
+  for (int s = 0; s <= nlev; ++s)
+    for (int k = 0; k < kDims; ++k) {
+      DimTabs &d = plan->lev[s].d[k];
+      const HostDim &h = hd[s][k];
+      d.nodal = (const int64_t *)(base + h.nodal);
+      d.r = (const double *)(base + h.r);
+      if (plan->lev[s].co[k]) {
+        d.W = (const double *)(base + h.W);
+        d.sub = (const double *)(base + h.sub);
+        d.sup = (const double *)(base + h.sup);
+        d.w = (const double *)(base + h.w);
+        d.invb = (const double *)(base + h.invb);
+        d.Ls = (const double *)(base + h.Ls);
+        d.Rs = (const double *)(base + h.Rs);
+        d.wr = (const double *)(base + h.wr);
+        d.invbr = (const double *)(base + h.invbr);
+        d.gam = (const double *)(base + h.gam);
+      }
+    }
+  status = 0;
+  return plan;
+}
+
+}  // namespace mgr

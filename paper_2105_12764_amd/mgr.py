@@ -1,0 +1,204 @@
+"""Python binding of libmgr (include/mgr.h): argument marshalling only.
+
+Every step of the refactoring runs in the HIP library; this module turns
+PyTorch tensors into device pointers, passes the current HIP stream and maps
+status codes to exceptions.  PyTorch provides device memory and streams only.
+The library must be built (``paper_2105_12764_amd.build``); there is no CPU
+fallback and a missing library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libmgr.so")
+
+MGR_OK = 0
+MGR_ERR_INVALID_ARG = 1
+MGR_ERR_UNSUPPORTED = 2
+MGR_ERR_WORKSPACE = 3
+MGR_ERR_OUT_OF_MEMORY = 4
+MGR_ERR_DEVICE = 5
+
+MGR_FLOAT32 = 0
+MGR_FLOAT64 = 1
+
+_lib = None
+
+
+class MgrError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        self.status = status
+        super().__init__(f"{status_string(status)} ({status}): {detail}")
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libmgr.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with paper_2105_12764_amd.build.build() "
+                "(there is no CPU fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        dpp = ctypes.POINTER(ctypes.POINTER(ctypes.c_double))
+        L.mgr_max_levels.argtypes = [ctypes.c_int, i64p]
+        L.mgr_max_levels.restype = ctypes.c_int
+        L.mgr_workspace_size.argtypes = [ctypes.c_int, i64p, ctypes.c_int, ctypes.c_int,
+                                         ctypes.POINTER(ctypes.c_size_t)]
+        L.mgr_workspace_size.restype = ctypes.c_int
+        for fn in (L.mgr_decompose, L.mgr_recompose):
+            fn.argtypes = [ctypes.c_int, i64p, dpp, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+            fn.restype = ctypes.c_int
+        L.mgr_status_string.argtypes = [ctypes.c_int]
+        L.mgr_status_string.restype = ctypes.c_char_p
+        L.mgr_last_error.argtypes = []
+        L.mgr_last_error.restype = ctypes.c_char_p
+        L.mgr_release_caches.argtypes = []
+        L.mgr_release_caches.restype = None
+        L.mgr_timing_enable.argtypes = [ctypes.c_int]
+        L.mgr_timing_enable.restype = ctypes.c_int
+        L.mgr_timing_reset.argtypes = []
+        L.mgr_timing_reset.restype = None
+        L.mgr_timing_count.argtypes = []
+        L.mgr_timing_count.restype = ctypes.c_int
+        L.mgr_timing_get.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_char_p),
+                                     ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double)]
+        L.mgr_timing_get.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def status_string(s: int) -> str:
+    return lib().mgr_status_string(int(s)).decode()
+
+
+def last_error() -> str:
+    return lib().mgr_last_error().decode()
+
+
+def _shape(shape: Sequence[int]):
+    return (ctypes.c_int64 * len(shape))(*[int(s) for s in shape])
+
+
+def max_levels(shape: Sequence[int]) -> int:
+    r = lib().mgr_max_levels(len(shape), _shape(shape))
+    if r < 0:
+        raise MgrError(-r, last_error())
+    return r
+
+
+def _dtype_code(dtype) -> int:
+    import torch
+    if dtype in (torch.float64, np.float64):
+        return MGR_FLOAT64
+    if dtype in (torch.float32, np.float32):
+        return MGR_FLOAT32
+    raise ValueError(f"unsupported dtype {dtype}")
+
+
+def workspace_size(shape: Sequence[int], dtype, nlevels: int) -> int:
+    out = ctypes.c_size_t(0)
+    s = lib().mgr_workspace_size(len(shape), _shape(shape), _dtype_code(dtype), int(nlevels),
+                                 ctypes.byref(out))
+    if s != MGR_OK:
+        raise MgrError(s, last_error())
+    return int(out.value)
+
+
+def _coords_arg(shape, coords):
+    if coords is None:
+        return None, []
+    if len(coords) != len(shape):
+        raise ValueError("coords needs one entry per dimension")
+    dp = ctypes.POINTER(ctypes.c_double)
+    arr = (dp * len(shape))()
+    keep = []
+    for k, c in enumerate(coords):
+        if c is None:
+            arr[k] = dp()
+            continue
+        c = np.ascontiguousarray(np.asarray(c, dtype=np.float64))
+        if c.shape != (shape[k],):
+            raise ValueError(f"coords[{k}] must have shape ({shape[k]},)")
+        keep.append(c)
+        arr[k] = c.ctypes.data_as(dp)
+    return arr, keep
+
+
+def alloc_workspace(shape, dtype, nlevels, device=None):
+    import torch
+    nb = workspace_size(shape, dtype, nlevels)
+    return torch.empty(max(nb, 1), dtype=torch.uint8, device=device or "cuda")
+
+
+def _call(fn, x, coords, nlevels, out, workspace, stream):
+    import torch
+    if not x.is_cuda:
+        raise ValueError("input must be a HIP device tensor")
+    if not x.is_contiguous():
+        raise ValueError("input must be contiguous (C order)")
+    shape = tuple(x.shape)
+    if nlevels is None:
+        nlevels = max_levels(shape)
+    if out is None:
+        out = torch.empty_like(x)
+    if workspace is None:
+        workspace = alloc_workspace(shape, x.dtype, nlevels, device=x.device)
+    if stream is None:
+        stream = torch.cuda.current_stream(x.device)
+    carr, keep = _coords_arg(shape, coords)
+    with torch.cuda.device(x.device):
+        s = fn(len(shape), _shape(shape), carr, _dtype_code(x.dtype), int(nlevels),
+               ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+               ctypes.c_void_p(workspace.data_ptr()), ctypes.c_size_t(workspace.numel()),
+               ctypes.c_void_p(stream.cuda_stream))
+    del keep
+    if s != MGR_OK:
+        raise MgrError(s, last_error())
+    return out
+
+
+def decompose(x, coords=None, nlevels: Optional[int] = None, out=None, workspace=None, stream=None):
+    """mgr_decompose on a contiguous float32/float64 HIP tensor; returns ``out``."""
+    return _call(lib().mgr_decompose, x, coords, nlevels, out, workspace, stream)
+
+
+def recompose(x, coords=None, nlevels: Optional[int] = None, out=None, workspace=None, stream=None):
+    """mgr_recompose (inverse of :func:`decompose`); returns ``out``."""
+    return _call(lib().mgr_recompose, x, coords, nlevels, out, workspace, stream)
+
+
+def release_caches() -> None:
+    lib().mgr_release_caches()
+
+
+def timing_enable(on: bool = True) -> None:
+    """Bracket every later kernel launch with HIP events on its stream."""
+    lib().mgr_timing_enable(1 if on else 0)
+
+
+def timing_reset() -> None:
+    lib().mgr_timing_reset()
+
+
+def timing_totals():
+    """{kernel name: (launches, total ms, algorithmic bytes)} of the recorded launches."""
+    L = lib()
+    out = {}
+    for i in range(L.mgr_timing_count()):
+        name = ctypes.c_char_p()
+        n = ctypes.c_int64()
+        ms = ctypes.c_double()
+        b = ctypes.c_double()
+        if L.mgr_timing_get(i, ctypes.byref(name), ctypes.byref(n), ctypes.byref(ms),
+                            ctypes.byref(b)) == MGR_OK:
+            out[name.value.decode()] = (int(n.value), float(ms.value), float(b.value))
+    return out

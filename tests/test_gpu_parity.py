@@ -1,0 +1,157 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 CPU oracle.
+
+Tolerances (stated per result, the bar of the target):
+  FP64:  max|gpu - oracle| / max|oracle| <= 1e-12 over the whole nodal array
+  FP32:  ||gpu - oracle||_2 / ||oracle||_2 <= 1e-5, oracle run in FP64 on the
+         FP32 input (so only the FP32 storage rounding is measured)
+Both directions are checked: decompose against the oracle's decomposition,
+recompose against the oracle's recomposition of the same representation, and
+the round trip.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2105_12764_amd import mgr
+from paper_2105_12764_amd.synth import WORKLOADS, make_input
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    mgr.lib()
+
+
+def _err(got, ref, dtype):
+    got = got.astype(np.float64)
+    if dtype == np.float64:
+        return float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+    return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+
+
+def _tol(dtype):
+    return TOL64 if dtype == np.float64 else TOL32
+
+
+def _case(shape, nlev, nonuni, dtype, seed=7):
+    print(f"\n[case] shape={shape} nlev={nlev} nonuniform={nonuni} dtype={np.dtype(dtype).name}",
+          flush=True)
+    u, coords = make_input(shape, seed, nonuniform=nonuni, dtype=dtype)
+    if nlev is None:
+        nlev = oracle.max_levels(shape)
+    x = torch.from_numpy(u).cuda()
+    d = mgr.decompose(x, coords, nlev)
+    torch.cuda.synchronize()
+    got = d.cpu().numpy()
+    ref = oracle.decompose(u.astype(np.float64), coords, nlev)
+    e_dec = _err(got, ref, dtype)
+    # recompose: GPU recomposition of the oracle's representation (rounded to dtype)
+    rep = torch.from_numpy(ref.astype(dtype)).cuda()
+    r = mgr.recompose(rep, coords, nlev)
+    torch.cuda.synchronize()
+    ref_r = oracle.recompose(ref.astype(dtype).astype(np.float64), coords, nlev)
+    e_rec = _err(r.cpu().numpy(), ref_r, dtype)
+    # round trip of the GPU's own output
+    rt = mgr.recompose(d, coords, nlev)
+    torch.cuda.synchronize()
+    e_rt = _err(rt.cpu().numpy(), u.astype(np.float64), dtype)
+    print(f"[case] dec {e_dec:.2e} rec {e_rec:.2e} roundtrip {e_rt:.2e}", flush=True)
+    tol = _tol(dtype)
+    assert e_dec <= tol, ("decompose", e_dec)
+    assert e_rec <= tol, ("recompose", e_rec)
+    assert e_rt <= tol, ("round trip", e_rt)
+
+
+SMALL = [
+    ((65, 65, 65), 5, False, np.float64),       # 65^3, 5 levels (to 3^3)
+    ((65, 65, 65), 6, False, np.float64),       # full depth to 2^3
+    ((33, 33, 33), 5, True, np.float64),
+    ((17, 40, 23), None, True, np.float64),     # ragged, even sizes
+    ((66, 70, 130), 4, True, np.float64),       # several tiles, ragged tails
+    ((9, 130, 70), 3, False, np.float64),
+    ((200, 3, 2), None, True, np.float64),      # tiny and never-coarsened dims
+    ((3, 3, 3), 1, False, np.float64),
+    ((2, 2, 2), 0, False, np.float64),          # nlevels = 0: copy
+    ((129, 257), None, False, np.float64),      # 2-D
+    ((300, 41), None, True, np.float64),
+    ((1000,), None, True, np.float64),          # 1-D
+    ((65,), 3, False, np.float64),
+    ((5000,), 4, True, np.float64),             # line > 1024: sequential solver
+    ((3000, 40), 2, True, np.float64),          # strided line > 1024
+    ((1500, 30), 2, True, np.float64),          # 64-partition strided solve
+    ((30, 1500), 2, True, np.float64),          # 64-partition row solve
+    ((129, 129, 129), None, True, np.float64),
+    ((65, 65, 65), 5, False, np.float32),
+    ((20, 17, 26), 3, True, np.float32),
+    ((129, 100, 77), None, True, np.float32),
+]
+
+
+@pytest.mark.parametrize("shape,nlev,nonuni,dtype", SMALL)
+def test_parity_small(shape, nlev, nonuni, dtype):
+    _case(shape, nlev, nonuni, dtype)
+
+
+def test_deterministic_and_stream_ordered():
+    u, coords = make_input((70, 66, 90), 3, nonuniform=True)
+    x = torch.from_numpy(u).cuda()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        a = mgr.decompose(x, coords, 4)
+        b = mgr.decompose(x, coords, 4)
+    s.synchronize()
+    assert torch.equal(a, b)
+    c = mgr.decompose(x, coords, 4)
+    torch.cuda.synchronize()
+    assert torch.equal(a, c)
+
+
+def test_workspace_reuse_between_shapes():
+    """A workspace sized for a big request serves a smaller one; contents on entry are ignored."""
+    ws = mgr.alloc_workspace((129, 129, 129), torch.float64, 7)
+    ws.fill_(255)  # NaN bit patterns in the scratch must not leak into results
+    for shape, nlev in (((129, 129, 129), 7), ((40, 33, 65), 4)):
+        u, coords = make_input(shape, 9, nonuniform=True)
+        d = mgr.decompose(torch.from_numpy(u).cuda(), coords, nlev, workspace=ws)
+        torch.cuda.synchronize()
+        ref = oracle.decompose(u, coords, nlev)
+        assert _err(d.cpu().numpy(), ref, np.float64) <= TOL64
+
+
+def test_multilinear_field_gives_zero_coefficients_on_gpu():
+    """Property that holds at any size: a field multilinear on the final coarse
+    grid has zero coefficients and keeps its coarse values."""
+    shape, nlev = (97, 65, 80), 5
+    _, coords = make_input(shape, 4, nonuniform=True)
+    from dense_l2 import coarse_positions, level_coords
+    xs = [level_coords(coords[k], nlev) for k in range(3)]
+    q = np.random.default_rng(5).standard_normal([len(xs[k][nlev]) for k in range(3)])
+    f = q
+    for k in range(3):
+        f = np.apply_along_axis(lambda v: np.interp(xs[k][0], xs[k][nlev], v), k, f)
+    d = mgr.decompose(torch.from_numpy(np.ascontiguousarray(f)).cuda(), coords, nlev)
+    got = d.cpu().numpy()
+    idx = []
+    for n in shape:
+        lev = np.arange(n)
+        for _ in range(nlev):
+            lev = lev[coarse_positions(len(lev))]
+        idx.append(lev)
+    mask = np.ones(shape, bool)
+    mask[np.ix_(*idx)] = False
+    assert np.max(np.abs(got[mask])) < 1e-12 * np.max(np.abs(q))
+    assert np.max(np.abs(got[np.ix_(*idx)] - q)) < 1e-12 * np.max(np.abs(q))
+
+
+@pytest.mark.parametrize("name", ["cube65_f64", "box400x300x250_f32", "cube513_f64", "cube513_f32"])
+def test_parity_benchmark_workloads(name):
+    """The benchmark's workloads at full size, in the launch configuration it times."""
+    shape, seed, nonuni, dtype, nlev = WORKLOADS[name]
+    _case(shape, nlev, nonuni, dtype, seed=seed)
