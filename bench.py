@@ -109,6 +109,32 @@ def run_gpu(name: str, steps: int, warmup: int):
     return res, u, coords, nlev
 
 
+def probe_bandwidth(nbytes: int = 1 << 30, reps: int = 10):
+    """Achievable single-pass bandwidth: the library's streaming copy probe
+    (one read + one write of every byte), 2 * bytes / time."""
+    import torch
+
+    from paper_2105_12764_amd import mgr
+
+    dev = torch.device("cuda:0")
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    stream = torch.cuda.current_stream(dev)
+    for _ in range(3):
+        mgr.probe_copy(a, b, stream=stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        mgr.probe_copy(a, b, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    ok = bool(torch.equal(a, b))
+    del a, b
+    torch.cuda.empty_cache()
+    return {"bytes": nbytes, "ms": ms, "GBps": 2.0 * nbytes / (ms * 1e-3) / 1e9, "verified": ok}
+
+
 def cpu_baseline(u, coords, nlev):
     import oracle
 
@@ -143,6 +169,8 @@ def main():
               "(this refactoring path runs on a single MI355X)", file=sys.stderr)
         sys.exit(2)
 
+    probe = probe_bandwidth()
+    _log(f"[bench] copy probe: {probe['GBps']:.0f} GB/s")
     res, u, coords, nlev = run_gpu(args.workload, args.steps, args.warmup)
     fp32 = None
     if not args.no_fp32 and args.fp32_workload:
@@ -172,6 +200,8 @@ def main():
         "t_rec_ms": round(res["t_rec_ms"], 4),
         "alg_GBps": round(res["alg_GBps"], 1),
         "pct_hbm_peak": round(100.0 * res["alg_GBps"] / HBM_PEAK_GBS, 2),
+        "copy_probe_GBps": round(probe["GBps"], 1),
+        "pct_of_copy_probe": round(100.0 * res["alg_GBps"] / probe["GBps"], 2),
         "roundtrip_max_rel_err": res["roundtrip_max_rel_err"],
         "roofline": res["roofline"],
         "cpu_baseline": cpu,

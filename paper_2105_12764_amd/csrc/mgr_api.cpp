@@ -59,6 +59,10 @@ bool pad_shape(int ndim, const int64_t *shape, int64_t n[mgr::kDims], std::strin
     }
     n[mgr::kDims - ndim + k] = shape[k];
   }
+  if (n[1] * n[2] >= ((int64_t)1 << 31)) {
+    why = "a plane (product of the last two dimensions) must hold fewer than 2^31 nodes";
+    return false;
+  }
   const int64_t total = n[0] * n[1] * n[2];
   if (total <= 0 || total > ((int64_t)1 << 40)) {
     why = "total element count out of range";
@@ -218,6 +222,19 @@ mgr_status mgr_recompose(int ndim, const int64_t *shape, const double *const *co
                          size_t workspace_bytes, void *stream) {
   return run(false, ndim, shape, coords, (int)dtype, nlevels, in, out, workspace, workspace_bytes,
              stream);
+}
+
+mgr_status mgr_probe_copy(const void *src, void *dst, size_t bytes, void *stream) {
+  g_last_error.clear();
+  if (!src || !dst) return fail(MGR_ERR_INVALID_ARG, "src and dst must be non-NULL");
+  if (bytes % 16 != 0) return fail(MGR_ERR_INVALID_ARG, "bytes must be a multiple of 16");
+  if ((uintptr_t)src % 16 != 0 || (uintptr_t)dst % 16 != 0)
+    return fail(MGR_ERR_INVALID_ARG, "src and dst must be 16-byte aligned");
+  const char *a = (const char *)src, *b = (const char *)dst;
+  if (a < b + bytes && b < a + bytes) return fail(MGR_ERR_INVALID_ARG, "src and dst overlap");
+  std::string err;
+  if (!mgr::enqueue_copy_probe(src, dst, bytes, stream, err)) return fail(MGR_ERR_DEVICE, err);
+  return MGR_OK;
 }
 
 const char *mgr_status_string(mgr_status s) {

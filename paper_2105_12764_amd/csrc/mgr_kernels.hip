@@ -86,109 +86,142 @@ struct LoadArgs {
   const double *r0, *r1, *r2;
   const double *W0, *W1, *W2;
   int64_t TI;     // coarse planes per workgroup along dim 0
+  int gx, gy, gz; // tile grid (dims 2, 1, 0)
 };
 
+// Tile id of this workgroup.  Hardware hands consecutive workgroup ids to
+// the 8 XCDs in turn; this mapping gives each XCD one contiguous run of
+// tiles so that neighbouring tiles, which share halo rows, share an L2.
+__device__ __forceinline__ int xcd_tile(int bid, int nb) {
+  const int q = nb / 8, r = nb % 8;
+  const int xcd = bid % 8, local = bid / 8;
+  return (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + local;
+}
+
+// One workgroup owns a (TJ x TK) tile of the coarse grid in dims (1, 2) and
+// a chunk of TI coarse planes along dim 0.  It walks the fine planes in
+// steps of two -- fine plane a = 2I+1 and coarse plane b = 2I+2 -- with the
+// next step's values prefetched into registers while the current step
+// computes.  Per step: the bilinear interpolant of plane b (dims 1, 2), the
+// coefficients of b and of a (whose interpolant is the dim-0 lerp of the
+// interpolants of the coarse planes around it), P^T M along dims 2 and 1 of
+// both planes, and the dim-0 taps from a five-plane register window.
 template <typename T, bool DEC, bool CO0, bool CO1, bool CO2>
 __global__ void __launch_bounds__(NTHR) k_loadvec(LoadArgs<T> a) {
-  constexpr int SI = CO0 ? 2 : 1, HI = CO0 ? 2 : 0;
   constexpr int SJ = CO1 ? 2 : 1, HJ = CO1 ? 2 : 0;
   constexpr int SK = CO2 ? 2 : 1, HK = CO2 ? 2 : 0;
   constexpr int NJ = SJ * (TJ - 1) + 1 + 2 * HJ;
   constexpr int NK = SK * (TK - 1) + 1 + 2 * HK;
-  constexpr int NPI = DEC ? (CO0 ? 2 : 1) : 0;
-  __shared__ double sC[NJ * NK];
-  __shared__ double sPi[NPI > 0 ? NPI * NJ * NK : 1];
-  __shared__ double sG[NJ * TK];
-  __shared__ double sH[5 * TJ * TK];
+  constexpr int NE = NJ * NK;
+  constexpr int EPT = (NE + NTHR - 1) / NTHR;  // tile elements per thread
+  constexpr int NT = 2 * NJ * TK > NE ? 2 * NJ * TK : NE;
+  __shared__ double sA[NE];  // coarse plane b: values, then coefficients
+  __shared__ double sB[NE];  // fine plane a: values, then coefficients
+  __shared__ double sT[NT];  // interpolation scratch, then dim-2 reduced rows of a and b
 
   const int tid = threadIdx.x;
-  const int64_t J0 = (int64_t)blockIdx.y * TJ, K0 = (int64_t)blockIdx.x * TK;
-  const int64_t I0 = (int64_t)blockIdx.z * a.TI;
+  const int tile = xcd_tile(blockIdx.x, a.gx * a.gy * a.gz);
+  const int tx = tile % a.gx, ty = (tile / a.gx) % a.gy, tz = tile / (a.gx * a.gy);
+  const int64_t J0 = (int64_t)ty * TJ, K0 = (int64_t)tx * TK;
+  const int64_t I0 = (int64_t)tz * a.TI;
   const int64_t I1 = min(I0 + a.TI, a.c0);
   const int64_t fj0 = SJ * J0 - HJ, fk0 = SK * K0 - HK;
   const bool lastJ = J0 + TJ >= a.c1, lastK = K0 + TK >= a.c2, lastI = I1 >= a.c0;
   const int64_t ojb = SJ * J0, oje = lastJ ? a.m1 : SJ * (J0 + TJ);
   const int64_t okb = SK * K0, oke = lastK ? a.m2 : SK * (K0 + TK);
-  const int64_t oib = SI * I0, oie = lastI ? a.m0 : SI * I1;
-  const int64_t pbeg = max<int64_t>(0, SI * I0 - HI);
-  const int64_t pend = min<int64_t>(a.m0 - 1, SI * (I1 - 1) + HI);
+  const int64_t oib = (CO0 ? 2 : 1) * I0, oie = lastI ? a.m0 : (CO0 ? 2 : 1) * I1;
 
-  // ring / emission ownership: one (J, K) per thread
+  // per-element constants of this thread's tile elements (same for every plane)
+  enum : unsigned { F_IN = 1, F_OWN = 2, F_C1 = 4, F_C2 = 8 };
+  unsigned flag[EPT];
+  int colS[EPT], colO[EPT], ucol[EPT];  // in-plane offsets (planes hold < 2^31 nodes)
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = tid + i * NTHR;
+    const int j = e / NK, k = e % NK;
+    const int64_t gj = fj0 + j, gk = fk0 + k;
+    unsigned f = 0;
+    colS[i] = colO[i] = ucol[i] = 0;
+    if (e < NE && gj >= 0 && gj < a.m1 && gk >= 0 && gk < a.m2) {
+      f |= F_IN;
+      if (gj >= ojb && gj < oje && gk >= okb && gk < oke) f |= F_OWN;
+      if (coarse_pos<CO1>(gj, a.m1)) f |= F_C1;
+      if (coarse_pos<CO2>(gk, a.m2)) f |= F_C2;
+      colS[i] = (int)(a.smap.t1 ? a.smap.t1[gj] + a.smap.t2[gk] : gj * a.smap.s1 + gk);
+      if (DEC) {
+        colO[i] = (int)(a.omap.t1 ? a.omap.t1[gj] + a.omap.t2[gk] : gj * a.omap.s1 + gk);
+        ucol[i] = (int)(coarse_idx<CO1>(gj, a.m1, a.c1) * a.c2 + coarse_idx<CO2>(gk, a.m2, a.c2));
+      }
+    }
+    flag[i] = f;
+  }
+
+  // the (J, K) load-vector entry this thread reduces and emits
   const int hJ = tid / TK, hK = tid % TK;
   const int64_t gJ = J0 + hJ, gK = K0 + hK;
   const bool hOK = gJ < a.c1 && gK < a.c2;
+  double w1[5];
+#pragma unroll
+  for (int o = 0; o < 5; ++o) w1[o] = (CO1 && gJ < a.c1) ? a.W1[gJ * 5 + o] : 0.0;
 
-  double *piPrev = sPi, *piNext = sPi + (NPI > 1 ? NJ * NK : 0);
+  auto plane_off = [&](const Map3 &m, int64_t p) -> int64_t { return m.t0 ? m.t0[p] : p * m.s0; };
 
-  auto load_plane = [&](int64_t p, bool plane_coarse) {
-    for (int e = tid; e < NJ * NK; e += NTHR) {
-      const int j = e / NK, k = e % NK;
-      const int64_t gj = fj0 + j, gk = fk0 + k;
-      double v = 0.0;
-      if (gj >= 0 && gj < a.m1 && gk >= 0 && gk < a.m2) {
-        v = (double)a.src[moff(a.smap, p, gj, gk)];
-        if (!DEC && plane_coarse && coarse_pos<CO1>(gj, a.m1) && coarse_pos<CO2>(gk, a.m2))
-          v = 0.0;  // stored coarse values are not coefficients
+  // loads of one plane into registers (zero outside the grid / at stored coarse values)
+  auto fetch = [&](double (&v)[EPT], int64_t p) {
+    const int64_t po = plane_off(a.smap, p);
+    const bool pc = coarse_pos<CO0>(p, a.m0);
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      double x = 0.0;
+      if (flag[i] & F_IN) {
+        x = (double)a.src[po + colS[i]];
+        if (!DEC && pc && (flag[i] & F_C1) && (flag[i] & F_C2)) x = 0.0;
       }
-      sC[e] = v;
+      v[i] = x;
+    }
+  };
+  auto stage = [&](double *s, const double (&v)[EPT]) {
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int e = tid + i * NTHR;
+      if (e < NE) s[e] = v[i];
     }
   };
 
-  // bilinear interpolant (dims 1, 2) of a plane held in sC, into pi
-  auto interp_plane = [&](double *pi) {
-    for (int e = tid; e < NJ * NK; e += NTHR) {
-      const int j = e / NK, k = e % NK;
-      const int64_t gj = fj0 + j, gk = fk0 + k;
+  // bilinear interpolant (dims 1, 2) of the plane in s, for this thread's elements
+  auto interp2 = [&](const double *s, double (&pi)[EPT]) {
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int e = tid + i * NTHR;
+      if (e >= NE) continue;
       double v = 0.0;
-      if (gj >= 0 && gj < a.m1 && gk >= 0 && gk < a.m2 && coarse_pos<CO1>(gj, a.m1)) {
-        v = coarse_pos<CO2>(gk, a.m2) ? sC[e] : lerp(sC[e - 1], sC[e + 1], a.r2[gk]);
+      if ((flag[i] & F_IN) && (flag[i] & F_C1)) {
+        const int64_t gk = fk0 + e % NK;
+        v = (flag[i] & F_C2) ? s[e] : lerp(s[e - 1], s[e + 1], a.r2[gk]);
       }
-      pi[e] = v;
+      sT[e] = v;
     }
     __syncthreads();
-    if (CO1) {
-      for (int e = tid; e < NJ * NK; e += NTHR) {
-        const int j = e / NK, k = e % NK;
-        const int64_t gj = fj0 + j, gk = fk0 + k;
-        if (gj >= 0 && gj < a.m1 && gk >= 0 && gk < a.m2 && !coarse_pos<CO1>(gj, a.m1))
-          pi[e] = lerp(pi[e - NK], pi[e + NK], a.r1[gj]);
-      }
-      __syncthreads();
-    }
-  };
-
-  // coefficients of plane p (sC holds U); writes owned outputs
-  auto coeff_plane = [&](int64_t p, bool plane_coarse, const double *pa, const double *pb,
-                         double r) {
-    const bool own_p = p >= oib && p < oie;
-    const int64_t ci0 = coarse_idx<CO0>(p, a.m0, a.c0);
-    for (int e = tid; e < NJ * NK; e += NTHR) {
-      const int j = e / NK, k = e % NK;
-      const int64_t gj = fj0 + j, gk = fk0 + k;
-      if (!(gj >= 0 && gj < a.m1 && gk >= 0 && gk < a.m2)) continue;
-      const double u = sC[e];
-      const bool c12 = coarse_pos<CO1>(gj, a.m1) && coarse_pos<CO2>(gk, a.m2);
-      double c;
-      if (plane_coarse) {
-        c = c12 ? 0.0 : u - pa[e];
-      } else {
-        c = u - lerp(pa[e], pb[e], r);
-      }
-      if (own_p && gj >= ojb && gj < oje && gk >= okb && gk < oke) {
-        if (plane_coarse && c12) {
-          const int64_t ci1 = coarse_idx<CO1>(gj, a.m1, a.c1), ci2 = coarse_idx<CO2>(gk, a.m2, a.c2);
-          a.uc[(ci0 * a.c1 + ci1) * a.c2 + ci2] = (T)u;
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int e = tid + i * NTHR;
+      double v = 0.0;
+      if (e < NE && (flag[i] & F_IN)) {
+        if (flag[i] & F_C1) {
+          v = sT[e];
         } else {
-          a.out[moff(a.omap, p, gj, gk)] = (T)c;
+          const int64_t gj = fj0 + e / NK;
+          v = lerp(sT[e - NK], sT[e + NK], a.r1[gj]);
         }
       }
-      sC[e] = c;
+      pi[i] = v;
     }
   };
 
-  // P^T M along dims 2 and 1 of the coefficient plane in sC -> ring slot
-  auto reduce_plane = [&](int64_t p) {
-    __syncthreads();
+  // P^T M along dims 2 and 1 of the coefficient plane in s; the dim-2 rows
+  // go to sT + off.  Returns this thread's (J, K) value after the barrier
+  // the caller places between the two halves.
+  auto reduce2 = [&](const double *s, int off) {
     for (int e = tid; e < NJ * TK; e += NTHR) {
       const int j = e / TK, K = e % TK;
       const int64_t gk2 = K0 + K;
@@ -196,86 +229,126 @@ __global__ void __launch_bounds__(NTHR) k_loadvec(LoadArgs<T> a) {
       if (gk2 < a.c2) {
         if (CO2) {
           const double *w = a.W2 + gk2 * 5;
-          const double *row = sC + j * NK + 2 * K;
+          const double *row = s + j * NK + 2 * K;
 #pragma unroll
           for (int o = 0; o < 5; ++o) g = fma(w[o], row[o], g);
         } else {
-          g = sC[j * NK + K];
+          g = s[j * NK + K];
         }
       }
-      sG[e] = g;
+      sT[off + e] = g;
     }
-    __syncthreads();
+  };
+  auto reduce1 = [&](int off) -> double {
     double h = 0.0;
     if (hOK) {
       if (CO1) {
-        const double *w = a.W1 + gJ * 5;
 #pragma unroll
-        for (int o = 0; o < 5; ++o) h = fma(w[o], sG[(2 * hJ + o) * TK + hK], h);
+        for (int o = 0; o < 5; ++o) h = fma(w1[o], sT[off + (2 * hJ + o) * TK + hK], h);
       } else {
-        h = sG[hJ * TK + hK];
+        h = sT[off + hJ * TK + hK];
       }
     }
-    sH[(int)(p % 5) * NTHR + tid] = h;
+    return h;
   };
 
-  auto emit = [&](int64_t I) {
-    if (!hOK) return;
-    double f = 0.0;
-    if (CO0) {
-      const double *w = a.W0 + I * 5;
+  double piPrev[EPT], piNext[EPT];
 #pragma unroll
-      for (int o = 0; o < 5; ++o) {
-        const int64_t q = 2 * I - 2 + o;
-        if (q >= 0 && q < a.m0) f = fma(w[o], sH[(int)(q % 5) * NTHR + tid], f);
-      }
-    } else {
-      f = sH[(int)(I % 5) * NTHR + tid];
-    }
-    a.F[(I * a.c1 + gJ) * a.c2 + gK] = f;
+  for (int i = 0; i < EPT; ++i) piPrev[i] = piNext[i] = 0.0;
+  double h0 = 0.0, h1 = 0.0, h2 = 0.0, h3 = 0.0, h4 = 0.0;
+
+  // step schedule: with dim 0 coarsened, step I covers fine planes
+  // (2I+1, 2I+2) for I in [I0-2, I1-1] and emits F[I] for I >= I0; without,
+  // step I is plane I and emits F[I].
+  const int64_t sbeg = CO0 ? I0 - 2 : I0, send = I1;  // [sbeg, send)
+  auto planes = [&](int64_t I, int64_t &pa, int64_t &pb) {
+    if (!CO0) { pa = -1; pb = I; return; }
+    pa = 2 * I + 1;
+    pb = 2 * I + 2;
+    if (!(pa >= 0 && pa < a.m0) || I < I0 - 1) pa = -1;
+    if (!(pb >= 0 && pb < a.m0)) pb = -1;
+    if (pa >= 0 && pb < 0) { pb = pa; pa = -1; }  // last plane of an even extent is coarse
   };
 
-  int64_t nextI = I0;
-  auto emit_ready = [&](int64_t done) {
-    while (nextI < I1 && min<int64_t>(SI * nextI + HI, a.m0 - 1) <= done) emit(nextI++);
-  };
-
-  int64_t p = pbeg;
-  while (p <= pend) {
-    const bool pc = coarse_pos<CO0>(p, a.m0);
-    if (pc) {
-      load_plane(p, true);
-      if (DEC) {
-        __syncthreads();
-        interp_plane(piNext);
-        coeff_plane(p, true, piNext, nullptr, 0.0);
-        double *t = piPrev; piPrev = piNext; piNext = t;
-      }
-      reduce_plane(p);
-      emit_ready(p);
-      __syncthreads();
-      p += 1;
-    } else {
-      // a fine plane needs the interpolant of the coarse plane after it
-      load_plane(p + 1, true);
-      if (DEC) {
-        __syncthreads();
-        interp_plane(piNext);
-        coeff_plane(p + 1, true, piNext, nullptr, 0.0);
-      }
-      reduce_plane(p + 1);
-      __syncthreads();
-      load_plane(p, false);
-      if (DEC) {
-        __syncthreads();
-        coeff_plane(p, false, piPrev, piNext, a.r0[p]);
-        double *t = piPrev; piPrev = piNext; piNext = t;
-      }
-      reduce_plane(p);
-      emit_ready(p + 1);
-      __syncthreads();
-      p += 2;
+  double va[EPT], vb[EPT];
+  {
+    int64_t pa, pb;
+    planes(sbeg, pa, pb);
+    if (pb >= 0) fetch(vb, pb);
+    if (pa >= 0) fetch(va, pa);
+  }
+  for (int64_t I = sbeg; I < send; ++I) {
+    int64_t pa, pb;
+    planes(I, pa, pb);
+    const bool b_is_a_slot = CO0 && pb >= 0 && pb == 2 * I + 1;  // coarse plane in the fine slot
+    if (pb >= 0) stage(sA, vb);
+    if (pa >= 0) stage(sB, va);
+    // prefetch the next step while this one computes
+    if (I + 1 < send) {
+      int64_t qa, qb;
+      planes(I + 1, qa, qb);
+      if (qb >= 0) fetch(vb, qb);
+      if (qa >= 0) fetch(va, qa);
     }
+    __syncthreads();
+    if (DEC && pb >= 0) {
+      interp2(sA, piNext);
+      const bool own_p = pb >= oib && pb < oie;
+      const int64_t oo = plane_off(a.omap, pb);
+      const int64_t uo = coarse_idx<CO0>(pb, a.m0, a.c0) * a.c1 * a.c2;
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) {
+        const int e = tid + i * NTHR;
+        if (e >= NE) continue;
+        const double u = sA[e];
+        const bool c12 = (flag[i] & F_C1) && (flag[i] & F_C2);
+        const double c = c12 ? 0.0 : u - piNext[i];
+        if (own_p && (flag[i] & F_OWN)) {
+          if (c12) a.uc[uo + ucol[i]] = (T)u;
+          else a.out[oo + colO[i]] = (T)c;
+        }
+        sA[e] = (flag[i] & F_IN) ? c : 0.0;
+      }
+    }
+    if (DEC && pa >= 0) {
+      const bool own_p = pa >= oib && pa < oie;
+      const int64_t oo = plane_off(a.omap, pa);
+      const double r = a.r0[pa];
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) {
+        const int e = tid + i * NTHR;
+        if (e >= NE) continue;
+        const double c = sB[e] - lerp(piPrev[i], piNext[i], r);
+        if (own_p && (flag[i] & F_OWN)) a.out[oo + colO[i]] = (T)c;
+        sB[e] = (flag[i] & F_IN) ? c : 0.0;
+      }
+    }
+    __syncthreads();
+    if (pb >= 0) reduce2(sA, 0);
+    if (pa >= 0) reduce2(sB, NJ * TK);
+    __syncthreads();
+    const double hb = pb >= 0 ? reduce1(0) : 0.0;
+    const double ha = pa >= 0 ? reduce1(NJ * TK) : 0.0;
+    if (CO0) {
+      h0 = h2;
+      h1 = h3;
+      h2 = h4;
+      h3 = b_is_a_slot ? hb : ha;
+      h4 = b_is_a_slot ? 0.0 : hb;
+      if (I >= I0 && hOK) {
+        const double *w = a.W0 + I * 5;
+        double f = w[0] * h0;
+        f = fma(w[1], h1, f);
+        f = fma(w[2], h2, f);
+        f = fma(w[3], h3, f);
+        f = fma(w[4], h4, f);
+        a.F[(I * a.c1 + gJ) * a.c2 + gK] = f;
+      }
+    } else if (hOK) {
+      a.F[(I * a.c1 + gJ) * a.c2 + gK] = hb;
+    }
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) piPrev[i] = piNext[i];
   }
 }
 
@@ -528,6 +601,22 @@ __global__ void __launch_bounds__(256) k_gather(const T *src, Map3 smap, T *dst,
   }
 }
 
+// Streaming copy of 16-byte words, four independent loads in flight per
+// thread (the single-pass bandwidth probe).
+__global__ void __launch_bounds__(256) k_copy_probe(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
+                                                   int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    const uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+    dst[i] = a;
+    dst[i + stride] = b;
+    dst[i + 2 * stride] = c;
+    dst[i + 3 * stride] = d;
+  }
+  for (; i < n; i += stride) dst[i] = src[i];
+}
+
 // ------------------------------------------------------------ host launch
 
 struct Ctx {
@@ -586,7 +675,8 @@ void launch_loadvec(const Level &L, LoadArgs<T> a, Ctx &cx) {
   int64_t TI = std::max<int64_t>(1, (a.c0 + want - 1) / want);
   a.TI = TI;
   const int64_t gz = (a.c0 + TI - 1) / TI;
-  dim3 grid((unsigned)gx, (unsigned)gy, (unsigned)gz);
+  a.gx = (int)gx; a.gy = (int)gy; a.gz = (int)gz;
+  dim3 grid((unsigned)(gx * gy * gz));
   const int key = (L.co[0] ? 4 : 0) | (L.co[1] ? 2 : 0) | (L.co[2] ? 1 : 0);
   switch (key) {
     case 0: launch_loadvec_t<T, DEC, false, false, false>(a, grid, cx); break;
@@ -800,6 +890,22 @@ bool recompose_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t stre
 }
 
 }  // namespace
+
+bool enqueue_copy_probe(const void *src, void *dst, size_t bytes, void *stream, std::string &err) {
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t n = (int64_t)(bytes / 16);
+  if (n == 0) return true;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 256 * 32);
+  TimedLaunch tl(st, "k_copy_probe", 2.0 * (double)bytes);
+  hipLaunchKernelGGL(k_copy_probe, dim3((unsigned)blocks), dim3(256), 0, st, (const uint4 *)src, (uint4 *)dst,
+                     n);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    err = std::string("k_copy_probe launch: ") + hipGetErrorString(e);
+    return false;
+  }
+  return true;
+}
 
 bool enqueue_decompose(const Plan &pl, bool f64, const void *in, void *out, void *ws, void *stream,
                        std::string &err) {

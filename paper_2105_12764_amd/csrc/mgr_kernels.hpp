@@ -12,6 +12,7 @@ namespace mgr {
 // launch fails.
 bool enqueue_decompose(const Plan &pl, bool f64, const void *in, void *out, void *ws, void *stream,
                        std::string &err);
+bool enqueue_copy_probe(const void *src, void *dst, size_t bytes, void *stream, std::string &err);
 bool enqueue_recompose(const Plan &pl, bool f64, const void *in, void *out, void *ws, void *stream,
                        std::string &err);
 

@@ -62,6 +62,9 @@ def lib() -> ctypes.CDLL:
         L.mgr_last_error.restype = ctypes.c_char_p
         L.mgr_release_caches.argtypes = []
         L.mgr_release_caches.restype = None
+        L.mgr_probe_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                     ctypes.c_void_p]
+        L.mgr_probe_copy.restype = ctypes.c_int
         L.mgr_timing_enable.argtypes = [ctypes.c_int]
         L.mgr_timing_enable.restype = ctypes.c_int
         L.mgr_timing_reset.argtypes = []
@@ -202,3 +205,17 @@ def timing_totals():
                             ctypes.byref(b)) == MGR_OK:
             out[name.value.decode()] = (int(n.value), float(ms.value), float(b.value))
     return out
+
+
+def probe_copy(src, dst, stream=None) -> None:
+    """Streaming copy of src into dst (same byte size): the single-pass bandwidth probe."""
+    import torch
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("src and dst must have the same byte size")
+    if stream is None:
+        stream = torch.cuda.current_stream(src.device)
+    s = lib().mgr_probe_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                             ctypes.c_size_t(nbytes), ctypes.c_void_p(stream.cuda_stream))
+    if s != MGR_OK:
+        raise MgrError(s, last_error())
