@@ -80,7 +80,6 @@ struct LoadArgs {
   Map3 smap;
   T *out;         // decompose: coefficient destination (nodal positions)
   Map3 omap;
-  T *uc;          // decompose: coarse values, compact next-level grid
   double *F;      // load vector, compact next-level grid (FP64)
   int64_t m0, m1, m2, c0, c1, c2;
   const double *r0, *r1, *r2;
@@ -102,11 +101,19 @@ __device__ __forceinline__ int xcd_tile(int bid, int nb) {
 // a chunk of TI coarse planes along dim 0.  It walks the fine planes in
 // steps of two -- fine plane a = 2I+1 and coarse plane b = 2I+2 -- with the
 // next step's values prefetched into registers while the current step
-// computes.  Per step: the bilinear interpolant of plane b (dims 1, 2), the
-// coefficients of b and of a (whose interpolant is the dim-0 lerp of the
-// interpolants of the coarse planes around it), P^T M along dims 2 and 1 of
-// both planes, and the dim-0 taps from a five-plane register window.
-template <typename T, bool DEC, bool CO0, bool CO1, bool CO2>
+// computes.  Per step, from the staged values U of both planes:
+//   * P^T M along dims 2 and 1 (LDS), then along dim 0 from a five-plane
+//     register window: f = (P^T M)^{(x)3} U.  By the Galerkin identity
+//     P^T M_l P = M_{l-1}, solving M_{l-1} z' = f gives z' = U_c + z, the
+//     corrected coarse values, so the load vector is formed from the values
+//     and the coefficient computation stays off its critical path;
+//   * (decompose) the coefficients U - Pi U_c of both planes, written to
+//     their nodal positions: Pi of plane b is its bilinear interpolant
+//     (dims 1, 2) from up to four staged neighbours, Pi of plane a the dim-0
+//     lerp of the interpolants of the coarse planes on either side.
+// Recomposition stages the stored coefficients (zero at the coarse nodes)
+// and forms f = (P^T M)^{(x)3} C the same way.
+template <typename T, bool DEC, bool NODAL, bool CO0, bool CO1, bool CO2>
 __global__ void __launch_bounds__(NTHR) k_loadvec(LoadArgs<T> a) {
   constexpr int SJ = CO1 ? 2 : 1, HJ = CO1 ? 2 : 0;
   constexpr int SK = CO2 ? 2 : 1, HK = CO2 ? 2 : 0;
@@ -114,10 +121,12 @@ __global__ void __launch_bounds__(NTHR) k_loadvec(LoadArgs<T> a) {
   constexpr int NK = SK * (TK - 1) + 1 + 2 * HK;
   constexpr int NE = NJ * NK;
   constexpr int EPT = (NE + NTHR - 1) / NTHR;  // tile elements per thread
-  constexpr int NT = 2 * NJ * TK > NE ? 2 * NJ * TK : NE;
-  __shared__ double sA[NE];  // coarse plane b: values, then coefficients
-  __shared__ double sB[NE];  // fine plane a: values, then coefficients
-  __shared__ double sT[NT];  // interpolation scratch, then dim-2 reduced rows of a and b
+  constexpr int NG = NJ * TK;                  // dim-2 reduced rows of one plane
+  __shared__ double sA[NE];      // plane b (coarse along dim 0)
+  __shared__ double sB[NE];      // plane a (fine along dim 0)
+  __shared__ double sG[2 * NG];  // dim-2 reduced rows of b, then of a
+  __shared__ double sR1[NJ], sR2[NK];          // interpolation weights of the tile's rows / columns
+  __shared__ double sW1[TJ * 5], sW2[TK * 5];  // load-vector taps of the tile's coarse rows / columns
 
   const int tid = threadIdx.x;
   const int tile = xcd_tile(blockIdx.x, a.gx * a.gy * a.gz);
@@ -133,36 +142,47 @@ __global__ void __launch_bounds__(NTHR) k_loadvec(LoadArgs<T> a) {
 
   // per-element constants of this thread's tile elements (same for every plane)
   enum : unsigned { F_IN = 1, F_OWN = 2, F_C1 = 4, F_C2 = 8 };
-  unsigned flag[EPT];
-  int colS[EPT], colO[EPT], ucol[EPT];  // in-plane offsets (planes hold < 2^31 nodes)
+  unsigned flags = 0;                    // 4 bits per element
+  int colS[EPT], colO[NODAL ? EPT : 1];  // in-plane offsets (planes hold < 2^31 nodes)
+  colO[0] = 0;
 #pragma unroll
   for (int i = 0; i < EPT; ++i) {
     const int e = tid + i * NTHR;
     const int j = e / NK, k = e % NK;
     const int64_t gj = fj0 + j, gk = fk0 + k;
     unsigned f = 0;
-    colS[i] = colO[i] = ucol[i] = 0;
+    colS[i] = 0;
+    if (NODAL) colO[NODAL ? i : 0] = 0;
     if (e < NE && gj >= 0 && gj < a.m1 && gk >= 0 && gk < a.m2) {
       f |= F_IN;
       if (gj >= ojb && gj < oje && gk >= okb && gk < oke) f |= F_OWN;
       if (coarse_pos<CO1>(gj, a.m1)) f |= F_C1;
       if (coarse_pos<CO2>(gk, a.m2)) f |= F_C2;
       colS[i] = (int)(a.smap.t1 ? a.smap.t1[gj] + a.smap.t2[gk] : gj * a.smap.s1 + gk);
-      if (DEC) {
-        colO[i] = (int)(a.omap.t1 ? a.omap.t1[gj] + a.omap.t2[gk] : gj * a.omap.s1 + gk);
-        ucol[i] = (int)(coarse_idx<CO1>(gj, a.m1, a.c1) * a.c2 + coarse_idx<CO2>(gk, a.m2, a.c2));
-      }
+      if (DEC && NODAL) colO[NODAL ? i : 0] = (int)(a.omap.t1[gj] + a.omap.t2[gk]);
     }
-    flag[i] = f;
+    flags |= f << (4 * i);
   }
+  auto flag_of = [&](int i) -> unsigned { return (flags >> (4 * i)) & 15u; };
 
   // the (J, K) load-vector entry this thread reduces and emits
   const int hJ = tid / TK, hK = tid % TK;
   const int64_t gJ = J0 + hJ, gK = K0 + hK;
   const bool hOK = gJ < a.c1 && gK < a.c2;
-  double w1[5];
-#pragma unroll
-  for (int o = 0; o < 5; ++o) w1[o] = (CO1 && gJ < a.c1) ? a.W1[gJ * 5 + o] : 0.0;
+  for (int e = tid; e < TJ * 5; e += NTHR)
+    sW1[e] = (CO1 && J0 + e / 5 < a.c1) ? a.W1[J0 * 5 + e] : 0.0;
+  for (int e = tid; e < TK * 5; e += NTHR)
+    sW2[e] = (CO2 && K0 + e / 5 < a.c2) ? a.W2[K0 * 5 + e] : 0.0;
+  if (DEC) {
+    for (int j = tid; j < NJ; j += NTHR) {
+      const int64_t gj = fj0 + j;
+      sR1[j] = (CO1 && gj >= 0 && gj < a.m1) ? a.r1[gj] : 0.0;
+    }
+    for (int k = tid; k < NK; k += NTHR) {
+      const int64_t gk = fk0 + k;
+      sR2[k] = (CO2 && gk >= 0 && gk < a.m2) ? a.r2[gk] : 0.0;
+    }
+  }
 
   auto plane_off = [&](const Map3 &m, int64_t p) -> int64_t { return m.t0 ? m.t0[p] : p * m.s0; };
 
@@ -173,9 +193,9 @@ __global__ void __launch_bounds__(NTHR) k_loadvec(LoadArgs<T> a) {
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
       double x = 0.0;
-      if (flag[i] & F_IN) {
+      if (flag_of(i) & F_IN) {
         x = (double)a.src[po + colS[i]];
-        if (!DEC && pc && (flag[i] & F_C1) && (flag[i] & F_C2)) x = 0.0;
+        if (!DEC && pc && (flag_of(i) & F_C1) && (flag_of(i) & F_C2)) x = 0.0;
       }
       v[i] = x;
     }
@@ -188,65 +208,44 @@ __global__ void __launch_bounds__(NTHR) k_loadvec(LoadArgs<T> a) {
     }
   };
 
-  // bilinear interpolant (dims 1, 2) of the plane in s, for this thread's elements
-  auto interp2 = [&](const double *s, double (&pi)[EPT]) {
-#pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-      const int e = tid + i * NTHR;
-      if (e >= NE) continue;
-      double v = 0.0;
-      if ((flag[i] & F_IN) && (flag[i] & F_C1)) {
-        const int64_t gk = fk0 + e % NK;
-        v = (flag[i] & F_C2) ? s[e] : lerp(s[e - 1], s[e + 1], a.r2[gk]);
-      }
-      sT[e] = v;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-      const int e = tid + i * NTHR;
-      double v = 0.0;
-      if (e < NE && (flag[i] & F_IN)) {
-        if (flag[i] & F_C1) {
-          v = sT[e];
-        } else {
-          const int64_t gj = fj0 + e / NK;
-          v = lerp(sT[e - NK], sT[e + NK], a.r1[gj]);
-        }
-      }
-      pi[i] = v;
-    }
+  // bilinear interpolant (dims 1, 2) at tile element e of the staged plane s
+  auto interp2 = [&](const double *s, int e, unsigned f) -> double {
+    if (!(f & F_IN)) return 0.0;
+    const bool c1 = f & F_C1, c2 = f & F_C2;
+    if (c1 && c2) return s[e];
+    if (c1) return lerp(s[e - 1], s[e + 1], sR2[e % NK]);
+    if (c2) return lerp(s[e - NK], s[e + NK], sR1[e / NK]);
+    const double rk = sR2[e % NK];
+    return lerp(lerp(s[e - NK - 1], s[e - NK + 1], rk), lerp(s[e + NK - 1], s[e + NK + 1], rk),
+                sR1[e / NK]);
   };
 
-  // P^T M along dims 2 and 1 of the coefficient plane in s; the dim-2 rows
-  // go to sT + off.  Returns this thread's (J, K) value after the barrier
-  // the caller places between the two halves.
+  // P^T M along dim 2 of the staged plane s into sG + off
   auto reduce2 = [&](const double *s, int off) {
-    for (int e = tid; e < NJ * TK; e += NTHR) {
+    for (int e = tid; e < NG; e += NTHR) {
       const int j = e / TK, K = e % TK;
-      const int64_t gk2 = K0 + K;
       double g = 0.0;
-      if (gk2 < a.c2) {
+      if (K0 + K < a.c2) {
         if (CO2) {
-          const double *w = a.W2 + gk2 * 5;
           const double *row = s + j * NK + 2 * K;
 #pragma unroll
-          for (int o = 0; o < 5; ++o) g = fma(w[o], row[o], g);
+          for (int o = 0; o < 5; ++o) g = fma(sW2[K * 5 + o], row[o], g);
         } else {
           g = s[j * NK + K];
         }
       }
-      sT[off + e] = g;
+      sG[off + e] = g;
     }
   };
+  // P^T M along dim 1 of the reduced rows at sG + off, for this thread's (J, K)
   auto reduce1 = [&](int off) -> double {
     double h = 0.0;
     if (hOK) {
       if (CO1) {
 #pragma unroll
-        for (int o = 0; o < 5; ++o) h = fma(w1[o], sT[off + (2 * hJ + o) * TK + hK], h);
+        for (int o = 0; o < 5; ++o) h = fma(sW1[hJ * 5 + o], sG[off + (2 * hJ + o) * TK + hK], h);
       } else {
-        h = sT[off + hJ * TK + hK];
+        h = sG[off + hJ * TK + hK];
       }
     }
     return h;
@@ -280,9 +279,12 @@ __global__ void __launch_bounds__(NTHR) k_loadvec(LoadArgs<T> a) {
   for (int64_t I = sbeg; I < send; ++I) {
     int64_t pa, pb;
     planes(I, pa, pb);
-    const bool b_is_a_slot = CO0 && pb >= 0 && pb == 2 * I + 1;  // coarse plane in the fine slot
+    const bool b_in_a_slot = CO0 && pb >= 0 && pb == 2 * I + 1;  // coarse plane in the fine slot
     if (pb >= 0) stage(sA, vb);
     if (pa >= 0) stage(sB, va);
+    // uniform across the workgroup: scalar loads
+    const double r0c = (DEC && CO0 && pa >= 0) ? a.r0[pa] : 0.0;
+    const double *w0c = a.W0 + (CO0 ? I : 0) * 5;
     // prefetch the next step while this one computes
     if (I + 1 < send) {
       int64_t qa, qb;
@@ -291,57 +293,47 @@ __global__ void __launch_bounds__(NTHR) k_loadvec(LoadArgs<T> a) {
       if (qa >= 0) fetch(va, qa);
     }
     __syncthreads();
+    if (pb >= 0) reduce2(sA, 0);
+    if (pa >= 0) reduce2(sB, NG);
     if (DEC && pb >= 0) {
-      interp2(sA, piNext);
       const bool own_p = pb >= oib && pb < oie;
       const int64_t oo = plane_off(a.omap, pb);
-      const int64_t uo = coarse_idx<CO0>(pb, a.m0, a.c0) * a.c1 * a.c2;
 #pragma unroll
       for (int i = 0; i < EPT; ++i) {
         const int e = tid + i * NTHR;
-        if (e >= NE) continue;
-        const double u = sA[e];
-        const bool c12 = (flag[i] & F_C1) && (flag[i] & F_C2);
-        const double c = c12 ? 0.0 : u - piNext[i];
-        if (own_p && (flag[i] & F_OWN)) {
-          if (c12) a.uc[uo + ucol[i]] = (T)u;
-          else a.out[oo + colO[i]] = (T)c;
-        }
-        sA[e] = (flag[i] & F_IN) ? c : 0.0;
+        const unsigned f = e < NE ? flag_of(i) : 0u;
+        piNext[i] = interp2(sA, e, f);
+        // nodes coarse along dims 1 and 2 of a coarse plane belong to the next level
+        if (own_p && (f & F_OWN) && !((f & F_C1) && (f & F_C2)))
+          a.out[oo + (NODAL ? colO[NODAL ? i : 0] : colS[i])] = (T)(sA[e] - piNext[i]);
       }
     }
     if (DEC && pa >= 0) {
       const bool own_p = pa >= oib && pa < oie;
       const int64_t oo = plane_off(a.omap, pa);
-      const double r = a.r0[pa];
 #pragma unroll
       for (int i = 0; i < EPT; ++i) {
         const int e = tid + i * NTHR;
-        if (e >= NE) continue;
-        const double c = sB[e] - lerp(piPrev[i], piNext[i], r);
-        if (own_p && (flag[i] & F_OWN)) a.out[oo + colO[i]] = (T)c;
-        sB[e] = (flag[i] & F_IN) ? c : 0.0;
+        if (e < NE && own_p && (flag_of(i) & F_OWN))
+          a.out[oo + (NODAL ? colO[NODAL ? i : 0] : colS[i])] =
+              (T)(sB[e] - lerp(piPrev[i], piNext[i], r0c));
       }
     }
     __syncthreads();
-    if (pb >= 0) reduce2(sA, 0);
-    if (pa >= 0) reduce2(sB, NJ * TK);
-    __syncthreads();
     const double hb = pb >= 0 ? reduce1(0) : 0.0;
-    const double ha = pa >= 0 ? reduce1(NJ * TK) : 0.0;
+    const double ha = pa >= 0 ? reduce1(NG) : 0.0;
     if (CO0) {
       h0 = h2;
       h1 = h3;
       h2 = h4;
-      h3 = b_is_a_slot ? hb : ha;
-      h4 = b_is_a_slot ? 0.0 : hb;
+      h3 = b_in_a_slot ? hb : ha;
+      h4 = b_in_a_slot ? 0.0 : hb;
       if (I >= I0 && hOK) {
-        const double *w = a.W0 + I * 5;
-        double f = w[0] * h0;
-        f = fma(w[1], h1, f);
-        f = fma(w[2], h2, f);
-        f = fma(w[3], h3, f);
-        f = fma(w[4], h4, f);
+        double f = w0c[0] * h0;
+        f = fma(w0c[1], h1, f);
+        f = fma(w0c[2], h2, f);
+        f = fma(w0c[3], h3, f);
+        f = fma(w0c[4], h4, f);
         a.F[(I * a.c1 + gJ) * a.c2 + gK] = f;
       }
     } else if (hOK) {
@@ -361,15 +353,18 @@ SolveDev solve_dev(const DimTabs &d) {
   return SolveDev{d.sub, d.sup, d.w, d.invb, d.Ls, d.Rs, d.wr, d.invbr, d.gam};
 }
 
-// What the last solve of a step does with z when it stores it.
-enum EpiMode { EPI_Z = 0, EPI_ADD_COMPACT = 1, EPI_ADD_NODAL = 2, EPI_SUB_COMPACT = 3 };
+// What the last solve of a step does with its solution z when it stores it:
+// keep it in F (FP64), store it as the next level's values (decompose: the
+// load vector was formed from the values, so z is the corrected coarse grid)
+// compactly or at its nodal positions, or subtract it from the stored coarse
+// values (recompose).
+enum EpiMode { EPI_Z = 0, EPI_STORE_COMPACT = 1, EPI_STORE_NODAL = 2, EPI_SUB_COMPACT = 3 };
 
 template <typename T>
 struct Epi {
   int mode;
-  T *base;       // coarse grid values (compact): coarse values (decompose) / stored grid (recompose)
-  T *dst;        // EPI_ADD_NODAL: output array
-  Map3 nmap;     // EPI_ADD_NODAL: nodal map of the coarse grid
+  T *dst;        // compact next-level grid (STORE_COMPACT / SUB_COMPACT) or output array (STORE_NODAL)
+  Map3 nmap;     // STORE_NODAL: nodal map of the coarse grid
 };
 
 template <typename T>
@@ -377,9 +372,9 @@ __device__ __forceinline__ void epi_store(const Epi<T> &e, double *F, int64_t id
                                           int64_t j, int64_t k, double z) {
   switch (e.mode) {
     case EPI_Z: F[idx] = z; break;
-    case EPI_ADD_COMPACT: e.base[idx] = (T)((double)e.base[idx] + z); break;
-    case EPI_ADD_NODAL: e.dst[moff(e.nmap, i, j, k)] = (T)((double)e.base[idx] + z); break;
-    default: e.base[idx] = (T)((double)e.base[idx] - z); break;
+    case EPI_STORE_COMPACT: e.dst[idx] = (T)z; break;
+    case EPI_STORE_NODAL: e.dst[moff(e.nmap, i, j, k)] = (T)z; break;
+    default: e.dst[idx] = (T)((double)e.dst[idx] - z); break;
   }
 }
 
@@ -565,28 +560,57 @@ __global__ void k_solve_seq(double *F, int64_t nlines, int64_t c, int axis, int6
 
 // --------------------------------------------------- recomposition kernels
 
+// One workgroup per (fine row, chunk of RCHUNK columns): the row's coarse
+// neighbours along dims 0 and 1 are fixed, so each element needs only the
+// dim-2 neighbours of up to four coarse rows (cache-resident: every coarse
+// row serves several fine rows).
+constexpr int RCHUNK = 1024;
+
 template <typename T, bool CO0, bool CO1, bool CO2>
 __global__ void __launch_bounds__(256) k_reconstruct(const T *coef, Map3 cmap, const T *uc, T *dst,
                                                      Map3 dmap, int64_t m0, int64_t m1, int64_t m2,
                                                      int64_t c0, int64_t c1, int64_t c2,
                                                      const double *r0, const double *r1,
-                                                     const double *r2) {
-  const int64_t n = m0 * m1 * m2;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t k = e % m2, row = e / m2, j = row % m1, i = row / m1;
-    const bool f0 = !coarse_pos<CO0>(i, m0), f1 = !coarse_pos<CO1>(j, m1), f2 = !coarse_pos<CO2>(k, m2);
-    const int64_t a0 = f0 ? (i - 1) / 2 : coarse_idx<CO0>(i, m0, c0), b0 = f0 ? a0 + 1 : a0;
-    const int64_t a1 = f1 ? (j - 1) / 2 : coarse_idx<CO1>(j, m1, c1), b1 = f1 ? a1 + 1 : a1;
-    const int64_t a2 = f2 ? (k - 1) / 2 : coarse_idx<CO2>(k, m2, c2), b2 = f2 ? a2 + 1 : a2;
-    const double w2 = f2 ? r2[k] : 0.0, w1 = f1 ? r1[j] : 0.0, w0 = f0 ? r0[i] : 0.0;
-    auto V = [&](int64_t x, int64_t y, int64_t z) { return (double)uc[(x * c1 + y) * c2 + z]; };
-    auto along2 = [&](int64_t x, int64_t y) { return f2 ? lerp(V(x, y, a2), V(x, y, b2), w2) : V(x, y, a2); };
-    auto along1 = [&](int64_t x) { return f1 ? lerp(along2(x, a1), along2(x, b1), w1) : along2(x, a1); };
-    const double pi = f0 ? lerp(along1(a0), along1(b0), w0) : along1(a0);
+                                                     const double *r2, int64_t nchunk) {
+  const int64_t bid = blockIdx.x;
+  const int64_t row = bid / nchunk, chunk = bid - row * nchunk;
+  const int64_t i = row / m1, j = row - i * m1;
+  const bool f0 = !coarse_pos<CO0>(i, m0), f1 = !coarse_pos<CO1>(j, m1);
+  const int64_t a0 = f0 ? (i - 1) / 2 : coarse_idx<CO0>(i, m0, c0), b0 = f0 ? a0 + 1 : a0;
+  const int64_t a1 = f1 ? (j - 1) / 2 : coarse_idx<CO1>(j, m1, c1), b1 = f1 ? a1 + 1 : a1;
+  const double w0 = f0 ? r0[i] : 0.0, w1 = f1 ? r1[j] : 0.0;
+  const T *R00 = uc + (a0 * c1 + a1) * c2, *R01 = uc + (a0 * c1 + b1) * c2;
+  const T *R10 = uc + (b0 * c1 + a1) * c2, *R11 = uc + (b0 * c1 + b1) * c2;
+  const int64_t crow = cmap.t0 ? cmap.t0[i] + cmap.t1[j] : i * cmap.s0 + j * cmap.s1;
+  const int64_t drow = dmap.t0 ? dmap.t0[i] + dmap.t1[j] : i * dmap.s0 + j * dmap.s1;
+  const int64_t kend = min<int64_t>(m2, (chunk + 1) * RCHUNK);
+  for (int64_t k = chunk * RCHUNK + threadIdx.x; k < kend; k += blockDim.x) {
+    const bool f2 = !coarse_pos<CO2>(k, m2);
+    const int64_t a2 = f2 ? (k - 1) / 2 : coarse_idx<CO2>(k, m2, c2);
+    double pi;
+    if (f2) {
+      const double w2 = r2[k];
+      auto at = [&](const T *R) { return lerp((double)R[a2], (double)R[a2 + 1], w2); };
+      const double x0 = f1 ? lerp(at(R00), at(R01), w1) : at(R00);
+      if (f0) {
+        const double x1 = f1 ? lerp(at(R10), at(R11), w1) : at(R10);
+        pi = lerp(x0, x1, w0);
+      } else {
+        pi = x0;
+      }
+    } else {
+      auto at = [&](const T *R) { return (double)R[a2]; };
+      const double x0 = f1 ? lerp(at(R00), at(R01), w1) : at(R00);
+      if (f0) {
+        const double x1 = f1 ? lerp(at(R10), at(R11), w1) : at(R10);
+        pi = lerp(x0, x1, w0);
+      } else {
+        pi = x0;
+      }
+    }
     double v = pi;
-    if (f0 || f1 || f2) v += (double)coef[moff(cmap, i, j, k)];
-    dst[moff(dmap, i, j, k)] = (T)v;
+    if (f0 || f1 || f2) v += (double)coef[crow + (cmap.t2 ? cmap.t2[k] : k)];
+    dst[drow + (dmap.t2 ? dmap.t2[k] : k)] = (T)v;
   }
 }
 
@@ -641,26 +665,28 @@ int64_t grid_1d(int64_t n, int64_t per) {
   return std::min<int64_t>(std::max<int64_t>(g, 1), 1 << 20);
 }
 
-template <typename T, bool DEC, bool C0, bool C1, bool C2>
+template <typename T, bool DEC, bool NODAL, bool C0, bool C1, bool C2>
 void launch_loadvec_t(const LoadArgs<T> &a, dim3 grid, Ctx &cx) {
   double bytes = 0.0;
   if (timing_enabled()) {
     const double nl = (double)a.m0 * a.m1 * a.m2, nc = (double)a.c0 * a.c1 * a.c2;
-    // decompose: read the level grid, write coefficients + coarse values, write f
     // recompose: read the coefficients, write f
-    bytes = DEC ? 2.0 * nl * sizeof(T) + 8.0 * nc : (nl - nc) * sizeof(T) + 8.0 * nc;
+    // decompose: read the level grid, write the coefficients and f
+    bytes = DEC ? (2.0 * nl - nc) * sizeof(T) + 8.0 * nc : (nl - nc) * sizeof(T) + 8.0 * nc;
   }
   TimedLaunch tl(cx.stream,
-                 std::string("k_loadvec<") + tname<T>() + ", " + bname(DEC) + ", " + bname(C0) + ", " +
-                     bname(C1) + ", " + bname(C2) + ">",
+                 std::string("k_loadvec<") + tname<T>() + ", " + bname(DEC) + ", " + bname(NODAL) + ", " +
+                     bname(C0) + ", " + bname(C1) + ", " + bname(C2) + ">",
                  bytes);
-  hipLaunchKernelGGL((k_loadvec<T, DEC, C0, C1, C2>), grid, dim3(NTHR), 0, cx.stream, a);
+  hipLaunchKernelGGL((k_loadvec<T, DEC, NODAL, C0, C1, C2>), grid, dim3(NTHR), 0, cx.stream, a);
 }
 
 // Algorithmic bytes of one correction solve over nc unknowns.
 template <typename T>
 double solve_bytes(double nc, int mode) {
-  return mode == EPI_Z ? 16.0 * nc : 8.0 * nc + 2.0 * sizeof(T) * nc;
+  if (mode == EPI_Z) return 16.0 * nc;                          // read F, write F
+  if (mode == EPI_SUB_COMPACT) return 8.0 * nc + 2.0 * sizeof(T) * nc;  // read F, read + write grid
+  return 8.0 * nc + sizeof(T) * nc;                             // read F, write grid
 }
 
 template <typename T, bool DEC>
@@ -678,15 +704,30 @@ void launch_loadvec(const Level &L, LoadArgs<T> a, Ctx &cx) {
   a.gx = (int)gx; a.gy = (int)gy; a.gz = (int)gz;
   dim3 grid((unsigned)(gx * gy * gz));
   const int key = (L.co[0] ? 4 : 0) | (L.co[1] ? 2 : 0) | (L.co[2] ? 1 : 0);
-  switch (key) {
-    case 0: launch_loadvec_t<T, DEC, false, false, false>(a, grid, cx); break;
-    case 1: launch_loadvec_t<T, DEC, false, false, true>(a, grid, cx); break;
-    case 2: launch_loadvec_t<T, DEC, false, true, false>(a, grid, cx); break;
-    case 3: launch_loadvec_t<T, DEC, false, true, true>(a, grid, cx); break;
-    case 4: launch_loadvec_t<T, DEC, true, false, false>(a, grid, cx); break;
-    case 5: launch_loadvec_t<T, DEC, true, false, true>(a, grid, cx); break;
-    case 6: launch_loadvec_t<T, DEC, true, true, false>(a, grid, cx); break;
-    default: launch_loadvec_t<T, DEC, true, true, true>(a, grid, cx); break;
+  // decompose writes coefficients through the nodal tables except on the
+  // finest level, where the output and the level grid share one layout
+  if (DEC && a.omap.t0) {
+    switch (key) {
+      case 0: launch_loadvec_t<T, DEC, true, false, false, false>(a, grid, cx); break;
+      case 1: launch_loadvec_t<T, DEC, true, false, false, true>(a, grid, cx); break;
+      case 2: launch_loadvec_t<T, DEC, true, false, true, false>(a, grid, cx); break;
+      case 3: launch_loadvec_t<T, DEC, true, false, true, true>(a, grid, cx); break;
+      case 4: launch_loadvec_t<T, DEC, true, true, false, false>(a, grid, cx); break;
+      case 5: launch_loadvec_t<T, DEC, true, true, false, true>(a, grid, cx); break;
+      case 6: launch_loadvec_t<T, DEC, true, true, true, false>(a, grid, cx); break;
+      default: launch_loadvec_t<T, DEC, true, true, true, true>(a, grid, cx); break;
+    }
+  } else {
+    switch (key) {
+      case 0: launch_loadvec_t<T, DEC, false, false, false, false>(a, grid, cx); break;
+      case 1: launch_loadvec_t<T, DEC, false, false, false, true>(a, grid, cx); break;
+      case 2: launch_loadvec_t<T, DEC, false, false, true, false>(a, grid, cx); break;
+      case 3: launch_loadvec_t<T, DEC, false, false, true, true>(a, grid, cx); break;
+      case 4: launch_loadvec_t<T, DEC, false, true, false, false>(a, grid, cx); break;
+      case 5: launch_loadvec_t<T, DEC, false, true, false, true>(a, grid, cx); break;
+      case 6: launch_loadvec_t<T, DEC, false, true, true, false>(a, grid, cx); break;
+      default: launch_loadvec_t<T, DEC, false, true, true, true>(a, grid, cx); break;
+    }
   }
   cx.check("k_loadvec launch");
 }
@@ -759,7 +800,7 @@ void solve_all(double *F, const Level &L, const Epi<T> &last, Ctx &cx) {
     if (L.co[k]) lastk = k;
   for (int k = 0; k < kDims; ++k) {
     if (!L.co[k]) continue;
-    Epi<T> ep = (k == lastk) ? last : Epi<T>{EPI_Z, nullptr, nullptr, Map3{}};
+    Epi<T> ep = (k == lastk) ? last : Epi<T>{EPI_Z, nullptr, Map3{}};
     launch_solve<T>(F, L, k, ep, cx);
   }
 }
@@ -768,7 +809,9 @@ template <typename T>
 void launch_reconstruct(const Level &L, const T *coef, Map3 cmap, const T *uc, T *dst, Map3 dmap,
                         Ctx &cx) {
   const int64_t n = L.m[0] * L.m[1] * L.m[2];
-  dim3 grid((unsigned)grid_1d(n, 256 * 4));
+  const int64_t nchunk = (L.m[2] + RCHUNK - 1) / RCHUNK;
+  const int64_t threads = std::min<int64_t>(256, (L.m[2] + 63) / 64 * 64);
+  dim3 grid((unsigned)(L.m[0] * L.m[1] * nchunk));
   const int key = (L.co[0] ? 4 : 0) | (L.co[1] ? 2 : 0) | (L.co[2] ? 1 : 0);
   const double nl = (double)n, nc = (double)L.c[0] * L.c[1] * L.c[2];
   // read coefficients and the coarse grid, write the level grid
@@ -776,10 +819,10 @@ void launch_reconstruct(const Level &L, const T *coef, Map3 cmap, const T *uc, T
                  std::string("k_reconstruct<") + tname<T>() + ", " + bname(L.co[0]) + ", " + bname(L.co[1]) +
                      ", " + bname(L.co[2]) + ">",
                  timing_enabled() ? ((nl - nc) + nc + nl) * sizeof(T) : 0.0);
-#define MGR_RECON(C0, C1, C2)                                                                       \
-  hipLaunchKernelGGL((k_reconstruct<T, C0, C1, C2>), grid, dim3(256), 0, cx.stream, coef, cmap, uc, \
-                     dst, dmap, L.m[0], L.m[1], L.m[2], L.c[0], L.c[1], L.c[2], L.d[0].r, L.d[1].r,  \
-                     L.d[2].r)
+#define MGR_RECON(C0, C1, C2)                                                                        \
+  hipLaunchKernelGGL((k_reconstruct<T, C0, C1, C2>), grid, dim3((unsigned)threads), 0, cx.stream, coef, \
+                     cmap, uc, dst, dmap, L.m[0], L.m[1], L.m[2], L.c[0], L.c[1], L.c[2], L.d[0].r,    \
+                     L.d[1].r, L.d[2].r, nchunk)
   switch (key) {
     case 0: MGR_RECON(false, false, false); break;
     case 1: MGR_RECON(false, false, true); break;
@@ -822,27 +865,25 @@ bool decompose_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t stre
   Map3 smap = compact_map(pl.n[1], pl.n[2]);
   for (int s = 0; s < pl.nlev && cx.ok; ++s) {
     const Level &L = pl.lev[s];
-    T *uc = (T *)w.buf[s % 2];
+    T *next = (T *)w.buf[s % 2];
     LoadArgs<T> a{};
     a.src = src;
     a.smap = smap;
     a.out = out;
     a.omap = (s == 0) ? compact_map(pl.n[1], pl.n[2]) : nodal_map(L);
-    a.uc = uc;
     a.F = w.F;
     launch_loadvec<T, true>(L, a, cx);
     Epi<T> ep{};
     if (s + 1 < pl.nlev) {
-      ep.mode = EPI_ADD_COMPACT;
-      ep.base = uc;
+      ep.mode = EPI_STORE_COMPACT;
+      ep.dst = next;
     } else {
-      ep.mode = EPI_ADD_NODAL;
-      ep.base = uc;
+      ep.mode = EPI_STORE_NODAL;
       ep.dst = out;
       ep.nmap = nodal_map(pl.lev[s + 1]);
     }
     solve_all<T>(w.F, L, ep, cx);
-    src = uc;
+    src = next;
     smap = compact_map(L.c[1], L.c[2]);
   }
   return cx.ok;
@@ -880,7 +921,7 @@ bool recompose_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t stre
     launch_loadvec<T, false>(L, a, cx);
     Epi<T> ep{};
     ep.mode = EPI_SUB_COMPACT;
-    ep.base = V;
+    ep.dst = V;
     solve_all<T>(w.F, L, ep, cx);
     T *dst = (s == 0) ? out : (T *)w.buf[s % 2];
     launch_reconstruct<T>(L, in, cmap, V, dst, compact_map(L.m[1], L.m[2]), cx);
