@@ -73,6 +73,8 @@ __device__ __forceinline__ int64_t coarse_idx(int64_t g, int64_t m, int64_t c) {
 constexpr int TJ = 8;        // coarse rows (dim 1) per tile
 constexpr int TK = 32;       // coarse columns (dim 2) per tile
 constexpr int NTHR = TJ * TK;
+#define LV_WAVES (DEC ? 1 : 5)
+#define LV_MAXP 128
 
 template <typename T>
 struct LoadArgs {
@@ -114,7 +116,7 @@ __device__ __forceinline__ int xcd_tile(int bid, int nb) {
 // Recomposition stages the stored coefficients (zero at the coarse nodes)
 // and forms f = (P^T M)^{(x)3} C the same way.
 template <typename T, bool DEC, bool NODAL, bool CO0, bool CO1, bool CO2>
-__global__ void __launch_bounds__(NTHR) k_loadvec(LoadArgs<T> a) {
+__global__ void __launch_bounds__(NTHR, LV_WAVES) k_loadvec(LoadArgs<T> a) {
   constexpr int SJ = CO1 ? 2 : 1, HJ = CO1 ? 2 : 0;
   constexpr int SK = CO2 ? 2 : 1, HK = CO2 ? 2 : 0;
   constexpr int NJ = SJ * (TJ - 1) + 1 + 2 * HJ;
@@ -125,8 +127,12 @@ __global__ void __launch_bounds__(NTHR) k_loadvec(LoadArgs<T> a) {
   __shared__ double sA[NE];      // plane b (coarse along dim 0)
   __shared__ double sB[NE];      // plane a (fine along dim 0)
   __shared__ double sG[2 * NG];  // dim-2 reduced rows of b, then of a
-  __shared__ double sR1[NJ], sR2[NK];          // interpolation weights of the tile's rows / columns
-  __shared__ double sW1[TJ * 5], sW2[TK * 5];  // load-vector taps of the tile's coarse rows / columns
+  __shared__ double sR1[DEC ? NJ : 1], sR2[DEC ? NK : 1];  // interpolation weights of rows / columns
+  // Tables read inside the plane loop are staged in LDS (or loaded one step
+  // ahead with the prefetch): a vector-memory read of a table there would
+  // make the compiler wait for the in-flight prefetch loads.
+  __shared__ int64_t sPO[NODAL ? LV_MAXP : 1];  // nodal plane offsets of the window
+  __shared__ double sStep[2][6];                // per-step dim-0 taps and weight
 
   const int tid = threadIdx.x;
   const int tile = xcd_tile(blockIdx.x, a.gx * a.gy * a.gz);
@@ -169,83 +175,107 @@ __global__ void __launch_bounds__(NTHR) k_loadvec(LoadArgs<T> a) {
   const int hJ = tid / TK, hK = tid % TK;
   const int64_t gJ = J0 + hJ, gK = K0 + hK;
   const bool hOK = gJ < a.c1 && gK < a.c2;
-  for (int e = tid; e < TJ * 5; e += NTHR)
-    sW1[e] = (CO1 && J0 + e / 5 < a.c1) ? a.W1[J0 * 5 + e] : 0.0;
-  for (int e = tid; e < TK * 5; e += NTHR)
-    sW2[e] = (CO2 && K0 + e / 5 < a.c2) ? a.W2[K0 * 5 + e] : 0.0;
   if (DEC) {
     for (int j = tid; j < NJ; j += NTHR) {
       const int64_t gj = fj0 + j;
-      sR1[j] = (CO1 && gj >= 0 && gj < a.m1) ? a.r1[gj] : 0.0;
+      sR1[j] = (CO1 && gj >= 0 && gj < a.m1 && !coarse_pos<CO1>(gj, a.m1)) ? a.r1[gj] : 0.0;
     }
     for (int k = tid; k < NK; k += NTHR) {
       const int64_t gk = fk0 + k;
-      sR2[k] = (CO2 && gk >= 0 && gk < a.m2) ? a.r2[gk] : 0.0;
+      sR2[k] = (CO2 && gk >= 0 && gk < a.m2 && !coarse_pos<CO2>(gk, a.m2)) ? a.r2[gk] : 0.0;
     }
   }
 
-  auto plane_off = [&](const Map3 &m, int64_t p) -> int64_t { return m.t0 ? m.t0[p] : p * m.s0; };
+  // plane window [pw0, pw0 + LV_MAXP) of this workgroup (host keeps 2 TI + 3 <= LV_MAXP)
+  const int64_t pw0 = CO0 ? max<int64_t>(0, 2 * I0 - 2) : I0;
+  if (NODAL) {
+    const int64_t *t0 = DEC ? a.omap.t0 : a.smap.t0;
+    for (int q = tid; q < LV_MAXP; q += NTHR) sPO[q] = (pw0 + q < a.m0) ? t0[pw0 + q] : 0;
+  }
+  // plane offsets: the field-side array of a coarser level goes through the nodal tables
+  auto src_plane = [&](int64_t p) -> int64_t { return (!DEC && NODAL) ? sPO[p - pw0] : p * a.smap.s0; };
+  auto out_plane = [&](int64_t p) -> int64_t { return (DEC && NODAL) ? sPO[p - pw0] : p * a.omap.s0; };
 
-  // loads of one plane into registers (zero outside the grid / at stored coarse values)
+  // loads of one plane into registers.  Branch-free, so that all of them
+  // are in flight together: elements outside the grid read the plane's first
+  // node (colS = 0) and are masked when staged.
   auto fetch = [&](double (&v)[EPT], int64_t p) {
-    const int64_t po = plane_off(a.smap, p);
-    const bool pc = coarse_pos<CO0>(p, a.m0);
+    const T *base = a.src + src_plane(p);
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-      double x = 0.0;
-      if (flag_of(i) & F_IN) {
-        x = (double)a.src[po + colS[i]];
-        if (!DEC && pc && (flag_of(i) & F_C1) && (flag_of(i) & F_C2)) x = 0.0;
-      }
-      v[i] = x;
-    }
+    for (int i = 0; i < EPT; ++i) v[i] = (double)base[colS[i]];
   };
-  auto stage = [&](double *s, const double (&v)[EPT]) {
+  // stage a plane into LDS: zero outside the grid and, for recomposition of a
+  // plane coarse along dim 0, at the stored coarse values (not coefficients)
+  auto stage = [&](double *s, const double (&v)[EPT], bool zero_coarse) {
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
       const int e = tid + i * NTHR;
-      if (e < NE) s[e] = v[i];
+      const unsigned f = flag_of(i);
+      const bool keep = (f & F_IN) && !(zero_coarse && (f & F_C1) && (f & F_C2));
+      if (e < NE) s[e] = keep ? v[i] : 0.0;
     }
   };
 
-  // bilinear interpolant (dims 1, 2) at tile element e of the staged plane s
+  // bilinear interpolant (dims 1, 2) at tile element e of the staged plane s,
+  // branch-free: along a dimension where the node is coarse both neighbours
+  // are the node itself and the weight is 0 (the weight tables hold 0 there)
   auto interp2 = [&](const double *s, int e, unsigned f) -> double {
     if (!(f & F_IN)) return 0.0;
-    const bool c1 = f & F_C1, c2 = f & F_C2;
-    if (c1 && c2) return s[e];
-    if (c1) return lerp(s[e - 1], s[e + 1], sR2[e % NK]);
-    if (c2) return lerp(s[e - NK], s[e + NK], sR1[e / NK]);
-    const double rk = sR2[e % NK];
-    return lerp(lerp(s[e - NK - 1], s[e - NK + 1], rk), lerp(s[e + NK - 1], s[e + NK + 1], rk),
-                sR1[e / NK]);
+    const int dk = (f & F_C2) ? 0 : 1, dj = (f & F_C1) ? 0 : NK;
+    const double rk = sR2[e % NK], rj = sR1[e / NK];
+    return lerp(lerp(s[e - dj - dk], s[e - dj + dk], rk), lerp(s[e + dj - dk], s[e + dj + dk], rk), rj);
   };
 
-  // P^T M along dim 2 of the staged plane s into sG + off
-  auto reduce2 = [&](const double *s, int off) {
-    for (int e = tid; e < NG; e += NTHR) {
-      const int j = e / TK, K = e % TK;
-      double g = 0.0;
-      if (K0 + K < a.c2) {
-        if (CO2) {
-          const double *row = s + j * NK + 2 * K;
+  // P^T M along dim 2 of the staged plane s into sG + off, stored column-major
+  // ([K][j]).  Thread t always takes column K = t / RG and rows j = t % RG,
+  // t % RG + RG, ...: no divisions, its five taps stay in registers, and
+  // consecutive lanes walk rows (odd pitch NK: no LDS bank conflicts).
+  constexpr int RG = NTHR / TK;               // row groups per column
+  constexpr int RPT = (NJ + RG - 1) / RG;     // rows per thread
+  const int rK = tid / RG, rj0 = tid % RG;
+  const bool rOK = K0 + rK < a.c2;
+  // taps of this thread's dim-2 column and dim-1 row: via LDS into registers
+  __shared__ double sW[(TJ + TK) * 5];
+  for (int e = tid; e < TK * 5; e += NTHR)
+    sW[TJ * 5 + e] = (CO2 && K0 + e / 5 < a.c2) ? a.W2[K0 * 5 + e] : 0.0;
+  for (int e = tid; e < TJ * 5; e += NTHR)
+    sW[e] = (CO1 && J0 + e / 5 < a.c1) ? a.W1[J0 * 5 + e] : 0.0;
+  __syncthreads();
+  double w1[5], w2[5];
 #pragma unroll
-          for (int o = 0; o < 5; ++o) g = fma(sW2[K * 5 + o], row[o], g);
-        } else {
-          g = s[j * NK + K];
+  for (int o = 0; o < 5; ++o) {
+    w2[o] = sW[TJ * 5 + rK * 5 + o];
+    w1[o] = sW[hJ * 5 + o];
+  }
+  auto reduce2 = [&](const double *s, int off) {
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int j = rj0 + q * RG;
+      if (j < NJ) {
+        double g = 0.0;
+        if (rOK) {
+          if (CO2) {
+            const double *row = s + j * NK + 2 * rK;
+#pragma unroll
+            for (int o = 0; o < 5; ++o) g = fma(w2[o], row[o], g);
+          } else {
+            g = s[j * NK + rK];
+          }
         }
+        sG[off + rK * NJ + j] = g;
       }
-      sG[off + e] = g;
     }
   };
   // P^T M along dim 1 of the reduced rows at sG + off, for this thread's (J, K)
   auto reduce1 = [&](int off) -> double {
     double h = 0.0;
     if (hOK) {
+      const double *col = sG + off + hK * NJ;
       if (CO1) {
 #pragma unroll
-        for (int o = 0; o < 5; ++o) h = fma(sW1[hJ * 5 + o], sG[off + (2 * hJ + o) * TK + hK], h);
+        for (int o = 0; o < 5; ++o) h = fma(w1[o], col[2 * hJ + o], h);
       } else {
-        h = sG[off + hJ * TK + hK];
+        h = col[hJ];
       }
     }
     return h;
@@ -269,35 +299,50 @@ __global__ void __launch_bounds__(NTHR) k_loadvec(LoadArgs<T> a) {
     if (pa >= 0 && pb < 0) { pb = pa; pa = -1; }  // last plane of an even extent is coarse
   };
 
+  // dim-0 taps of step I (threads 0-4) and the dim-0 weight of its fine plane
+  // (thread 5), loaded with the step's plane data and staged with it
+  // The load is unconditional (every thread reads some valid double) and
+  // nothing uses kv before it is staged, so the compiler keeps it in flight
+  // with the plane loads; entries are only read where they are meaningful.
+  double kv = 0.0;
+  auto fetch_consts = [&](int64_t I, int64_t pa) {
+    const double *kp = a.r1 ? a.r1 : a.r2;  // any valid table when dim 0 is not coarsened
+    if (CO0) {
+      const int64_t Ic = min(max(I, (int64_t)0), a.c0 - 1);
+      kp = tid < 5 ? a.W0 + Ic * 5 + tid : ((DEC && pa >= 0) ? a.r0 + pa : a.W0);
+    }
+    kv = *kp;
+  };
   double va[EPT], vb[EPT];
   {
     int64_t pa, pb;
     planes(sbeg, pa, pb);
     if (pb >= 0) fetch(vb, pb);
     if (pa >= 0) fetch(va, pa);
+    fetch_consts(sbeg, pa);
   }
   for (int64_t I = sbeg; I < send; ++I) {
     int64_t pa, pb;
     planes(I, pa, pb);
     const bool b_in_a_slot = CO0 && pb >= 0 && pb == 2 * I + 1;  // coarse plane in the fine slot
-    if (pb >= 0) stage(sA, vb);
-    if (pa >= 0) stage(sB, va);
-    // uniform across the workgroup: scalar loads
-    const double r0c = (DEC && CO0 && pa >= 0) ? a.r0[pa] : 0.0;
-    const double *w0c = a.W0 + (CO0 ? I : 0) * 5;
+    if (pb >= 0) stage(sA, vb, !DEC);
+    if (pa >= 0) stage(sB, va, false);
+    double *kst = sStep[I & 1];
+    if (tid < 6) kst[tid] = kv;
     // prefetch the next step while this one computes
     if (I + 1 < send) {
       int64_t qa, qb;
       planes(I + 1, qa, qb);
       if (qb >= 0) fetch(vb, qb);
       if (qa >= 0) fetch(va, qa);
+      fetch_consts(I + 1, qa);
     }
     __syncthreads();
     if (pb >= 0) reduce2(sA, 0);
     if (pa >= 0) reduce2(sB, NG);
     if (DEC && pb >= 0) {
       const bool own_p = pb >= oib && pb < oie;
-      const int64_t oo = plane_off(a.omap, pb);
+      const int64_t oo = out_plane(pb);
 #pragma unroll
       for (int i = 0; i < EPT; ++i) {
         const int e = tid + i * NTHR;
@@ -310,13 +355,13 @@ __global__ void __launch_bounds__(NTHR) k_loadvec(LoadArgs<T> a) {
     }
     if (DEC && pa >= 0) {
       const bool own_p = pa >= oib && pa < oie;
-      const int64_t oo = plane_off(a.omap, pa);
+      const int64_t oo = out_plane(pa);
 #pragma unroll
       for (int i = 0; i < EPT; ++i) {
         const int e = tid + i * NTHR;
         if (e < NE && own_p && (flag_of(i) & F_OWN))
           a.out[oo + (NODAL ? colO[NODAL ? i : 0] : colS[i])] =
-              (T)(sB[e] - lerp(piPrev[i], piNext[i], r0c));
+              (T)(sB[e] - lerp(piPrev[i], piNext[i], kst[5]));
       }
     }
     __syncthreads();
@@ -329,11 +374,11 @@ __global__ void __launch_bounds__(NTHR) k_loadvec(LoadArgs<T> a) {
       h3 = b_in_a_slot ? hb : ha;
       h4 = b_in_a_slot ? 0.0 : hb;
       if (I >= I0 && hOK) {
-        double f = w0c[0] * h0;
-        f = fma(w0c[1], h1, f);
-        f = fma(w0c[2], h2, f);
-        f = fma(w0c[3], h3, f);
-        f = fma(w0c[4], h4, f);
+        double f = kst[0] * h0;
+        f = fma(kst[1], h1, f);
+        f = fma(kst[2], h2, f);
+        f = fma(kst[3], h3, f);
+        f = fma(kst[4], h4, f);
         a.F[(I * a.c1 + gJ) * a.c2 + gK] = f;
       }
     } else if (hOK) {
@@ -560,57 +605,203 @@ __global__ void k_solve_seq(double *F, int64_t nlines, int64_t c, int axis, int6
 
 // --------------------------------------------------- recomposition kernels
 
-// One workgroup per (fine row, chunk of RCHUNK columns): the row's coarse
-// neighbours along dims 0 and 1 are fixed, so each element needs only the
-// dim-2 neighbours of up to four coarse rows (cache-resident: every coarse
-// row serves several fine rows).
-constexpr int RCHUNK = 1024;
+// Recomposition of one level: every node of the level grid gets its stored
+// coefficient plus the multilinear interpolant of the coarse values
+// (U_c = stored coarse grid - z).  A workgroup owns a (2TJ x 2TK) tile of
+// fine nodes in dims (1, 2) and a chunk of coarse planes along dim 0, and
+// walks plane pairs like k_loadvec: the coarse values of the tile (with a
+// one-node halo) are staged in LDS per coarse plane, the interpolant of each
+// owned node stays in registers for the fine plane after it, and the next
+// pair's coefficients and coarse values are prefetched into registers.  Each
+// coefficient is read once and each output written once.
+template <typename T>
+struct ReconArgs {
+  const T *coef;  // stored coefficients (level grid positions)
+  Map3 cmap;
+  const T *uc;    // coarse values U_c, compact next-level grid
+  T *dst;         // level grid, compact
+  int64_t m0, m1, m2, c0, c1, c2;
+  const double *r0, *r1, *r2;
+  int64_t TI;
+  int gx, gy, gz;
+};
 
-template <typename T, bool CO0, bool CO1, bool CO2>
-__global__ void __launch_bounds__(256) k_reconstruct(const T *coef, Map3 cmap, const T *uc, T *dst,
-                                                     Map3 dmap, int64_t m0, int64_t m1, int64_t m2,
-                                                     int64_t c0, int64_t c1, int64_t c2,
-                                                     const double *r0, const double *r1,
-                                                     const double *r2, int64_t nchunk) {
-  const int64_t bid = blockIdx.x;
-  const int64_t row = bid / nchunk, chunk = bid - row * nchunk;
-  const int64_t i = row / m1, j = row - i * m1;
-  const bool f0 = !coarse_pos<CO0>(i, m0), f1 = !coarse_pos<CO1>(j, m1);
-  const int64_t a0 = f0 ? (i - 1) / 2 : coarse_idx<CO0>(i, m0, c0), b0 = f0 ? a0 + 1 : a0;
-  const int64_t a1 = f1 ? (j - 1) / 2 : coarse_idx<CO1>(j, m1, c1), b1 = f1 ? a1 + 1 : a1;
-  const double w0 = f0 ? r0[i] : 0.0, w1 = f1 ? r1[j] : 0.0;
-  const T *R00 = uc + (a0 * c1 + a1) * c2, *R01 = uc + (a0 * c1 + b1) * c2;
-  const T *R10 = uc + (b0 * c1 + a1) * c2, *R11 = uc + (b0 * c1 + b1) * c2;
-  const int64_t crow = cmap.t0 ? cmap.t0[i] + cmap.t1[j] : i * cmap.s0 + j * cmap.s1;
-  const int64_t drow = dmap.t0 ? dmap.t0[i] + dmap.t1[j] : i * dmap.s0 + j * dmap.s1;
-  const int64_t kend = min<int64_t>(m2, (chunk + 1) * RCHUNK);
-  for (int64_t k = chunk * RCHUNK + threadIdx.x; k < kend; k += blockDim.x) {
-    const bool f2 = !coarse_pos<CO2>(k, m2);
-    const int64_t a2 = f2 ? (k - 1) / 2 : coarse_idx<CO2>(k, m2, c2);
-    double pi;
-    if (f2) {
-      const double w2 = r2[k];
-      auto at = [&](const T *R) { return lerp((double)R[a2], (double)R[a2 + 1], w2); };
-      const double x0 = f1 ? lerp(at(R00), at(R01), w1) : at(R00);
-      if (f0) {
-        const double x1 = f1 ? lerp(at(R10), at(R11), w1) : at(R10);
-        pi = lerp(x0, x1, w0);
-      } else {
-        pi = x0;
-      }
-    } else {
-      auto at = [&](const T *R) { return (double)R[a2]; };
-      const double x0 = f1 ? lerp(at(R00), at(R01), w1) : at(R00);
-      if (f0) {
-        const double x1 = f1 ? lerp(at(R10), at(R11), w1) : at(R10);
-        pi = lerp(x0, x1, w0);
-      } else {
-        pi = x0;
+template <typename T, bool NODALC, bool CO0, bool CO1, bool CO2>
+__global__ void __launch_bounds__(NTHR) k_reconstruct(ReconArgs<T> a) {
+  constexpr int SJ = CO1 ? 2 : 1, SK = CO2 ? 2 : 1;
+  constexpr int FJ = SJ * TJ, FK = SK * TK;  // owned fine tile
+  constexpr int NE = FJ * FK;
+  constexpr int EPT = (NE + NTHR - 1) / NTHR;
+  constexpr int CJ = TJ + (CO1 ? 1 : 0), CK = TK + (CO2 ? 1 : 0);  // coarse tile with halo
+  constexpr int NC = CJ * CK;
+  constexpr int EPC = (NC + NTHR - 1) / NTHR;
+  __shared__ double sU[2][NC];  // coarse values of the current / previous coarse plane
+  __shared__ double sR1[FJ], sR2[FK];
+  // tables read inside the plane loop come from LDS or are loaded one step
+  // ahead with the prefetch (see k_loadvec)
+  __shared__ int64_t sPO[NODALC ? LV_MAXP : 1];  // nodal plane offsets of the coefficients
+  __shared__ double sR0[2];                      // dim-0 weight of the step's fine plane
+
+  const int tid = threadIdx.x;
+  const int tile = xcd_tile(blockIdx.x, a.gx * a.gy * a.gz);
+  const int tx = tile % a.gx, ty = (tile / a.gx) % a.gy, tz = tile / (a.gx * a.gy);
+  const int64_t J0 = (int64_t)ty * TJ, K0 = (int64_t)tx * TK;
+  const int64_t I0 = (int64_t)tz * a.TI;
+  const int64_t I1 = min(I0 + a.TI, a.c0);
+  const bool lastJ = J0 + TJ >= a.c1, lastK = K0 + TK >= a.c2, lastI = I1 >= a.c0;
+  const int64_t fj0 = SJ * J0, fje = lastJ ? a.m1 : SJ * (J0 + TJ);
+  const int64_t fk0 = SK * K0, fke = lastK ? a.m2 : SK * (K0 + TK);
+  const int64_t oib = (CO0 ? 2 : 1) * I0, oie = lastI ? a.m0 : (CO0 ? 2 : 1) * I1;
+
+  enum : unsigned { F_IN = 1, F_C1 = 2, F_C2 = 4 };
+  unsigned flags = 0;
+  int colC[EPT], colD[EPT];
+  int lo[EPT];  // coarse-tile index of the lower corner
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = tid + i * NTHR;
+    const int j = e / FK, k = e % FK;
+    const int64_t gj = fj0 + j, gk = fk0 + k;
+    unsigned f = 0;
+    colC[i] = colD[i] = lo[i] = 0;
+    if (e < NE && gj < fje && gk < fke) {
+      f |= F_IN;
+      const bool c1 = coarse_pos<CO1>(gj, a.m1), c2 = coarse_pos<CO2>(gk, a.m2);
+      if (c1) f |= F_C1;
+      if (c2) f |= F_C2;
+      const int64_t a1 = c1 ? coarse_idx<CO1>(gj, a.m1, a.c1) : (gj - 1) / 2;
+      const int64_t a2 = c2 ? coarse_idx<CO2>(gk, a.m2, a.c2) : (gk - 1) / 2;
+      lo[i] = (int)((a1 - J0) * CK + (a2 - K0));
+      colC[i] = (int)(NODALC ? a.cmap.t1[gj] + a.cmap.t2[gk] : gj * a.m2 + gk);
+      colD[i] = (int)(gj * a.m2 + gk);
+    }
+    flags |= f << (3 * i);
+  }
+  auto flag_of = [&](int i) -> unsigned { return (flags >> (3 * i)) & 7u; };
+  for (int j = tid; j < FJ; j += NTHR) {
+    const int64_t gj = fj0 + j;
+    sR1[j] = (CO1 && gj < a.m1 && !coarse_pos<CO1>(gj, a.m1)) ? a.r1[gj] : 0.0;
+  }
+  for (int k = tid; k < FK; k += NTHR) {
+    const int64_t gk = fk0 + k;
+    sR2[k] = (CO2 && gk < a.m2 && !coarse_pos<CO2>(gk, a.m2)) ? a.r2[gk] : 0.0;
+  }
+
+  // coarse-tile elements this thread stages
+  int ucol[EPC];
+#pragma unroll
+  for (int i = 0; i < EPC; ++i) {
+    const int e = tid + i * NTHR;
+    const int64_t J = J0 + e / CK, K = K0 + e % CK;
+    ucol[i] = (e < NC && J < a.c1 && K < a.c2) ? (int)(J * a.c2 + K) : -1;
+  }
+  const int64_t pw0 = CO0 ? max<int64_t>(0, 2 * I0 - 1) : I0;  // plane window (host: 2 TI + 2 <= LV_MAXP)
+  if (NODALC)
+    for (int q = tid; q < LV_MAXP; q += NTHR) sPO[q] = (pw0 + q < a.m0) ? a.cmap.t0[pw0 + q] : 0;
+  __syncthreads();
+
+  // branch-free loads (invalid elements read a valid node and are never used)
+  auto fetchC = [&](double (&v)[EPT], int64_t p) {
+    const T *base = a.coef + (NODALC ? sPO[p - pw0] : p * a.m1 * a.m2);
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) v[i] = (double)base[colC[i]];
+  };
+  auto fetchU = [&](double (&v)[EPC], int64_t cp) {
+    const T *base = a.uc + cp * a.c1 * a.c2;
+#pragma unroll
+    for (int i = 0; i < EPC; ++i) v[i] = (double)base[ucol[i] >= 0 ? ucol[i] : 0];
+  };
+  double kv = 0.0;  // dim-0 weight of the fine plane of a step (thread 0), loaded a step ahead
+  auto fetch_r0 = [&](int64_t pa) { kv = a.r0 ? a.r0[pa >= 0 ? pa : 0] : 0.0; };
+  // interpolant (dims 1, 2) of owned element i from the staged coarse tile s
+  auto interp2 = [&](const double *s, int i) -> double {
+    const unsigned f = flag_of(i);
+    if (!(f & F_IN)) return 0.0;
+    const int e = tid + i * NTHR;
+    const int l = lo[i];
+    const bool c1 = f & F_C1, c2 = f & F_C2;
+    if (c1 && c2) return s[l];
+    if (c1) return lerp(s[l], s[l + 1], sR2[e % FK]);
+    if (c2) return lerp(s[l], s[l + CK], sR1[e / FK]);
+    const double rk = sR2[e % FK];
+    return lerp(lerp(s[l], s[l + 1], rk), lerp(s[l + CK], s[l + CK + 1], rk), sR1[e / FK]);
+  };
+
+  // steps: with dim 0 coarsened, step I covers (a = 2I+1, b = 2I+2) for I in
+  // [I0-1, I1-1]; plane a of the first step is not owned.  Without, step I
+  // is plane I.
+  const int64_t sbeg = CO0 ? I0 - 1 : I0, send = I1;
+  auto planes = [&](int64_t I, int64_t &pa, int64_t &pb) {
+    if (!CO0) { pa = -1; pb = I; return; }
+    pa = 2 * I + 1;
+    pb = 2 * I + 2;
+    if (!(pa >= 0 && pa < a.m0) || I < I0) pa = -1;
+    if (!(pb >= 0 && pb < a.m0)) pb = -1;
+    if (pa >= 0 && pb < 0) { pb = pa; pa = -1; }  // last plane of an even extent is coarse
+  };
+
+  double ca[EPT], cb[EPT], uv[EPC];
+  double piPrev[EPT], piNext[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) piPrev[i] = piNext[i] = 0.0;
+  {
+    int64_t pa, pb;
+    planes(sbeg, pa, pb);
+    if (pb >= 0) { fetchC(cb, pb); fetchU(uv, coarse_idx<CO0>(pb, a.m0, a.c0)); }
+    if (pa >= 0) fetchC(ca, pa);
+    fetch_r0(pa);
+  }
+  int buf = 0;
+  for (int64_t I = sbeg; I < send; ++I) {
+    int64_t pa, pb;
+    planes(I, pa, pb);
+    double *s = sU[buf];
+    if (pb >= 0) {
+#pragma unroll
+      for (int i = 0; i < EPC; ++i) {
+        const int e = tid + i * NTHR;
+        if (e < NC) s[e] = ucol[i] >= 0 ? uv[i] : 0.0;
       }
     }
-    double v = pi;
-    if (f0 || f1 || f2) v += (double)coef[crow + (cmap.t2 ? cmap.t2[k] : k)];
-    dst[drow + (dmap.t2 ? dmap.t2[k] : k)] = (T)v;
+    if (tid == 0) sR0[buf] = kv;
+    double xb[EPT], xa[EPT];
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      xb[i] = cb[i];
+      xa[i] = ca[i];
+    }
+    if (I + 1 < send) {
+      int64_t qa, qb;
+      planes(I + 1, qa, qb);
+      if (qb >= 0) { fetchC(cb, qb); fetchU(uv, coarse_idx<CO0>(qb, a.m0, a.c0)); }
+      if (qa >= 0) fetchC(ca, qa);
+      fetch_r0(qa);
+    }
+    __syncthreads();
+    if (pb >= 0) {
+      const bool own_p = pb >= oib && pb < oie;
+      const int64_t po = pb * a.m1 * a.m2;
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) {
+        piNext[i] = interp2(s, i);
+        const unsigned f = flag_of(i);
+        if (own_p && (f & F_IN)) {
+          const bool coarse_all = coarse_pos<CO0>(pb, a.m0) && (f & F_C1) && (f & F_C2);
+          a.dst[po + colD[i]] = (T)(coarse_all ? piNext[i] : xb[i] + piNext[i]);
+        }
+      }
+    }
+    if (pa >= 0) {
+      const bool own_p = pa >= oib && pa < oie;
+      const int64_t po = pa * a.m1 * a.m2;
+#pragma unroll
+      for (int i = 0; i < EPT; ++i)
+        if (own_p && (flag_of(i) & F_IN))
+          a.dst[po + colD[i]] = (T)(xa[i] + lerp(piPrev[i], piNext[i], sR0[buf]));
+    }
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) piPrev[i] = piNext[i];
+    buf ^= 1;
   }
 }
 
@@ -698,15 +889,16 @@ void launch_loadvec(const Level &L, LoadArgs<T> a, Ctx &cx) {
   const int64_t gx = (a.c2 + TK - 1) / TK, gy = (a.c1 + TJ - 1) / TJ;
   // enough workgroups to fill 256 CUs several times over; chunks of dim 0
   const int64_t want = std::max<int64_t>(1, (2048 + gx * gy - 1) / (gx * gy));
-  int64_t TI = std::max<int64_t>(1, (a.c0 + want - 1) / want);
+  // chunks short enough for the kernel's LDS plane window (2 TI + 3 planes)
+  int64_t TI = std::min<int64_t>(std::max<int64_t>(1, (a.c0 + want - 1) / want), (LV_MAXP - 3) / 2);
   a.TI = TI;
   const int64_t gz = (a.c0 + TI - 1) / TI;
   a.gx = (int)gx; a.gy = (int)gy; a.gz = (int)gz;
   dim3 grid((unsigned)(gx * gy * gz));
   const int key = (L.co[0] ? 4 : 0) | (L.co[1] ? 2 : 0) | (L.co[2] ? 1 : 0);
-  // decompose writes coefficients through the nodal tables except on the
-  // finest level, where the output and the level grid share one layout
-  if (DEC && a.omap.t0) {
+  // on coarser levels the field-side array (decompose: out; recompose: src)
+  // goes through the nodal tables
+  if (DEC ? a.omap.t0 != nullptr : a.smap.t0 != nullptr) {
     switch (key) {
       case 0: launch_loadvec_t<T, DEC, true, false, false, false>(a, grid, cx); break;
       case 1: launch_loadvec_t<T, DEC, true, false, false, true>(a, grid, cx); break;
@@ -805,33 +997,51 @@ void solve_all(double *F, const Level &L, const Epi<T> &last, Ctx &cx) {
   }
 }
 
+template <typename T, bool NC, bool C0, bool C1, bool C2>
+void launch_reconstruct_t(const ReconArgs<T> &a, dim3 grid, Ctx &cx) {
+  hipLaunchKernelGGL((k_reconstruct<T, NC, C0, C1, C2>), grid, dim3(NTHR), 0, cx.stream, a);
+}
+
 template <typename T>
-void launch_reconstruct(const Level &L, const T *coef, Map3 cmap, const T *uc, T *dst, Map3 dmap,
-                        Ctx &cx) {
+void launch_reconstruct(const Level &L, const T *coef, Map3 cmap, const T *uc, T *dst, Ctx &cx) {
+  ReconArgs<T> a{};
+  a.coef = coef; a.cmap = cmap; a.uc = uc; a.dst = dst;
+  a.m0 = L.m[0]; a.m1 = L.m[1]; a.m2 = L.m[2];
+  a.c0 = L.c[0]; a.c1 = L.c[1]; a.c2 = L.c[2];
+  a.r0 = L.d[0].r; a.r1 = L.d[1].r; a.r2 = L.d[2].r;
+  const int64_t gx = (a.c2 + TK - 1) / TK, gy = (a.c1 + TJ - 1) / TJ;
+  const int64_t want = std::max<int64_t>(1, (2048 + gx * gy - 1) / (gx * gy));
+  const int64_t TI = std::min<int64_t>(std::max<int64_t>(1, (a.c0 + want - 1) / want), (LV_MAXP - 2) / 2);
+  a.TI = TI;
+  const int64_t gz = (a.c0 + TI - 1) / TI;
+  a.gx = (int)gx; a.gy = (int)gy; a.gz = (int)gz;
+  dim3 grid((unsigned)(gx * gy * gz));
   const int64_t n = L.m[0] * L.m[1] * L.m[2];
-  const int64_t nchunk = (L.m[2] + RCHUNK - 1) / RCHUNK;
-  const int64_t threads = std::min<int64_t>(256, (L.m[2] + 63) / 64 * 64);
-  dim3 grid((unsigned)(L.m[0] * L.m[1] * nchunk));
-  const int key = (L.co[0] ? 4 : 0) | (L.co[1] ? 2 : 0) | (L.co[2] ? 1 : 0);
   const double nl = (double)n, nc = (double)L.c[0] * L.c[1] * L.c[2];
-  // read coefficients and the coarse grid, write the level grid
+  // read the coefficients and the coarse grid, write the level grid
   TimedLaunch tl(cx.stream,
-                 std::string("k_reconstruct<") + tname<T>() + ", " + bname(L.co[0]) + ", " + bname(L.co[1]) +
-                     ", " + bname(L.co[2]) + ">",
+                 std::string("k_reconstruct<") + tname<T>() + ", " + bname(cmap.t0 != nullptr) + ", " +
+                     bname(L.co[0]) + ", " + bname(L.co[1]) + ", " + bname(L.co[2]) + ">",
                  timing_enabled() ? ((nl - nc) + nc + nl) * sizeof(T) : 0.0);
-#define MGR_RECON(C0, C1, C2)                                                                        \
-  hipLaunchKernelGGL((k_reconstruct<T, C0, C1, C2>), grid, dim3((unsigned)threads), 0, cx.stream, coef, \
-                     cmap, uc, dst, dmap, L.m[0], L.m[1], L.m[2], L.c[0], L.c[1], L.c[2], L.d[0].r,    \
-                     L.d[1].r, L.d[2].r, nchunk)
+  const int key = (cmap.t0 ? 8 : 0) | (L.co[0] ? 4 : 0) | (L.co[1] ? 2 : 0) | (L.co[2] ? 1 : 0);
+#define MGR_RECON(NC, C0, C1, C2) launch_reconstruct_t<T, NC, C0, C1, C2>(a, grid, cx)
   switch (key) {
-    case 0: MGR_RECON(false, false, false); break;
-    case 1: MGR_RECON(false, false, true); break;
-    case 2: MGR_RECON(false, true, false); break;
-    case 3: MGR_RECON(false, true, true); break;
-    case 4: MGR_RECON(true, false, false); break;
-    case 5: MGR_RECON(true, false, true); break;
-    case 6: MGR_RECON(true, true, false); break;
-    default: MGR_RECON(true, true, true); break;
+    case 0: MGR_RECON(false, false, false, false); break;
+    case 1: MGR_RECON(false, false, false, true); break;
+    case 2: MGR_RECON(false, false, true, false); break;
+    case 3: MGR_RECON(false, false, true, true); break;
+    case 4: MGR_RECON(false, true, false, false); break;
+    case 5: MGR_RECON(false, true, false, true); break;
+    case 6: MGR_RECON(false, true, true, false); break;
+    case 7: MGR_RECON(false, true, true, true); break;
+    case 8: MGR_RECON(true, false, false, false); break;
+    case 9: MGR_RECON(true, false, false, true); break;
+    case 10: MGR_RECON(true, false, true, false); break;
+    case 11: MGR_RECON(true, false, true, true); break;
+    case 12: MGR_RECON(true, true, false, false); break;
+    case 13: MGR_RECON(true, true, false, true); break;
+    case 14: MGR_RECON(true, true, true, false); break;
+    default: MGR_RECON(true, true, true, true); break;
   }
 #undef MGR_RECON
   cx.check("k_reconstruct launch");
@@ -924,7 +1134,7 @@ bool recompose_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t stre
     ep.dst = V;
     solve_all<T>(w.F, L, ep, cx);
     T *dst = (s == 0) ? out : (T *)w.buf[s % 2];
-    launch_reconstruct<T>(L, in, cmap, V, dst, compact_map(L.m[1], L.m[2]), cx);
+    launch_reconstruct<T>(L, in, cmap, V, dst, cx);
     V = dst;
   }
   return cx.ok;
