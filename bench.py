@@ -37,7 +37,7 @@ def _log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
-def run_gpu(name: str, steps: int, warmup: int):
+def run_gpu(name: str, steps: int, warmup: int, graph_steps: int = 0):
     import torch
 
     from paper_2105_12764_amd import mgr
@@ -64,8 +64,7 @@ def run_gpu(name: str, steps: int, warmup: int):
         step()
     torch.cuda.synchronize()
 
-    mgr.timing_reset()
-    mgr.timing_enable(True)
+    # timed region 1: the throughput (events only at decompose/recompose boundaries)
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
     mids = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
@@ -77,11 +76,46 @@ def run_gpu(name: str, steps: int, warmup: int):
         ends[i].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    mgr.timing_enable(False)
-    totals = mgr.timing_totals()
     t_dec = sum(starts[i].elapsed_time(mids[i]) for i in range(steps)) / steps
     t_rec = sum(mids[i].elapsed_time(ends[i]) for i in range(steps)) / steps
     _log(f"[bench] {name}: {steps} steps, dec {t_dec:.3f} ms, rec {t_rec:.3f} ms")
+
+    # timed region 2: the same steps with every kernel launch bracketed by HIP
+    # events on its stream (per-kernel times for the roofline)
+    mgr.timing_reset()
+    mgr.timing_enable(True)
+    torch.cuda.synchronize()
+    for i in range(steps):
+        step()
+    torch.cuda.synchronize()
+    mgr.timing_enable(False)
+    totals = mgr.timing_totals()
+
+    graph = None
+    if graph_steps:
+        # the same step captured once into a HIP graph and replayed: the
+        # library's launches become graph nodes (no per-launch host overhead)
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream(dev)
+        side.wait_stream(stream)
+        with torch.cuda.stream(side):
+            step()  # warm the plan cache outside the capture
+            with torch.cuda.graph(g, stream=side):
+                mgr.decompose(x, coords, nlev, out=d, workspace=ws, stream=side)
+                mgr.recompose(d, coords, nlev, out=r, workspace=ws, stream=side)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            g.replay()
+        torch.cuda.synchronize()
+        g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        g0.record()
+        for _ in range(graph_steps):
+            g.replay()
+        g1.record()
+        torch.cuda.synchronize()
+        gms = g0.elapsed_time(g1) / graph_steps
+        graph = {"ms_per_step": gms, "value": 2.0 * int(np.prod(shape)) * np.dtype(dtype).itemsize / (gms * 1e-3) / 1e9}
+        _log(f"[bench] {name}: graph replay {gms:.3f} ms/step")
 
     rt_err = float((r.double() - x.double()).abs().max() / x.double().abs().max())
     n = int(np.prod(shape))
@@ -103,6 +137,7 @@ def run_gpu(name: str, steps: int, warmup: int):
         "alg_GB_per_step": alg_bytes_step / 1e9,
         "alg_GBps": alg_bytes_step / ((t_dec + t_rec) * 1e-3) / 1e9,
         "roundtrip_max_rel_err": rt_err, "kernels": kernels, "roofline": roofline,
+        "graph": graph,
     }
     del x, d, r, ws
     torch.cuda.empty_cache()
@@ -162,6 +197,8 @@ def main():
     ap.add_argument("--fp32-workload", default="cube513_f32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--graph-steps", type=int, default=0,
+                    help="also time this many replays of the step captured as a HIP graph")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -171,7 +208,7 @@ def main():
 
     probe = probe_bandwidth()
     _log(f"[bench] copy probe: {probe['GBps']:.0f} GB/s")
-    res, u, coords, nlev = run_gpu(args.workload, args.steps, args.warmup)
+    res, u, coords, nlev = run_gpu(args.workload, args.steps, args.warmup, args.graph_steps)
     fp32 = None
     if not args.no_fp32 and args.fp32_workload:
         r32, _, _, _ = run_gpu(args.fp32_workload, args.steps, args.warmup)
@@ -207,6 +244,7 @@ def main():
         "cpu_baseline": cpu,
         "kernels": res["kernels"],
         "fp32": fp32,
+        "graph": res["graph"],
     }
     print(json.dumps(line), flush=True)
 

@@ -468,6 +468,39 @@ __device__ __forceinline__ void separator_solve(const SolveDev &tb, int S, int P
   }
 }
 
+// Copies a line's solve tables into LDS -- w, invb, sup, sub, Ls, Rs [c]
+// each, then wr, invbr, gam [P] -- with eight loads in flight per thread, and
+// returns LDS-backed accessors.  Used by the row solver, whose lanes work on
+// different partitions: it is persistent, so a workgroup stages the tables
+// once and then walks many blocks of rows, and table reads inside the
+// sequential solve chain cost an LDS access instead of a round trip to
+// memory.  (In the strided solver a wave shares one partition, and its
+// table reads are scalar-cache loads.)
+__device__ __forceinline__ SolveDev stage_tables(double *tab, const SolveDev &tg, int c, int P, int t,
+                                                 int nt) {
+  const double *src[6] = {tg.w, tg.invb, tg.sup, tg.sub, tg.Ls, tg.Rs};
+  const int n = 6 * c;
+  for (int e = t; e < n; e += 8 * nt) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int q = min(e + u * nt, n - 1);
+      v[u] = src[q / c][q % c];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (e + u * nt < n) tab[e + u * nt] = v[u];
+  }
+  for (int q = t; q < P - 1; q += nt) {
+    tab[n + q] = tg.wr[q];
+    tab[n + P + q] = tg.invbr[q];
+    tab[n + 2 * P + q] = tg.gam[q];
+  }
+  return SolveDev{tab + 3 * c, tab + 2 * c, tab, tab + c, tab + 4 * c, tab + 5 * c,
+                  tab + n, tab + n + P, tab + n + 2 * P};
+}
+__host__ __device__ constexpr int tables_size(int c, int P) { return 6 * c + 3 * P; }
+
 // Lines along dim 0 or 1: lane = position along the contiguous dim 2,
 // wave = partition.  Element q of partition p of line (outer, k) sits at
 // F[outer * so + k + (p*S + q) * sp].
@@ -521,55 +554,71 @@ __global__ void __launch_bounds__(1024) k_solve_strided(double *F, int64_t c, in
 }
 
 // Lines along the contiguous dim 2: a workgroup stages R consecutive rows in
-// LDS (coalesced), thread (r, p) solves partition p of row r in registers.
+// LDS (a straight coalesced copy: consecutive rows are contiguous), thread
+// (r, p) solves partition p of row r in registers.  Persistent over blocks
+// of R rows.
 template <typename T, int S>
 __global__ void __launch_bounds__(1024) k_solve_rows(double *F, int64_t nrows, int c, int P, int R,
-                                                     int pitch, int64_t c1, SolveDev tb, Epi<T> ep) {
+                                                     int64_t c1, SolveDev tg, Epi<T> ep) {
   extern __shared__ double sm[];
   const int t = threadIdx.x, nt = blockDim.x;
+  const SolveDev tb = stage_tables(sm, tg, c, P, t, nt);
+  double *tile = sm + tables_size(c, P);  // [R][c]
+  double *ex = tile + (size_t)R * c;       // separator exchange [4][P][R]
+  double *yF = ex, *yL = ex + P * R, *Fs = ex + 2 * P * R, *tt = ex + 3 * P * R;
   const int r = t % R, p = t / R;
-  const int64_t row0 = (int64_t)blockIdx.x * R;
-  const int nr = (int)min<int64_t>(R, nrows - row0);
-  const int64_t gbase = row0 * c;
-  for (int e = t; e < nr * c; e += nt) sm[(e / c) * pitch + e % c] = F[gbase + e];
-  __syncthreads();
-  const bool active = r < nr;
   const int64_t f = (int64_t)p * S;
   const int nload = p < P - 1 ? S : (int)(c - f);
   const int nint = p < P - 1 ? S - 1 : nload;
-  double x[S];
-  const double *rowp = sm + r * pitch + f;
+  const int64_t nblocks = (nrows + R - 1) / R;
+  for (int64_t blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
+    const int64_t row0 = blk * R;
+    const int nr = (int)min<int64_t>(R, nrows - row0);
+    const int64_t gbase = row0 * c;
+    const int n = nr * c;
+    __syncthreads();  // the previous block's stores have read the tile
+    for (int e = t; e < n; e += 8 * nt) {
+      double v[8];
 #pragma unroll
-  for (int q = 0; q < S; ++q) x[q] = (active && q < nload) ? rowp[q] : 0.0;
-  partition_solve<S>(x, tb, f, nint);
-  if (P > 1) {
-    double *ex = sm + R * pitch;
-    double *yF = ex, *yL = ex + P * R, *Fs = ex + 2 * P * R, *tt = ex + 3 * P * R;
-    yF[p * R + r] = x[0];
-    yL[p * R + r] = pick<S>(x, nint - 1);
-    Fs[p * R + r] = x[S - 1];
+      for (int u = 0; u < 8; ++u) v[u] = F[gbase + min(e + u * nt, n - 1)];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (e + u * nt < n) tile[e + u * nt] = v[u];
+    }
     __syncthreads();
-    if (p == 0) separator_solve(tb, S, P, yF + r, yL + r, Fs + r, tt + r, R);
+    const bool active = r < nr;
+    double x[S];
+    const double *rowp = tile + r * c + f;
+#pragma unroll
+    for (int q = 0; q < S; ++q) x[q] = (active && q < nload) ? rowp[q] : 0.0;
+    partition_solve<S>(x, tb, f, nint);
+    if (P > 1) {
+      yF[p * R + r] = x[0];
+      yL[p * R + r] = pick<S>(x, nint - 1);
+      Fs[p * R + r] = x[S - 1];
+      __syncthreads();
+      if (p == 0) separator_solve(tb, S, P, yF + r, yL + r, Fs + r, tt + r, R);
+      __syncthreads();
+      const double tl = p > 0 ? tt[(p - 1) * R + r] : 0.0;
+      const double tr = p < P - 1 ? tt[p * R + r] : 0.0;
+#pragma unroll
+      for (int q = 0; q < S; ++q)
+        if (q < nint) x[q] = fma(-tl, tb.Ls[f + q], fma(-tr, tb.Rs[f + q], x[q]));
+      if (p < P - 1) x[S - 1] = tr;
+    }
+    if (active) {
+      double *roww = tile + r * c + f;
+#pragma unroll
+      for (int q = 0; q < S; ++q)
+        if (q < nload) roww[q] = x[q];
+    }
     __syncthreads();
-    const double tl = p > 0 ? tt[(p - 1) * R + r] : 0.0;
-    const double tr = p < P - 1 ? tt[p * R + r] : 0.0;
-#pragma unroll
-    for (int q = 0; q < S; ++q)
-      if (q < nint) x[q] = fma(-tl, tb.Ls[f + q], fma(-tr, tb.Rs[f + q], x[q]));
-    if (p < P - 1) x[S - 1] = tr;
-  }
-  __syncthreads();
-  if (active) {
-    double *roww = sm + r * pitch + f;
-#pragma unroll
-    for (int q = 0; q < S; ++q)
-      if (q < nload) roww[q] = x[q];
-  }
-  __syncthreads();
-  for (int e = t; e < nr * c; e += nt) {
-    const int rr = e / c, cc = e % c;
-    const int64_t row = row0 + rr;
-    epi_store(ep, F, gbase + e, row / c1, row % c1, cc, sm[rr * pitch + cc]);
+    for (int e = t; e < n; e += nt) {
+      const unsigned rr = (unsigned)e / (unsigned)c, cc = (unsigned)e - rr * (unsigned)c;
+      const unsigned row = (unsigned)row0 + rr;
+      const unsigned i = row / (unsigned)c1, j = row - i * (unsigned)c1;
+      epi_store(ep, F, gbase + e, i, j, cc, tile[e]);
+    }
   }
 }
 
@@ -924,6 +973,19 @@ void launch_loadvec(const Level &L, LoadArgs<T> a, Ctx &cx) {
   cx.check("k_loadvec launch");
 }
 
+// Persistent grid size: enough workgroups to fill the device a few times.
+int64_t persistent_grid(int64_t nblocks) {
+  static int ncu = 0;
+  if (ncu == 0) {
+    int dev = 0, v = 0;
+    ncu = (hipGetDevice(&dev) == hipSuccess &&
+           hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+              ? v
+              : 256;
+  }
+  return std::max<int64_t>(1, std::min<int64_t>(nblocks, 4 * (int64_t)ncu));
+}
+
 template <typename T, int S>
 void launch_strided_s(double *F, const Level &L, int axis, const Epi<T> &ep, Ctx &cx) {
   const DimTabs &d = L.d[axis];
@@ -944,23 +1006,22 @@ template <typename T, int S>
 void launch_rows_s(double *F, const Level &L, const Epi<T> &ep, Ctx &cx) {
   const DimTabs &d = L.d[2];
   const int64_t c = L.c[2], nrows = L.c[0] * L.c[1];
-  const int pitch = (int)(c | 1);
-  const int budget = 64 * 1024 / (int)sizeof(double);
+  const int budget = 64 * 1024 / (int)sizeof(double) - tables_size((int)c, d.P);
   int R = std::min(64, 1024 / d.P);
-  R = std::min<int64_t>(R, budget / (pitch + 4 * d.P));
+  R = std::min<int64_t>(R, budget / (c + 4 * d.P));
   R = std::max(R, 1);
-  const size_t lds = (size_t)(R * pitch + 4 * d.P * R) * sizeof(double);
-  dim3 grid((unsigned)((nrows + R - 1) / R));
+  const size_t lds = (size_t)(tables_size((int)c, d.P) + R * c + 4 * d.P * R) * sizeof(double);
+  dim3 grid((unsigned)persistent_grid((nrows + R - 1) / R));
   TimedLaunch tl(cx.stream, std::string("k_solve_rows<") + tname<T>() + ", " + std::to_string(S) + ">",
                  timing_enabled() ? solve_bytes<T>((double)nrows * c, ep.mode) : 0.0);
   hipLaunchKernelGGL((k_solve_rows<T, S>), grid, dim3(R * d.P), lds, cx.stream, F, nrows, (int)c, d.P,
-                     R, pitch, L.c[1], solve_dev(d), ep);
+                     R, L.c[1], solve_dev(d), ep);
 }
 
 template <typename T>
 void launch_solve(double *F, const Level &L, int axis, const Epi<T> &ep, Ctx &cx) {
   const DimTabs &d = L.d[axis];
-  if (d.S == 0) {
+  if (d.S == 0) {  // the plan chose one sequential partition (tables built for it)
     const int64_t nlines = L.c[0] * L.c[1] * L.c[2] / L.c[axis];
     TimedLaunch tl(cx.stream, std::string("k_solve_seq<") + tname<T>() + ">",
                    timing_enabled() ? solve_bytes<T>((double)L.c[0] * L.c[1] * L.c[2], ep.mode) : 0.0);
