@@ -4,7 +4,7 @@
 A step is one full decomposition followed by one full recomposition of the
 workload (every level, every kernel of the path), inputs resident in HBM.
 Prints one JSON line:
-  value        refactoring throughput, the paper's unit (Sec. V-D): bytes of
+  value        refactoring throughput, the paper's unit (Sec. IV-D): bytes of
                field decomposed plus bytes recomposed per second,
                2 * n * sizeof(dtype) / (t_decompose + t_recompose), in GB/s;
   roofline     the dominant kernel's algorithmic bytes per launch / its mean
@@ -30,6 +30,27 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2105_12764_amd", "csrc", "mgr_kernels.hip")
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from a committed rocprofv3 PMC summary
+    (profiles/*.md, a line '<!-- traffic: {json} -->'), or None when there is
+    none or the kernel source changed since the counters were taken."""
+    import glob
+    import hashlib
+    import json as _json
+
+    sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    for path in sorted(glob.glob(os.path.join(PROFILES, "*.md"))):
+        for line in open(path):
+            line = line.strip()
+            if line.startswith("<!-- traffic:") and line.endswith("-->"):
+                rec = _json.loads(line[len("<!-- traffic:"):-3])
+                if rec.get("kernel") == kernel and rec.get("source_sha256") == sha:
+                    return rec["bytes_per_launch"]
+    return None
 METRIC = "decompose+recompose GB/s at 513^3 FP64/FP32 (% HBM peak); batched p50/p99 ms"
 
 
@@ -129,7 +150,8 @@ def run_gpu(name: str, steps: int, warmup: int, graph_steps: int = 0):
     dom_name, (dom_n, dom_ms, dom_b) = max(totals.items(), key=lambda kv: kv[1][1])
     achieved = dom_b / (dom_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom_name,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom_name),
+                "kernel": dom_name,
                 "alg_bytes_per_launch": dom_b / dom_n, "mean_launch_us": dom_ms * 1e3 / dom_n}
     res = {
         "workload": name, "shape": list(shape), "dtype": np.dtype(dtype).name, "nlevels": nlev,

@@ -124,7 +124,7 @@ void mgr_release_caches(void);
 /* Streaming copy probe: copies `bytes` bytes (a multiple of 16) from device
  * buffer src to device buffer dst with one read and one write of every
  * byte and no arithmetic -- the "achievable single-pass" bandwidth probe the
- * paper divides by to place its throughput (Sec. V-D), and a kernel of known
+ * paper divides by to place its throughput (Sec. IV-D), and a kernel of known
  * traffic for calibrating hardware byte counters.  Buffers must not
  * overlap; MGR_ERR_INVALID_ARG otherwise.  Enqueued on `stream`. */
 mgr_status mgr_probe_copy(const void *src, void *dst, size_t bytes, void *stream);

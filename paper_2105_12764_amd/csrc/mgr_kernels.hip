@@ -56,7 +56,7 @@ __device__ __forceinline__ int64_t moff(const Map3 &m, int64_t i, int64_t j, int
 }
 
 // Linear interpolation between a (left) and b (right) with the weight r of
-// the right node, in the paper's FMA form (Sec. III-E, Table II).
+// the right node, in the paper's FMA form (Sec. III-E, Table III).
 __device__ __forceinline__ double lerp(double a, double b, double r) { return fma(r, b, fma(-r, a, a)); }
 
 template <bool CO>

@@ -4,7 +4,7 @@ This module draws coordinates and fields only; it holds none of the
 refactoring arithmetic, so both the HIP library's callers and the CPU oracle's
 callers can use it without sharing method code.
 
-The paper evaluates on Gray-Scott reaction-diffusion outputs (Sec. V-A) and
+The paper evaluates on Gray-Scott reaction-diffusion outputs (Sec. IV-A) and
 notes that the running time does not depend on the values, only on the grid
 size.  Those outputs are not available, so smooth multi-frequency fields with
 a small noise floor stand in for them:
