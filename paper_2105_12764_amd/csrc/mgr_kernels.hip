@@ -348,8 +348,11 @@ __global__ void __launch_bounds__(NTHR, LV_WAVES) k_loadvec(LoadArgs<T> a) {
         const int e = tid + i * NTHR;
         const unsigned f = e < NE ? flag_of(i) : 0u;
         piNext[i] = interp2(sA, e, f);
-        // nodes coarse along dims 1 and 2 of a coarse plane belong to the next level
-        if (own_p && (f & F_OWN) && !((f & F_C1) && (f & F_C2)))
+        // Nodes coarse along dims 1 and 2 of a coarse plane belong to the next
+        // level, which writes them later.  On the finest level they are
+        // written here too (their coefficient is exactly 0): that keeps every
+        // written row whole, so no cache line of the output is stored in part.
+        if (own_p && (f & F_OWN) && (!NODAL || !((f & F_C1) && (f & F_C2))))
           a.out[oo + (NODAL ? colO[NODAL ? i : 0] : colS[i])] = (T)(sA[e] - piNext[i]);
       }
     }
@@ -553,12 +556,17 @@ __global__ void __launch_bounds__(1024) k_solve_strided(double *F, int64_t c, in
   }
 }
 
+// Threads of a row-solver workgroup at most: its LDS budget keeps blocks small
+// anyway, and the cap leaves each thread room for a whole partition in
+// registers.
+constexpr int ROWS_THR = 256;
+
 // Lines along the contiguous dim 2: a workgroup stages R consecutive rows in
 // LDS (a straight coalesced copy: consecutive rows are contiguous), thread
 // (r, p) solves partition p of row r in registers.  Persistent over blocks
 // of R rows.
 template <typename T, int S>
-__global__ void __launch_bounds__(1024) k_solve_rows(double *F, int64_t nrows, int c, int P, int R,
+__global__ void __launch_bounds__(ROWS_THR) k_solve_rows(double *F, int64_t nrows, int c, int P, int R,
                                                      int64_t c1, SolveDev tg, Epi<T> ep) {
   extern __shared__ double sm[];
   const int t = threadIdx.x, nt = blockDim.x;
@@ -622,8 +630,69 @@ __global__ void __launch_bounds__(1024) k_solve_rows(double *F, int64_t nrows, i
   }
 }
 
-// Sequential Thomas per line (lines longer than 16 partitions of 64): one
-// thread per line, elimination in place in F.
+// Lines of more than kMaxBlocks partitions of 64 (up to kLongBlocks): the
+// same partitioned solve, with each wave taking partitions w, w + LONG_WAVES,
+// ... in turn.  The interior solutions wait in F between the elimination and
+// the separator fix-up, so such a line is read and written twice.  Lanes are
+// lines: 64 adjacent lines of a strided dimension (coalesced), or 64 rows of
+// the contiguous one (each lane walks its own row).
+constexpr int LONG_WAVES = 8;
+template <typename T>
+__global__ void __launch_bounds__(64 * LONG_WAVES) k_solve_long(double *F, int64_t c, int P, int64_t nk,
+                                                                int64_t sp_, int64_t so, int64_t sk,
+                                                                int axis, int64_t c1, SolveDev tb,
+                                                                Epi<T> ep) {
+  constexpr int S = 64;
+  extern __shared__ double xs[];  // yF, yL, Fs, t: [P][64] each
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t k = (int64_t)blockIdx.x * 64 + lane;
+  const int64_t outer = blockIdx.y;
+  const bool active = k < nk;
+  const int64_t base = outer * so + (active ? k : 0) * sk;
+  double *yF = xs, *yL = xs + P * 64, *Fs = xs + 2 * P * 64, *tt = xs + 3 * P * 64;
+  for (int p = w; p < P; p += LONG_WAVES) {
+    const int64_t f = (int64_t)p * S;
+    const int nload = p < P - 1 ? S : (int)(c - f);
+    const int nint = p < P - 1 ? S - 1 : nload;
+    double x[S];
+#pragma unroll
+    for (int q = 0; q < S; ++q) x[q] = (active && q < nload) ? F[base + (f + q) * sp_] : 0.0;
+    partition_solve<S>(x, tb, f, nint);
+    yF[p * 64 + lane] = x[0];
+    yL[p * 64 + lane] = pick<S>(x, nint - 1);
+    Fs[p * 64 + lane] = x[S - 1];
+    if (active) {
+#pragma unroll
+      for (int q = 0; q < S; ++q)
+        if (q < nint) F[base + (f + q) * sp_] = x[q];
+    }
+  }
+  __syncthreads();
+  if (w == 0) separator_solve(tb, S, P, yF + lane, yL + lane, Fs + lane, tt + lane, 64);
+  __syncthreads();
+  if (!active) return;
+  for (int p = w; p < P; p += LONG_WAVES) {
+    const int64_t f = (int64_t)p * S;
+    const int nload = p < P - 1 ? S : (int)(c - f);
+    const int nint = p < P - 1 ? S - 1 : nload;
+    const double tl = p > 0 ? tt[(p - 1) * 64 + lane] : 0.0;
+    const double tr = p < P - 1 ? tt[p * 64 + lane] : 0.0;
+    for (int q = 0; q < nload; ++q) {
+      const int64_t pos = f + q;
+      const int64_t idx = base + pos * sp_;
+      const double v = q < nint ? fma(-tl, tb.Ls[pos], fma(-tr, tb.Rs[pos], F[idx])) : tr;
+      int64_t i, j, kk;
+      if (axis == 0) { i = pos; j = outer; kk = k; }
+      else if (axis == 1) { i = outer; j = pos; kk = k; }
+      else { i = k / c1; j = k % c1; kk = pos; }
+      epi_store(ep, F, idx, i, j, kk, v);
+    }
+  }
+}
+
+// Sequential Thomas per line (lines longer than kLongBlocks partitions of
+// 64): one thread per line, elimination in place in F.
 template <typename T>
 __global__ void k_solve_seq(double *F, int64_t nlines, int64_t c, int axis, int64_t c1, int64_t c2,
                             SolveDev tb, Epi<T> ep) {
@@ -881,6 +950,277 @@ __global__ void __launch_bounds__(256) k_copy_probe(const uint4 *__restrict__ sr
   for (; i < n; i += stride) dst[i] = src[i];
 }
 
+// ------------------------------------------------------------ tail kernels
+//
+// The coarsest levels hold a few thousand nodes; one launch per operator
+// there costs more than the work.  One workgroup of TAIL_THR threads runs all
+// of them from LDS in a single launch per direction, with the same operators
+// as the grid-wide kernels: coefficients (value minus multilinear
+// interpolant), the load vector f = (P^T M) U per coarsened dimension from
+// the plan's taps, and each coarse line solved with whole-line Thomas factors
+// by one thread.  Every table of the tail levels is copied into LDS first, so
+// that the serial chain of phases waits on LDS, not on global memory.  Three
+// LDS grids of kTailNodes doubles rotate between the roles of level grid,
+// tap-pass input and output.
+
+constexpr int TAIL_THR = 1024;
+constexpr int TAIL_PER = (kTailNodes + TAIL_THR - 1) / TAIL_THR;  // grid nodes per thread
+
+struct TailArgs {
+  const TailLevel *lv;   // [nt + 1] descriptors, level tail_start first
+  const int64_t *off;    // packed nodal offsets
+  const double *dbl;     // packed FP64 tables
+  int noff, ndbl, nt;
+};
+
+// LDS of a tail kernel: three level grids and the packed tables.
+struct TailSmem {
+  double g[3 * kTailNodes];
+  double d[kTailDoubles];
+  int64_t o[kTailOffsets];
+};
+
+__device__ __forceinline__ void tail_split(int t, int e1, int e2, int &i, int &j, int &k) {
+  k = t % e2;
+  const int r = t / e2;
+  j = r % e1;
+  i = r / e1;
+}
+
+__device__ __forceinline__ void tail_load_tables(TailSmem &sm, const TailArgs &a) {
+  for (int t = threadIdx.x; t < a.ndbl; t += TAIL_THR) sm.d[t] = a.dbl[t];
+  for (int t = threadIdx.x; t < a.noff; t += TAIL_THR) sm.o[t] = a.off[t];
+}
+
+// y = (P^T M) x along `axis` of an (e0, e1, e2) grid; y has extent c there.
+__device__ __forceinline__ void tail_taps(const double *x, double *y, const int e[3], int axis, int c,
+                                          const double *W) {
+  int oe[3] = {e[0], e[1], e[2]};
+  oe[axis] = c;
+  const int n = oe[0] * oe[1] * oe[2];
+  const int m = e[axis];
+  const int st = axis == 0 ? e[1] * e[2] : (axis == 1 ? e[2] : 1);
+  for (int t = threadIdx.x; t < n; t += TAIL_THR) {
+    int i, j, k;
+    tail_split(t, oe[1], oe[2], i, j, k);
+    const int J = axis == 0 ? i : (axis == 1 ? j : k);
+    if (axis == 0) i = 0;
+    else if (axis == 1) j = 0;
+    else k = 0;
+    const int base = (i * e[1] + j) * e[2] + k;
+    double acc = 0.0;
+#pragma unroll
+    for (int o = 0; o < kTaps; ++o) {
+      const int q = 2 * J - 2 + o;
+      if (q >= 0 && q < m) acc = fma(W[J * kTaps + o], x[base + q * st], acc);
+    }
+    y[t] = acc;
+  }
+}
+
+// Solves M z = f along `axis` of the (c0, c1, c2) grid F in place.
+__device__ __forceinline__ void tail_solve(double *F, const int ce[3], int axis, const double *sup,
+                                           const double *tw, const double *tinvb) {
+  const int c = ce[axis];
+  const int nlines = ce[0] * ce[1] * ce[2] / c;
+  const int st = axis == 0 ? ce[1] * ce[2] : (axis == 1 ? ce[2] : 1);
+  for (int t = threadIdx.x; t < nlines; t += TAIL_THR) {
+    int base;
+    if (axis == 0) base = t;
+    else if (axis == 1) base = (t / ce[2]) * ce[1] * ce[2] + t % ce[2];
+    else base = t * ce[2];
+    double prev = F[base];
+    for (int q = 1; q < c; ++q) {
+      prev = fma(-tw[q], prev, F[base + q * st]);
+      F[base + q * st] = prev;
+    }
+    double x = prev * tinvb[c - 1];
+    F[base + (c - 1) * st] = x;
+    for (int q = c - 2; q >= 0; --q) {
+      x = fma(-sup[q], x, F[base + q * st]) * tinvb[q];
+      F[base + q * st] = x;
+    }
+  }
+}
+
+// Load vector of the level grid x (extents L.m) along every coarsened
+// dimension, then the correction solves; returns the buffer (y0 or y1) that
+// holds the result (extents L.c).
+__device__ __forceinline__ double *tail_project(const TailLevel &L, const double *sd, const double *x,
+                                                double *y0, double *y1) {
+  int e[3] = {L.m[0], L.m[1], L.m[2]};
+  const double *cur = x;
+  double *nxt = y0, *oth = y1;
+  for (int ax = 2; ax >= 0; --ax) {
+    if (!L.co[ax]) continue;
+    tail_taps(cur, nxt, e, ax, L.c[ax], sd + L.W[ax]);
+    __syncthreads();
+    e[ax] = L.c[ax];
+    cur = nxt;
+    nxt = oth;
+    oth = (double *)cur;
+  }
+  double *F = (double *)cur;
+  for (int ax = 0; ax < kDims; ++ax) {
+    if (!L.co[ax]) continue;
+    tail_solve(F, L.c, ax, sd + L.sup[ax], sd + L.tw[ax], sd + L.tinvb[ax]);
+    __syncthreads();
+  }
+  return F;
+}
+
+__device__ __forceinline__ bool tail_coarse_all(const TailLevel &L, int i, int j, int k) {
+  auto cp = [](int g, int m, int co) { return !co || g % 2 == 0 || g == m - 1; };
+  return cp(i, L.m[0], L.co[0]) && cp(j, L.m[1], L.co[1]) && cp(k, L.m[2], L.co[2]);
+}
+
+// Neighbours and right weight of level position g along one dimension, for
+// the interpolant of the coarse values: in the level grid itself (dec) or in
+// the compact coarse grid (rec).
+template <bool COMPACT>
+__device__ __forceinline__ void tail_nb(int g, int m, int c, int co, const double *r, int &lo, int &hi,
+                                        double &w) {
+  const bool fine = co && (g % 2 == 1) && (g != m - 1);
+  w = fine ? r[g] : 0.0;
+  if (!COMPACT) {
+    lo = fine ? g - 1 : g;
+    hi = fine ? g + 1 : g;
+  } else if (!co) {
+    lo = hi = g;
+  } else {
+    lo = fine ? (g - 1) / 2 : (g == m - 1 ? c - 1 : g / 2);
+    hi = fine ? (g + 1) / 2 : lo;
+  }
+}
+
+// Multilinear interpolant at (i, j, k) from the grid G (row extents g1, g2):
+// dims interpolated 2, then 1, then 0.
+template <bool COMPACT>
+__device__ __forceinline__ double tail_interp(const TailLevel &L, const double *sd, const double *G, int i,
+                                              int j, int k) {
+  int lo[3], hi[3];
+  double w[3];
+  tail_nb<COMPACT>(i, L.m[0], L.c[0], L.co[0], sd + L.r[0], lo[0], hi[0], w[0]);
+  tail_nb<COMPACT>(j, L.m[1], L.c[1], L.co[1], sd + L.r[1], lo[1], hi[1], w[1]);
+  tail_nb<COMPACT>(k, L.m[2], L.c[2], L.co[2], sd + L.r[2], lo[2], hi[2], w[2]);
+  const int g1 = COMPACT ? L.c[1] : L.m[1], g2 = COMPACT ? L.c[2] : L.m[2];
+  auto at = [&](int a, int b, int c) { return G[(a * g1 + b) * g2 + c]; };
+  auto row = [&](int a, int b) { return lerp(at(a, b, lo[2]), at(a, b, hi[2]), w[2]); };
+  auto pl = [&](int a) { return lerp(row(a, lo[1]), row(a, hi[1]), w[1]); };
+  return lerp(pl(lo[0]), pl(hi[0]), w[0]);
+}
+
+__device__ __forceinline__ int64_t tail_off(const TailLevel &L, const int64_t *so, int i, int j, int k) {
+  return so[L.nodal[0] + i] + so[L.nodal[1] + j] + so[L.nodal[2] + k];
+}
+
+// Decomposition of levels tail_start .. nlev-1.  src: level grid of the first
+// tail level, compact; out: the caller's output array (nodal positions).
+template <typename T>
+__global__ void __launch_bounds__(TAIL_THR) k_tail_dec(const T *__restrict__ src, T *__restrict__ out,
+                                                       TailArgs a) {
+  __shared__ TailSmem sm;
+  auto buf = [&](int b) { return sm.g + b * kTailNodes; };
+  tail_load_tables(sm, a);
+  {
+    const TailLevel L = a.lv[0];
+    const int n = L.m[0] * L.m[1] * L.m[2];
+    for (int t = threadIdx.x; t < n; t += TAIL_THR) sm.g[t] = (double)src[t];
+  }
+  __syncthreads();
+  int ia = 0;  // buffer holding the level grid
+  for (int s = 0; s < a.nt; ++s) {
+    const TailLevel L = a.lv[s];
+    const double *U = buf(ia);
+    const int n = L.m[0] * L.m[1] * L.m[2];
+    // coefficients of this level
+    for (int t = threadIdx.x; t < n; t += TAIL_THR) {
+      int i, j, k;
+      tail_split(t, L.m[1], L.m[2], i, j, k);
+      if (tail_coarse_all(L, i, j, k)) continue;
+      out[tail_off(L, sm.o, i, j, k)] = (T)(U[t] - tail_interp<false>(L, sm.d, U, i, j, k));
+    }
+    // corrected coarse values U_c + z: the next level grid
+    const double *F = tail_project(L, sm.d, U, buf((ia + 1) % 3), buf((ia + 2) % 3));
+    ia = (F == buf(0)) ? 0 : (F == buf(1) ? 1 : 2);
+  }
+  // coarsest values to their nodal positions
+  const TailLevel Lc = a.lv[a.nt];
+  const int n = Lc.m[0] * Lc.m[1] * Lc.m[2];
+  const double *V = buf(ia);
+  for (int t = threadIdx.x; t < n; t += TAIL_THR) {
+    int i, j, k;
+    tail_split(t, Lc.m[1], Lc.m[2], i, j, k);
+    out[tail_off(Lc, sm.o, i, j, k)] = (T)V[t];
+  }
+}
+
+// Recomposition of levels nlev-1 .. tail_start.  in: the caller's input
+// (nodal positions); dst: level grid of the first tail level, compact.
+template <typename T>
+__global__ void __launch_bounds__(TAIL_THR) k_tail_rec(const T *__restrict__ in, T *__restrict__ dst,
+                                                       TailArgs a) {
+  __shared__ TailSmem sm;
+  auto buf = [&](int b) { return sm.g + b * kTailNodes; };
+  tail_load_tables(sm, a);
+  __syncthreads();
+  {
+    const TailLevel Lc = a.lv[a.nt];
+    const int n = Lc.m[0] * Lc.m[1] * Lc.m[2];
+    for (int t = threadIdx.x; t < n; t += TAIL_THR) {
+      int i, j, k;
+      tail_split(t, Lc.m[1], Lc.m[2], i, j, k);
+      sm.g[t] = (double)in[tail_off(Lc, sm.o, i, j, k)];
+    }
+  }
+  int ia = 0;  // buffer holding the coarse values of the current step
+  for (int s = a.nt - 1; s >= 0; --s) {
+    const TailLevel L = a.lv[s];
+    const int n = L.m[0] * L.m[1] * L.m[2];
+    // this level's coefficients (zero at the coarse nodes), all loads in flight at once
+    double cf[TAIL_PER];
+#pragma unroll
+    for (int u = 0; u < TAIL_PER; ++u) {
+      const int t = threadIdx.x + u * TAIL_THR;
+      cf[u] = 0.0;
+      if (t < n) {
+        int i, j, k;
+        tail_split(t, L.m[1], L.m[2], i, j, k);
+        if (!tail_coarse_all(L, i, j, k)) cf[u] = (double)in[tail_off(L, sm.o, i, j, k)];
+      }
+    }
+    double *Cb = buf((ia + 1) % 3);
+#pragma unroll
+    for (int u = 0; u < TAIL_PER; ++u) {
+      const int t = threadIdx.x + u * TAIL_THR;
+      if (t < n) Cb[t] = cf[u];
+    }
+    __syncthreads();
+    const double *F = tail_project(L, sm.d, Cb, buf((ia + 2) % 3), Cb);
+    // coarse values before the correction: V - z
+    double *V = buf(ia);
+    const int nc = L.c[0] * L.c[1] * L.c[2];
+    for (int t = threadIdx.x; t < nc; t += TAIL_THR) V[t] -= F[t];
+    __syncthreads();
+    // level grid: coefficient plus interpolant of the coarse values
+    const int ig = (F == buf((ia + 1) % 3)) ? (ia + 2) % 3 : (ia + 1) % 3;
+    double *G = buf(ig);
+#pragma unroll
+    for (int u = 0; u < TAIL_PER; ++u) {
+      const int t = threadIdx.x + u * TAIL_THR;
+      if (t < n) {
+        int i, j, k;
+        tail_split(t, L.m[1], L.m[2], i, j, k);
+        const double v = cf[u] + tail_interp<true>(L, sm.d, V, i, j, k);
+        if (s == 0) dst[t] = (T)v;
+        else G[t] = v;
+      }
+    }
+    __syncthreads();
+    ia = ig;
+  }
+}
+
 // ------------------------------------------------------------ host launch
 
 struct Ctx {
@@ -905,8 +1245,56 @@ int64_t grid_1d(int64_t n, int64_t per) {
   return std::min<int64_t>(std::max<int64_t>(g, 1), 1 << 20);
 }
 
+// Compute units of the current device.
+int device_cus() {
+  static int ncu = 0;
+  if (ncu == 0) {
+    int dev = 0, v = 0;
+    ncu = (hipGetDevice(&dev) == hipSuccess &&
+           hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+              ? v
+              : 256;
+  }
+  return ncu;
+}
+
+// Workgroups of `kernel` (NTHR threads, static LDS) resident on the device at once.
+int resident_slots(const void *kernel) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, NTHR, 0) != hipSuccess || nb < 1) {
+    (void)hipGetLastError();
+    nb = 1;
+  }
+  return nb * device_cus();
+}
+
+// Coarse planes per workgroup (TI) for a plane-marching kernel over `tiles`
+// tile columns: each chunk of TI planes re-reads `halo` planes, and the
+// workgroups run in rounds of `slots` resident ones, so the cost is
+// rounds x (TI + halo) plane steps.  The cheapest TI <= maxTI wins; ties go to
+// the larger TI (fewer re-read planes).
+int64_t pick_chunk(int64_t c0, int64_t tiles, int64_t slots, int halo, int64_t maxTI) {
+  int64_t best = 1;
+  double best_cost = 1e300;
+  for (int64_t TI = 1; TI <= std::min(c0, maxTI); ++TI) {
+    const int64_t nwg = tiles * ((c0 + TI - 1) / TI);
+    const double cost = (double)((nwg + slots - 1) / slots) * (double)(TI + halo);
+    if (cost <= best_cost) {
+      best_cost = cost;
+      best = TI;
+    }
+  }
+  return best;
+}
+
 template <typename T, bool DEC, bool NODAL, bool C0, bool C1, bool C2>
-void launch_loadvec_t(const LoadArgs<T> &a, dim3 grid, Ctx &cx) {
+void launch_loadvec_t(LoadArgs<T> a, Ctx &cx) {
+  static const int slots = resident_slots((const void *)k_loadvec<T, DEC, NODAL, C0, C1, C2>);
+  const int64_t tiles = (int64_t)a.gx * a.gy;
+  // chunks short enough for the kernel's LDS plane window (2 TI + 3 planes)
+  a.TI = pick_chunk(a.c0, tiles, slots, C0 ? 2 : 0, (LV_MAXP - 3) / 2);
+  a.gz = (int)((a.c0 + a.TI - 1) / a.TI);
+  const dim3 grid((unsigned)(tiles * a.gz));
   double bytes = 0.0;
   if (timing_enabled()) {
     const double nl = (double)a.m0 * a.m1 * a.m2, nc = (double)a.c0 * a.c1 * a.c2;
@@ -935,39 +1323,32 @@ void launch_loadvec(const Level &L, LoadArgs<T> a, Ctx &cx) {
   a.c0 = L.c[0]; a.c1 = L.c[1]; a.c2 = L.c[2];
   a.r0 = L.d[0].r; a.r1 = L.d[1].r; a.r2 = L.d[2].r;
   a.W0 = L.d[0].W; a.W1 = L.d[1].W; a.W2 = L.d[2].W;
-  const int64_t gx = (a.c2 + TK - 1) / TK, gy = (a.c1 + TJ - 1) / TJ;
-  // enough workgroups to fill 256 CUs several times over; chunks of dim 0
-  const int64_t want = std::max<int64_t>(1, (2048 + gx * gy - 1) / (gx * gy));
-  // chunks short enough for the kernel's LDS plane window (2 TI + 3 planes)
-  int64_t TI = std::min<int64_t>(std::max<int64_t>(1, (a.c0 + want - 1) / want), (LV_MAXP - 3) / 2);
-  a.TI = TI;
-  const int64_t gz = (a.c0 + TI - 1) / TI;
-  a.gx = (int)gx; a.gy = (int)gy; a.gz = (int)gz;
-  dim3 grid((unsigned)(gx * gy * gz));
+  a.gx = (int)((a.c2 + TK - 1) / TK);
+  a.gy = (int)((a.c1 + TJ - 1) / TJ);
   const int key = (L.co[0] ? 4 : 0) | (L.co[1] ? 2 : 0) | (L.co[2] ? 1 : 0);
   // on coarser levels the field-side array (decompose: out; recompose: src)
   // goes through the nodal tables
   if (DEC ? a.omap.t0 != nullptr : a.smap.t0 != nullptr) {
     switch (key) {
-      case 0: launch_loadvec_t<T, DEC, true, false, false, false>(a, grid, cx); break;
-      case 1: launch_loadvec_t<T, DEC, true, false, false, true>(a, grid, cx); break;
-      case 2: launch_loadvec_t<T, DEC, true, false, true, false>(a, grid, cx); break;
-      case 3: launch_loadvec_t<T, DEC, true, false, true, true>(a, grid, cx); break;
-      case 4: launch_loadvec_t<T, DEC, true, true, false, false>(a, grid, cx); break;
-      case 5: launch_loadvec_t<T, DEC, true, true, false, true>(a, grid, cx); break;
-      case 6: launch_loadvec_t<T, DEC, true, true, true, false>(a, grid, cx); break;
-      default: launch_loadvec_t<T, DEC, true, true, true, true>(a, grid, cx); break;
+      case 0: launch_loadvec_t<T, DEC, true, false, false, false>(a, cx); break;
+      case 1: launch_loadvec_t<T, DEC, true, false, false, true>(a, cx); break;
+      case 2: launch_loadvec_t<T, DEC, true, false, true, false>(a, cx); break;
+      case 3: launch_loadvec_t<T, DEC, true, false, true, true>(a, cx); break;
+      case 4: launch_loadvec_t<T, DEC, true, true, false, false>(a, cx); break;
+      case 5: launch_loadvec_t<T, DEC, true, true, false, true>(a, cx); break;
+      case 6: launch_loadvec_t<T, DEC, true, true, true, false>(a, cx); break;
+      default: launch_loadvec_t<T, DEC, true, true, true, true>(a, cx); break;
     }
   } else {
     switch (key) {
-      case 0: launch_loadvec_t<T, DEC, false, false, false, false>(a, grid, cx); break;
-      case 1: launch_loadvec_t<T, DEC, false, false, false, true>(a, grid, cx); break;
-      case 2: launch_loadvec_t<T, DEC, false, false, true, false>(a, grid, cx); break;
-      case 3: launch_loadvec_t<T, DEC, false, false, true, true>(a, grid, cx); break;
-      case 4: launch_loadvec_t<T, DEC, false, true, false, false>(a, grid, cx); break;
-      case 5: launch_loadvec_t<T, DEC, false, true, false, true>(a, grid, cx); break;
-      case 6: launch_loadvec_t<T, DEC, false, true, true, false>(a, grid, cx); break;
-      default: launch_loadvec_t<T, DEC, false, true, true, true>(a, grid, cx); break;
+      case 0: launch_loadvec_t<T, DEC, false, false, false, false>(a, cx); break;
+      case 1: launch_loadvec_t<T, DEC, false, false, false, true>(a, cx); break;
+      case 2: launch_loadvec_t<T, DEC, false, false, true, false>(a, cx); break;
+      case 3: launch_loadvec_t<T, DEC, false, false, true, true>(a, cx); break;
+      case 4: launch_loadvec_t<T, DEC, false, true, false, false>(a, cx); break;
+      case 5: launch_loadvec_t<T, DEC, false, true, false, true>(a, cx); break;
+      case 6: launch_loadvec_t<T, DEC, false, true, true, false>(a, cx); break;
+      default: launch_loadvec_t<T, DEC, false, true, true, true>(a, cx); break;
     }
   }
   cx.check("k_loadvec launch");
@@ -975,15 +1356,7 @@ void launch_loadvec(const Level &L, LoadArgs<T> a, Ctx &cx) {
 
 // Persistent grid size: enough workgroups to fill the device a few times.
 int64_t persistent_grid(int64_t nblocks) {
-  static int ncu = 0;
-  if (ncu == 0) {
-    int dev = 0, v = 0;
-    ncu = (hipGetDevice(&dev) == hipSuccess &&
-           hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
-              ? v
-              : 256;
-  }
-  return std::max<int64_t>(1, std::min<int64_t>(nblocks, 4 * (int64_t)ncu));
+  return std::max<int64_t>(1, std::min<int64_t>(nblocks, 4 * (int64_t)device_cus()));
 }
 
 template <typename T, int S>
@@ -1007,7 +1380,7 @@ void launch_rows_s(double *F, const Level &L, const Epi<T> &ep, Ctx &cx) {
   const DimTabs &d = L.d[2];
   const int64_t c = L.c[2], nrows = L.c[0] * L.c[1];
   const int budget = 64 * 1024 / (int)sizeof(double) - tables_size((int)c, d.P);
-  int R = std::min(64, 1024 / d.P);
+  int R = std::min(64, ROWS_THR / d.P);
   R = std::min<int64_t>(R, budget / (c + 4 * d.P));
   R = std::max(R, 1);
   const size_t lds = (size_t)(tables_size((int)c, d.P) + R * c + 4 * d.P * R) * sizeof(double);
@@ -1019,9 +1392,28 @@ void launch_rows_s(double *F, const Level &L, const Epi<T> &ep, Ctx &cx) {
 }
 
 template <typename T>
+void launch_long(double *F, const Level &L, int axis, const Epi<T> &ep, Ctx &cx) {
+  const DimTabs &d = L.d[axis];
+  const int64_t c0 = L.c[0], c1 = L.c[1], c2 = L.c[2];
+  int64_t sp_, so, sk, nk, nouter;
+  if (axis == 0) { sp_ = c1 * c2; so = c2; sk = 1; nk = c2; nouter = c1; }
+  else if (axis == 1) { sp_ = c2; so = c1 * c2; sk = 1; nk = c2; nouter = c0; }
+  else { sp_ = 1; so = 0; sk = c2; nk = c0 * c1; nouter = 1; }
+  dim3 grid((unsigned)((nk + 63) / 64), (unsigned)nouter);
+  const size_t lds = (size_t)4 * d.P * 64 * sizeof(double);
+  // the interior solutions are written and re-read once more
+  TimedLaunch tl(cx.stream, std::string("k_solve_long<") + tname<T>() + ">",
+                 timing_enabled() ? solve_bytes<T>((double)c0 * c1 * c2, ep.mode) : 0.0);
+  hipLaunchKernelGGL((k_solve_long<T>), grid, dim3(64 * LONG_WAVES), lds, cx.stream, F, L.c[axis], d.P, nk,
+                     sp_, so, sk, axis, c1, solve_dev(d), ep);
+}
+
+template <typename T>
 void launch_solve(double *F, const Level &L, int axis, const Epi<T> &ep, Ctx &cx) {
   const DimTabs &d = L.d[axis];
-  if (d.S == 0) {  // the plan chose one sequential partition (tables built for it)
+  if (d.P > kMaxBlocks) {
+    launch_long<T>(F, L, axis, ep, cx);
+  } else if (d.S == 0) {  // the plan chose one sequential partition (tables built for it)
     const int64_t nlines = L.c[0] * L.c[1] * L.c[2] / L.c[axis];
     TimedLaunch tl(cx.stream, std::string("k_solve_seq<") + tname<T>() + ">",
                    timing_enabled() ? solve_bytes<T>((double)L.c[0] * L.c[1] * L.c[2], ep.mode) : 0.0);
@@ -1059,8 +1451,14 @@ void solve_all(double *F, const Level &L, const Epi<T> &last, Ctx &cx) {
 }
 
 template <typename T, bool NC, bool C0, bool C1, bool C2>
-void launch_reconstruct_t(const ReconArgs<T> &a, dim3 grid, Ctx &cx) {
-  hipLaunchKernelGGL((k_reconstruct<T, NC, C0, C1, C2>), grid, dim3(NTHR), 0, cx.stream, a);
+void launch_reconstruct_t(ReconArgs<T> a, Ctx &cx) {
+  static const int slots = resident_slots((const void *)k_reconstruct<T, NC, C0, C1, C2>);
+  const int64_t tiles = (int64_t)a.gx * a.gy;
+  // chunks short enough for the kernel's LDS plane window (2 TI + 2 planes)
+  a.TI = pick_chunk(a.c0, tiles, slots, C0 ? 1 : 0, (LV_MAXP - 2) / 2);
+  a.gz = (int)((a.c0 + a.TI - 1) / a.TI);
+  hipLaunchKernelGGL((k_reconstruct<T, NC, C0, C1, C2>), dim3((unsigned)(tiles * a.gz)), dim3(NTHR), 0,
+                     cx.stream, a);
 }
 
 template <typename T>
@@ -1070,13 +1468,8 @@ void launch_reconstruct(const Level &L, const T *coef, Map3 cmap, const T *uc, T
   a.m0 = L.m[0]; a.m1 = L.m[1]; a.m2 = L.m[2];
   a.c0 = L.c[0]; a.c1 = L.c[1]; a.c2 = L.c[2];
   a.r0 = L.d[0].r; a.r1 = L.d[1].r; a.r2 = L.d[2].r;
-  const int64_t gx = (a.c2 + TK - 1) / TK, gy = (a.c1 + TJ - 1) / TJ;
-  const int64_t want = std::max<int64_t>(1, (2048 + gx * gy - 1) / (gx * gy));
-  const int64_t TI = std::min<int64_t>(std::max<int64_t>(1, (a.c0 + want - 1) / want), (LV_MAXP - 2) / 2);
-  a.TI = TI;
-  const int64_t gz = (a.c0 + TI - 1) / TI;
-  a.gx = (int)gx; a.gy = (int)gy; a.gz = (int)gz;
-  dim3 grid((unsigned)(gx * gy * gz));
+  a.gx = (int)((a.c2 + TK - 1) / TK);
+  a.gy = (int)((a.c1 + TJ - 1) / TJ);
   const int64_t n = L.m[0] * L.m[1] * L.m[2];
   const double nl = (double)n, nc = (double)L.c[0] * L.c[1] * L.c[2];
   // read the coefficients and the coarse grid, write the level grid
@@ -1085,7 +1478,7 @@ void launch_reconstruct(const Level &L, const T *coef, Map3 cmap, const T *uc, T
                      bname(L.co[0]) + ", " + bname(L.co[1]) + ", " + bname(L.co[2]) + ">",
                  timing_enabled() ? ((nl - nc) + nc + nl) * sizeof(T) : 0.0);
   const int key = (cmap.t0 ? 8 : 0) | (L.co[0] ? 4 : 0) | (L.co[1] ? 2 : 0) | (L.co[2] ? 1 : 0);
-#define MGR_RECON(NC, C0, C1, C2) launch_reconstruct_t<T, NC, C0, C1, C2>(a, grid, cx)
+#define MGR_RECON(NC, C0, C1, C2) launch_reconstruct_t<T, NC, C0, C1, C2>(a, cx)
   switch (key) {
     case 0: MGR_RECON(false, false, false, false); break;
     case 1: MGR_RECON(false, false, false, true); break;
@@ -1106,6 +1499,25 @@ void launch_reconstruct(const Level &L, const T *coef, Map3 cmap, const T *uc, T
   }
 #undef MGR_RECON
   cx.check("k_reconstruct launch");
+}
+
+// Levels tail_start .. nlev-1 in one workgroup.  Decompose: src is the
+// compact level grid of level tail_start, dst the caller's output.
+// Recompose: src is the caller's input, dst the compact level grid.
+template <typename T, bool DEC>
+void launch_tail(const Plan &pl, const T *src, T *dst, Ctx &cx) {
+  const int nt = pl.nlev - pl.tail_start;
+  const Level &L = pl.lev[pl.tail_start];
+  const double n = (double)L.m[0] * L.m[1] * L.m[2];
+  // read the level grid (or the coefficients), write the coefficients (or the level grid)
+  TimedLaunch tl(cx.stream, std::string(DEC ? "k_tail_dec<" : "k_tail_rec<") + tname<T>() + ">",
+                 timing_enabled() ? 2.0 * n * sizeof(T) : 0.0);
+  const TailArgs ta{pl.dev_tail, pl.dev_tail_off, pl.dev_tail_dbl, pl.tail_noff, pl.tail_ndbl, nt};
+  if (DEC)
+    hipLaunchKernelGGL((k_tail_dec<T>), dim3(1), dim3(TAIL_THR), 0, cx.stream, src, dst, ta);
+  else
+    hipLaunchKernelGGL((k_tail_rec<T>), dim3(1), dim3(TAIL_THR), 0, cx.stream, src, dst, ta);
+  cx.check(DEC ? "k_tail_dec launch" : "k_tail_rec launch");
 }
 
 struct Workspace {
@@ -1134,7 +1546,8 @@ bool decompose_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t stre
   Workspace w = carve(pl, ws, sizeof(T));
   const T *src = in;
   Map3 smap = compact_map(pl.n[1], pl.n[2]);
-  for (int s = 0; s < pl.nlev && cx.ok; ++s) {
+  const int st = std::min(pl.tail_start, pl.nlev);
+  for (int s = 0; s < st && cx.ok; ++s) {
     const Level &L = pl.lev[s];
     T *next = (T *)w.buf[s % 2];
     LoadArgs<T> a{};
@@ -1157,6 +1570,7 @@ bool decompose_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t stre
     src = next;
     smap = compact_map(L.c[1], L.c[2]);
   }
+  if (st < pl.nlev && cx.ok) launch_tail<T, true>(pl, src, out, cx);
   return cx.ok;
 }
 
@@ -1172,17 +1586,23 @@ bool recompose_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t stre
     return true;
   }
   Workspace w = carve(pl, ws, sizeof(T));
-  // coarsest grid values, gathered compactly
-  const Level &Lc = pl.lev[pl.nlev];
-  T *V = (T *)w.buf[pl.nlev % 2];
-  {
+  const int st = std::min(pl.tail_start, pl.nlev);
+  T *V = nullptr;
+  if (st < pl.nlev) {
+    // the coarsest levels in one workgroup, up to the level grid of level st
+    V = (st == 0) ? out : (T *)w.buf[st % 2];
+    launch_tail<T, false>(pl, in, V, cx);
+  } else {
+    // coarsest grid values, gathered compactly
+    const Level &Lc = pl.lev[pl.nlev];
+    V = (T *)w.buf[pl.nlev % 2];
     const int64_t n = Lc.m[0] * Lc.m[1] * Lc.m[2];
     TimedLaunch tl(stream, std::string("k_gather<") + tname<T>() + ">", 2.0 * n * sizeof(T));
     hipLaunchKernelGGL((k_gather<T>), dim3((unsigned)grid_1d(n, 256)), dim3(256), 0, stream, in,
                        nodal_map(Lc), V, Lc.m[0], Lc.m[1], Lc.m[2]);
     cx.check("k_gather launch");
   }
-  for (int s = pl.nlev - 1; s >= 0 && cx.ok; --s) {
+  for (int s = st - 1; s >= 0 && cx.ok; --s) {
     const Level &L = pl.lev[s];
     const Map3 cmap = (s == 0) ? compact_map(pl.n[1], pl.n[2]) : nodal_map(L);
     LoadArgs<T> a{};

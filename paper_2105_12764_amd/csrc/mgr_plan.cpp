@@ -82,7 +82,7 @@ struct Image {
 
 struct HostDim {
   size_t nodal = 0, r = 0, W = 0, sub = 0, sup = 0, w = 0, invb = 0, Ls = 0, Rs = 0,
-         wr = 0, invbr = 0, gam = 0;
+         wr = 0, invbr = 0, gam = 0, tw = 0, tinvb = 0;
   bool has_solve = false;
 };
 
@@ -93,15 +93,17 @@ int64_t coarse_index(int64_t m, int64_t i) {
 bool is_coarse(int64_t m, int64_t i) { return m < 3 || i % 2 == 0 || i == m - 1; }
 
 // Partition length for a line of c unknowns: the smallest of 8/16/32/64 that
-// needs at most kMaxBlocks partitions; 0 selects the sequential fallback.
+// needs at most kMaxBlocks partitions, else 64 for up to kLongBlocks
+// partitions (the long-line solver); 0 selects the sequential fallback.
 int pick_partition(int64_t c) {
   for (int S : {8, 16, 32, 64})
     if ((c + S - 1) / S <= kMaxBlocks) return S;
+  if ((c + 63) / 64 <= kLongBlocks) return 64;
   return 0;
 }
 
 struct SolveTabs {
-  std::vector<double> sub, sup, w, invb, Ls, Rs, wr, invbr, gam;
+  std::vector<double> sub, sup, w, invb, Ls, Rs, wr, invbr, gam, tw, tinvb;
   int S = 0, P = 1;
 };
 
@@ -182,6 +184,16 @@ SolveTabs solve_tables(const std::vector<double> &X) {
     t.invbr.assign(1, 0.0);
     t.gam.assign(1, 0.0);
   }
+  // whole-line Thomas factors (one partition), for the single-workgroup tail
+  t.tw.assign(c, 0.0);
+  t.tinvb.assign(c, 0.0);
+  double piv = b[0];
+  t.tinvb[0] = 1.0 / piv;
+  for (int64_t i = 1; i < c; ++i) {
+    t.tw[i] = a[i] / piv;
+    piv = b[i] - t.tw[i] * e[i - 1];
+    t.tinvb[i] = 1.0 / piv;
+  }
   return t;
 }
 
@@ -208,6 +220,7 @@ std::unique_ptr<Plan> build_plan(int ndim, const int64_t n[kDims],
 
   Image img;
   std::vector<std::array<HostDim, kDims>> hd(nlev + 1);
+  size_t hd_tail[3] = {0, 0, 0};
   for (int s = 0; s <= nlev; ++s) {
     Level &L = plan->lev[s];
     for (int k = 0; k < kDims; ++k) {
@@ -282,6 +295,8 @@ std::unique_ptr<Plan> build_plan(int ndim, const int64_t n[kDims],
       h.wr = img.put(st.wr);
       h.invbr = img.put(st.invbr);
       h.gam = img.put(st.gam);
+      h.tw = img.put(st.tw);
+      h.tinvb = img.put(st.tinvb);
       L.d[k].S = st.S;
       L.d[k].P = st.P;
     }
@@ -303,6 +318,63 @@ std::unique_ptr<Plan> build_plan(int ndim, const int64_t n[kDims],
   }
   plan->max_coarse = 0;
   if (nlev > 0) plan->max_coarse = plan->lev[0].c[0] * plan->lev[0].c[1] * plan->lev[0].c[2];
+  // the tail runs the last levels whose grids and tables fit one workgroup's LDS
+  {
+    int64_t noff = 0, ndbl = 0;
+    for (int k = 0; k < kDims; ++k) noff += plan->lev[nlev].m[k];
+    plan->tail_start = nlev;
+    for (int s = nlev - 1; s >= 0 && nlev - s <= kTailMaxLevels; --s) {
+      const Level &L = plan->lev[s];
+      if (L.m[0] * L.m[1] * L.m[2] > kTailNodes || L.m[0] > kTailMaxExtent || L.m[1] > kTailMaxExtent ||
+          L.m[2] > kTailMaxExtent)
+        break;
+      for (int k = 0; k < kDims; ++k) {
+        noff += L.m[k];
+        ndbl += L.m[k] + (L.co[k] ? (kTaps + 3) * L.c[k] : 0);
+      }
+      if (noff > kTailOffsets || ndbl > kTailDoubles) break;
+      plan->tail_start = s;
+    }
+  }
+  const int ntail = nlev - plan->tail_start;
+  if (ntail > 0) {
+    // pack the tail tables from the host image
+    std::vector<TailLevel> tl((size_t)ntail + 1);
+    std::vector<int64_t> toff;
+    std::vector<double> tdbl;
+    auto copy_d = [&](size_t at, int64_t cnt) {
+      const int o = (int)tdbl.size();
+      const double *src = (const double *)(img.bytes.data() + at);
+      tdbl.insert(tdbl.end(), src, src + cnt);
+      return o;
+    };
+    for (int t = 0; t <= ntail; ++t) {
+      const int s = plan->tail_start + t;
+      const Level &L = plan->lev[s];
+      TailLevel &e = tl[t];
+      for (int k = 0; k < kDims; ++k) {
+        const HostDim &h = hd[s][k];
+        e.m[k] = (int)L.m[k];
+        e.c[k] = (int)L.c[k];
+        e.co[k] = L.co[k] ? 1 : 0;
+        e.nodal[k] = (int)toff.size();
+        const int64_t *nsrc = (const int64_t *)(img.bytes.data() + h.nodal);
+        toff.insert(toff.end(), nsrc, nsrc + L.m[k]);
+        if (t == ntail) continue;
+        e.r[k] = copy_d(h.r, L.m[k]);
+        if (!L.co[k]) continue;
+        e.W[k] = copy_d(h.W, (int64_t)kTaps * L.c[k]);
+        e.sup[k] = copy_d(h.sup, L.c[k]);
+        e.tw[k] = copy_d(h.tw, L.c[k]);
+        e.tinvb[k] = copy_d(h.tinvb, L.c[k]);
+      }
+    }
+    plan->tail_noff = (int)toff.size();
+    plan->tail_ndbl = (int)tdbl.size();
+    hd_tail[0] = img.put(tl);
+    hd_tail[1] = img.put(toff);
+    hd_tail[2] = img.put(tdbl);
+  }
 
   // upload
   (void)hipGetDevice(&plan->device);
@@ -312,12 +384,6 @@ std::unique_ptr<Plan> build_plan(int ndim, const int64_t n[kDims],
     plan->dev_tables = nullptr;
     err = "hipMalloc of plan tables failed";
     status = 4;
-    return nullptr;
-  }
-  if (hipMemcpy(plan->dev_tables, img.bytes.data(), plan->table_bytes,
-                hipMemcpyHostToDevice) != hipSuccess) {
-    err = "upload of plan tables failed";
-    status = 5;
     return nullptr;
   }
   char *base = (char *)plan->dev_tables;
@@ -338,8 +404,21 @@ std::unique_ptr<Plan> build_plan(int ndim, const int64_t n[kDims],
         d.wr = (const double *)(base + h.wr);
         d.invbr = (const double *)(base + h.invbr);
         d.gam = (const double *)(base + h.gam);
+        d.tw = (const double *)(base + h.tw);
+        d.tinvb = (const double *)(base + h.tinvb);
       }
     }
+  if (ntail > 0) {
+    plan->dev_tail = (const TailLevel *)(base + hd_tail[0]);
+    plan->dev_tail_off = (const int64_t *)(base + hd_tail[1]);
+    plan->dev_tail_dbl = (const double *)(base + hd_tail[2]);
+  }
+  if (hipMemcpy(plan->dev_tables, img.bytes.data(), plan->table_bytes,
+                hipMemcpyHostToDevice) != hipSuccess) {
+    err = "upload of plan tables failed";
+    status = 5;
+    return nullptr;
+  }
   status = 0;
   return plan;
 }

@@ -14,6 +14,7 @@ namespace mgr {
 constexpr int kDims = 3;        // internal rank: leading dims of size 1 pad 1-D/2-D
 constexpr int kTaps = 5;        // load-vector row: fine positions 2J-2 .. 2J+2
 constexpr int kMaxBlocks = 16;  // partitions per line in the register solvers
+constexpr int kLongBlocks = 32; // partitions of 64 per line in the long-line solver
 constexpr int kMaxLevels = 62;
 
 // Device pointers of the tables of one dimension at one level.
@@ -31,6 +32,8 @@ struct DimTabs {
   const double *wr = nullptr;      // [P-1] separator-system elimination factor
   const double *invbr = nullptr;   // [P-1] 1 / separator-system pivot
   const double *gam = nullptr;     // [P-1] separator-system upper coupling
+  const double *tw = nullptr;      // [c] whole-line Thomas elimination factor
+  const double *tinvb = nullptr;   // [c] whole-line Thomas 1 / pivot
   int S = 0;                       // partition length (0: sequential fallback)
   int P = 1;                       // partitions per line
 };
@@ -42,6 +45,25 @@ struct Level {
   DimTabs d[kDims];
 };
 
+// Levels small enough to run entirely in one workgroup's LDS (k_tail_dec,
+// k_tail_rec): at most kTailNodes nodes and kTailMaxExtent per dimension (the
+// tail solves each line with one thread), with all their tables in at most
+// kTailDoubles FP64 words and kTailOffsets nodal offsets.
+constexpr int kTailNodes = 17 * 17 * 17;
+constexpr int kTailMaxExtent = 65;
+constexpr int kTailMaxLevels = 16;
+constexpr int kTailDoubles = 3072;
+constexpr int kTailOffsets = 1024;
+
+// Descriptor of one tail level: extents and the word offsets of its tables
+// in the packed tail tables (nodal: into the offset table; the rest: into the
+// FP64 table).  Tables of a dimension that is not coarsened are absent except
+// nodal and r (all zero).
+struct TailLevel {
+  int m[kDims], c[kDims], co[kDims];
+  int nodal[kDims], r[kDims], W[kDims], sup[kDims], tw[kDims], tinvb[kDims];
+};
+
 struct Plan {
   int ndim = 0;                 // caller's rank
   int64_t n[kDims];             // finest shape, padded to rank 3
@@ -51,6 +73,11 @@ struct Plan {
   void *dev_tables = nullptr;   // one device allocation holding every table
   size_t table_bytes = 0;
   int64_t max_coarse = 0;       // elements of the largest coarse grid (level 1)
+  int tail_start = 0;           // first level run by the single-workgroup tail kernels
+  const TailLevel *dev_tail = nullptr;  // [nlev - tail_start + 1], inside dev_tables
+  const int64_t *dev_tail_off = nullptr;  // packed nodal offsets of the tail levels
+  const double *dev_tail_dbl = nullptr;   // packed FP64 tables of the tail levels
+  int tail_noff = 0, tail_ndbl = 0;
   ~Plan();
 };
 

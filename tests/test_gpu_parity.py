@@ -83,8 +83,12 @@ SMALL = [
     ((300, 41), None, True, np.float64),
     ((1000,), None, True, np.float64),          # 1-D
     ((65,), 3, False, np.float64),
-    ((5000,), 4, True, np.float64),             # line > 1024: sequential solver
-    ((3000, 40), 2, True, np.float64),          # strided line > 1024
+    ((5000,), 4, True, np.float64),             # line > 2048 unknowns: sequential solver
+    ((3000, 40), 2, True, np.float64),          # strided line of 1501: long-line solver
+    ((40, 3000), 2, True, np.float64),          # row of 1501: long-line solver
+    ((2049, 9), 1, False, np.float64),          # 1025 unknowns: 17 partitions of 64
+    ((2100,), 2, True, np.float32),             # 1-D long line, FP32
+    ((2500, 3, 4), 2, True, np.float64),        # long dim-0 lines in 3-D
     ((1500, 30), 2, True, np.float64),          # 64-partition strided solve
     ((30, 1500), 2, True, np.float64),          # 64-partition row solve
     ((129, 129, 129), None, True, np.float64),
