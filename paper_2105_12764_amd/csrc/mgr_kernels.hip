@@ -544,6 +544,20 @@ __global__ void __launch_bounds__(1024) k_solve_strided(double *F, int64_t c, in
     if (p < P - 1) x[S - 1] = tr;
   }
   if (!active) return;
+  if (ep.mode == EPI_SUB_COMPACT) {
+    // read the stored values eight at a time: one memory round trip per
+    // eight elements, not one per element
+#pragma unroll
+    for (int q0 = 0; q0 < S; q0 += 8) {
+      T d[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) d[u] = ep.dst[base + (f + min(q0 + u, nload - 1)) * sp_];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (q0 + u < nload) ep.dst[base + (f + q0 + u) * sp_] = (T)((double)d[u] - x[q0 + u]);
+    }
+    return;
+  }
 #pragma unroll
   for (int q = 0; q < S; ++q) {
     if (q < nload) {
@@ -621,11 +635,24 @@ __global__ void __launch_bounds__(ROWS_THR) k_solve_rows(double *F, int64_t nrow
         if (q < nload) roww[q] = x[q];
     }
     __syncthreads();
-    for (int e = t; e < n; e += nt) {
-      const unsigned rr = (unsigned)e / (unsigned)c, cc = (unsigned)e - rr * (unsigned)c;
-      const unsigned row = (unsigned)row0 + rr;
-      const unsigned i = row / (unsigned)c1, j = row - i * (unsigned)c1;
-      epi_store(ep, F, gbase + e, i, j, cc, tile[e]);
+    if (ep.mode == EPI_SUB_COMPACT) {
+      // read the stored values eight at a time: one memory round trip per
+      // eight elements, not one per element
+      for (int e = t; e < n; e += 8 * nt) {
+        T d[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) d[u] = ep.dst[gbase + min(e + u * nt, n - 1)];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (e + u * nt < n) ep.dst[gbase + e + u * nt] = (T)((double)d[u] - tile[e + u * nt]);
+      }
+    } else {
+      for (int e = t; e < n; e += nt) {
+        const unsigned rr = (unsigned)e / (unsigned)c, cc = (unsigned)e - rr * (unsigned)c;
+        const unsigned row = (unsigned)row0 + rr;
+        const unsigned i = row / (unsigned)c1, j = row - i * (unsigned)c1;
+        epi_store(ep, F, gbase + e, i, j, cc, tile[e]);
+      }
     }
   }
 }
@@ -1309,6 +1336,17 @@ void launch_loadvec_t(LoadArgs<T> a, Ctx &cx) {
   hipLaunchKernelGGL((k_loadvec<T, DEC, NODAL, C0, C1, C2>), grid, dim3(NTHR), 0, cx.stream, a);
 }
 
+// Suffix of a solve's timing label naming what its store does (the kernel
+// symbol is the same for every epilogue).
+inline const char *epi_tag(int mode) {
+  switch (mode) {
+    case EPI_STORE_COMPACT: return " [store]";
+    case EPI_STORE_NODAL: return " [nodal]";
+    case EPI_SUB_COMPACT: return " [sub]";
+    default: return "";
+  }
+}
+
 // Algorithmic bytes of one correction solve over nc unknowns.
 template <typename T>
 double solve_bytes(double nc, int mode) {
@@ -1369,7 +1407,7 @@ void launch_strided_s(double *F, const Level &L, int axis, const Epi<T> &ep, Ctx
   else { sp_ = c2; so = c1 * c2; nouter = c0; }
   dim3 grid((unsigned)((c2 + 63) / 64), (unsigned)nouter);
   const size_t lds = (size_t)4 * d.P * 64 * sizeof(double);
-  TimedLaunch tl(cx.stream, std::string("k_solve_strided<") + tname<T>() + ", " + std::to_string(S) + ">",
+  TimedLaunch tl(cx.stream, std::string("k_solve_strided<") + tname<T>() + ", " + std::to_string(S) + ">" + epi_tag(ep.mode),
                  timing_enabled() ? solve_bytes<T>((double)c0 * c1 * c2, ep.mode) : 0.0);
   hipLaunchKernelGGL((k_solve_strided<T, S>), grid, dim3(64 * d.P), lds, cx.stream, F, c, d.P, c2, sp_,
                      so, axis, c1, c2, solve_dev(d), ep);
@@ -1379,13 +1417,14 @@ template <typename T, int S>
 void launch_rows_s(double *F, const Level &L, const Epi<T> &ep, Ctx &cx) {
   const DimTabs &d = L.d[2];
   const int64_t c = L.c[2], nrows = L.c[0] * L.c[1];
-  const int budget = 64 * 1024 / (int)sizeof(double) - tables_size((int)c, d.P);
+  // about 96 KB of LDS per workgroup: larger blocks of rows measured faster
+  const int budget = 96 * 1024 / (int)sizeof(double) - tables_size((int)c, d.P);
   int R = std::min(64, ROWS_THR / d.P);
   R = std::min<int64_t>(R, budget / (c + 4 * d.P));
   R = std::max(R, 1);
   const size_t lds = (size_t)(tables_size((int)c, d.P) + R * c + 4 * d.P * R) * sizeof(double);
   dim3 grid((unsigned)persistent_grid((nrows + R - 1) / R));
-  TimedLaunch tl(cx.stream, std::string("k_solve_rows<") + tname<T>() + ", " + std::to_string(S) + ">",
+  TimedLaunch tl(cx.stream, std::string("k_solve_rows<") + tname<T>() + ", " + std::to_string(S) + ">" + epi_tag(ep.mode),
                  timing_enabled() ? solve_bytes<T>((double)nrows * c, ep.mode) : 0.0);
   hipLaunchKernelGGL((k_solve_rows<T, S>), grid, dim3(R * d.P), lds, cx.stream, F, nrows, (int)c, d.P,
                      R, L.c[1], solve_dev(d), ep);
@@ -1402,7 +1441,7 @@ void launch_long(double *F, const Level &L, int axis, const Epi<T> &ep, Ctx &cx)
   dim3 grid((unsigned)((nk + 63) / 64), (unsigned)nouter);
   const size_t lds = (size_t)4 * d.P * 64 * sizeof(double);
   // the interior solutions are written and re-read once more
-  TimedLaunch tl(cx.stream, std::string("k_solve_long<") + tname<T>() + ">",
+  TimedLaunch tl(cx.stream, std::string("k_solve_long<") + tname<T>() + ">" + epi_tag(ep.mode),
                  timing_enabled() ? solve_bytes<T>((double)c0 * c1 * c2, ep.mode) : 0.0);
   hipLaunchKernelGGL((k_solve_long<T>), grid, dim3(64 * LONG_WAVES), lds, cx.stream, F, L.c[axis], d.P, nk,
                      sp_, so, sk, axis, c1, solve_dev(d), ep);
@@ -1415,7 +1454,7 @@ void launch_solve(double *F, const Level &L, int axis, const Epi<T> &ep, Ctx &cx
     launch_long<T>(F, L, axis, ep, cx);
   } else if (d.S == 0) {  // the plan chose one sequential partition (tables built for it)
     const int64_t nlines = L.c[0] * L.c[1] * L.c[2] / L.c[axis];
-    TimedLaunch tl(cx.stream, std::string("k_solve_seq<") + tname<T>() + ">",
+    TimedLaunch tl(cx.stream, std::string("k_solve_seq<") + tname<T>() + ">" + epi_tag(ep.mode),
                    timing_enabled() ? solve_bytes<T>((double)L.c[0] * L.c[1] * L.c[2], ep.mode) : 0.0);
     hipLaunchKernelGGL((k_solve_seq<T>), dim3((unsigned)grid_1d(nlines, 64)), dim3(64), 0, cx.stream, F,
                        nlines, L.c[axis], axis, L.c[1], L.c[2], solve_dev(d), ep);

@@ -77,6 +77,8 @@ SMALL = [
     ((66, 70, 130), 4, True, np.float64),       # several tiles, ragged tails
     ((9, 130, 70), 3, False, np.float64),
     ((200, 3, 2), None, True, np.float64),      # tiny and never-coarsened dims
+    ((129, 150, 2), 3, True, np.float64),       # last coarsened dim strided: subtracting epilogue
+    ((40, 150, 2), 2, True, np.float32),
     ((3, 3, 3), 1, False, np.float64),
     ((2, 2, 2), 0, False, np.float64),          # nlevels = 0: copy
     ((129, 257), None, False, np.float64),      # 2-D
