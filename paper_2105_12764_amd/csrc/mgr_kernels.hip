@@ -395,10 +395,10 @@ __global__ void __launch_bounds__(NTHR, LV_WAVES) k_loadvec(LoadArgs<T> a) {
 // ------------------------------------------------------------ correction solves
 
 struct SolveDev {
-  const double *sub, *sup, *w, *invb, *Ls, *Rs, *wr, *invbr, *gam;
+  const double *sup, *w, *invb, *supi, *Ls, *Rs, *sepa, *sepe, *wr, *invbr, *gam;
 };
 SolveDev solve_dev(const DimTabs &d) {
-  return SolveDev{d.sub, d.sup, d.w, d.invb, d.Ls, d.Rs, d.wr, d.invbr, d.gam};
+  return SolveDev{d.sup, d.w, d.invb, d.supi, d.Ls, d.Rs, d.sepa, d.sepe, d.wr, d.invbr, d.gam};
 }
 
 // What the last solve of a step does with its solution z when it stores it:
@@ -427,20 +427,28 @@ __device__ __forceinline__ void epi_store(const Epi<T> &e, double *F, int64_t id
 }
 
 // Interior solve of one partition held in x[0..S): forward elimination and
-// back substitution with the block factors; positions f .. f+nint-1.
+// back substitution with the block factors of positions f .. f+S-1.  The
+// tables are padded so that the separator slot and the slots past the end
+// of the line pass through unchanged: the loop is straight-line code whose
+// table reads do not depend on the data, so they can all be in flight
+// before the dependent chain needs them.
 template <int S>
-__device__ __forceinline__ void partition_solve(double (&x)[S], const SolveDev &tb, int64_t f, int nint) {
+__device__ __forceinline__ void partition_solve(double (&x)[S], const SolveDev &tb, int64_t f) {
 #pragma unroll
-  for (int q = 1; q < S; ++q)
-    if (q < nint) x[q] = fma(-tb.w[f + q], x[q - 1], x[q]);
+  for (int q = 1; q < S; ++q) x[q] = fma(-tb.w[f + q], x[q - 1], x[q]);
+  x[S - 1] *= tb.invb[f + S - 1];
 #pragma unroll
-  for (int q = S - 1; q >= 0; --q) {
-    if (q == nint - 1) {
-      x[q] *= tb.invb[f + q];
-    } else if (q < nint - 1) {
-      x[q] = fma(-tb.sup[f + q], x[q + 1], x[q]) * tb.invb[f + q];
-    }
-  }
+  for (int q = S - 2; q >= 0; --q) x[q] = fma(-tb.supi[f + q], x[q + 1], x[q]) * tb.invb[f + q];
+}
+
+// Separator fix-up of a partition: x -= t_left Ls + t_right Rs (zero at the
+// separator and padding slots), then the separator slot takes its value.
+template <int S>
+__device__ __forceinline__ void partition_fixup(double (&x)[S], const SolveDev &tb, int64_t f, double tl,
+                                                double tr, bool has_sep) {
+#pragma unroll
+  for (int q = 0; q < S; ++q) x[q] = fma(-tl, tb.Ls[f + q], fma(-tr, tb.Rs[f + q], x[q]));
+  if (has_sep) x[S - 1] = tr;
 }
 
 template <int S>
@@ -459,8 +467,7 @@ __device__ __forceinline__ void separator_solve(const SolveDev &tb, int S, int P
                                                 int ld) {
   double g = 0.0;
   for (int sp = 0; sp < P - 1; ++sp) {
-    const int64_t s = (int64_t)(sp + 1) * S - 1;
-    double rhs = Fs[sp * ld] - tb.sub[s] * yL[sp * ld] - tb.sup[s] * yF[(sp + 1) * ld];
+    double rhs = Fs[sp * ld] - tb.sepa[sp] * yL[sp * ld] - tb.sepe[sp] * yF[(sp + 1) * ld];
     g = fma(-tb.wr[sp], g, rhs);
     t[sp * ld] = g;
   }
@@ -471,44 +478,47 @@ __device__ __forceinline__ void separator_solve(const SolveDev &tb, int S, int P
   }
 }
 
-// Copies a line's solve tables into LDS -- w, invb, sup, sub, Ls, Rs [c]
-// each, then wr, invbr, gam [P] -- with eight loads in flight per thread, and
-// returns LDS-backed accessors.  Used by the row solver, whose lanes work on
+// Copies a line's solve tables into LDS -- w, invb, supi, Ls, Rs [cp = P*S]
+// each, then sepa, sepe, wr, invbr, gam [P] -- with eight loads in flight
+// per thread, and returns LDS-backed accessors.  Used by the row solver, whose lanes work on
 // different partitions: it is persistent, so a workgroup stages the tables
 // once and then walks many blocks of rows, and table reads inside the
 // sequential solve chain cost an LDS access instead of a round trip to
 // memory.  (In the strided solver a wave shares one partition, and its
 // table reads are scalar-cache loads.)
-__device__ __forceinline__ SolveDev stage_tables(double *tab, const SolveDev &tg, int c, int P, int t,
+__device__ __forceinline__ SolveDev stage_tables(double *tab, const SolveDev &tg, int cp, int P, int t,
                                                  int nt) {
-  const double *src[6] = {tg.w, tg.invb, tg.sup, tg.sub, tg.Ls, tg.Rs};
-  const int n = 6 * c;
+  const double *src[5] = {tg.w, tg.invb, tg.supi, tg.Ls, tg.Rs};
+  const int n = 5 * cp;
   for (int e = t; e < n; e += 8 * nt) {
     double v[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int q = min(e + u * nt, n - 1);
-      v[u] = src[q / c][q % c];
+      v[u] = src[q / cp][q % cp];
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u)
       if (e + u * nt < n) tab[e + u * nt] = v[u];
   }
   for (int q = t; q < P - 1; q += nt) {
-    tab[n + q] = tg.wr[q];
-    tab[n + P + q] = tg.invbr[q];
-    tab[n + 2 * P + q] = tg.gam[q];
+    tab[n + q] = tg.sepa[q];
+    tab[n + P + q] = tg.sepe[q];
+    tab[n + 2 * P + q] = tg.wr[q];
+    tab[n + 3 * P + q] = tg.invbr[q];
+    tab[n + 4 * P + q] = tg.gam[q];
   }
-  return SolveDev{tab + 3 * c, tab + 2 * c, tab, tab + c, tab + 4 * c, tab + 5 * c,
-                  tab + n, tab + n + P, tab + n + 2 * P};
+  return SolveDev{nullptr, tab, tab + cp, tab + 2 * cp, tab + 3 * cp, tab + 4 * cp,
+                  tab + n, tab + n + P, tab + n + 2 * P, tab + n + 3 * P, tab + n + 4 * P};
 }
-__host__ __device__ constexpr int tables_size(int c, int P) { return 6 * c + 3 * P; }
+__host__ __device__ constexpr int tables_size(int cp, int P) { return 5 * cp + 5 * P; }
 
 // Lines along dim 0 or 1: lane = position along the contiguous dim 2,
 // wave = partition.  Element q of partition p of line (outer, k) sits at
 // F[outer * so + k + (p*S + q) * sp].
+// (five waves per SIMD keep two 9-wave workgroups resident per CU at S = 32)
 template <typename T, int S>
-__global__ void __launch_bounds__(1024) k_solve_strided(double *F, int64_t c, int P, int64_t nk,
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5))) k_solve_strided(double *F, int64_t c, int P, int64_t nk,
                                                         int64_t sp_, int64_t so, int axis,
                                                         int64_t c1, int64_t c2, SolveDev tb,
                                                         Epi<T> ep) {
@@ -526,7 +536,7 @@ __global__ void __launch_bounds__(1024) k_solve_strided(double *F, int64_t c, in
   double x[S];
 #pragma unroll
   for (int q = 0; q < S; ++q) x[q] = (active && q < nload) ? F[base + (f + q) * sp_] : 0.0;
-  partition_solve<S>(x, tb, f, nint);
+  partition_solve<S>(x, tb, f);
 
   double *yF = xs, *yL = xs + P * 64, *Fs = xs + 2 * P * 64, *tt = xs + 3 * P * 64;
   if (P > 1) {
@@ -538,10 +548,7 @@ __global__ void __launch_bounds__(1024) k_solve_strided(double *F, int64_t c, in
     __syncthreads();
     const double tl = p > 0 ? tt[(p - 1) * 64 + lane] : 0.0;
     const double tr = p < P - 1 ? tt[p * 64 + lane] : 0.0;
-#pragma unroll
-    for (int q = 0; q < S; ++q)
-      if (q < nint) x[q] = fma(-tl, tb.Ls[f + q], fma(-tr, tb.Rs[f + q], x[q]));
-    if (p < P - 1) x[S - 1] = tr;
+    partition_fixup<S>(x, tb, f, tl, tr, p < P - 1);
   }
   if (!active) return;
   if (ep.mode == EPI_SUB_COMPACT) {
@@ -584,8 +591,8 @@ __global__ void __launch_bounds__(ROWS_THR) k_solve_rows(double *F, int64_t nrow
                                                      int64_t c1, SolveDev tg, Epi<T> ep) {
   extern __shared__ double sm[];
   const int t = threadIdx.x, nt = blockDim.x;
-  const SolveDev tb = stage_tables(sm, tg, c, P, t, nt);
-  double *tile = sm + tables_size(c, P);  // [R][c]
+  const SolveDev tb = stage_tables(sm, tg, P * S, P, t, nt);
+  double *tile = sm + tables_size(P * S, P);  // [R][c]
   double *ex = tile + (size_t)R * c;       // separator exchange [4][P][R]
   double *yF = ex, *yL = ex + P * R, *Fs = ex + 2 * P * R, *tt = ex + 3 * P * R;
   const int r = t % R, p = t / R;
@@ -613,7 +620,7 @@ __global__ void __launch_bounds__(ROWS_THR) k_solve_rows(double *F, int64_t nrow
     const double *rowp = tile + r * c + f;
 #pragma unroll
     for (int q = 0; q < S; ++q) x[q] = (active && q < nload) ? rowp[q] : 0.0;
-    partition_solve<S>(x, tb, f, nint);
+    partition_solve<S>(x, tb, f);
     if (P > 1) {
       yF[p * R + r] = x[0];
       yL[p * R + r] = pick<S>(x, nint - 1);
@@ -623,10 +630,7 @@ __global__ void __launch_bounds__(ROWS_THR) k_solve_rows(double *F, int64_t nrow
       __syncthreads();
       const double tl = p > 0 ? tt[(p - 1) * R + r] : 0.0;
       const double tr = p < P - 1 ? tt[p * R + r] : 0.0;
-#pragma unroll
-      for (int q = 0; q < S; ++q)
-        if (q < nint) x[q] = fma(-tl, tb.Ls[f + q], fma(-tr, tb.Rs[f + q], x[q]));
-      if (p < P - 1) x[S - 1] = tr;
+      partition_fixup<S>(x, tb, f, tl, tr, p < P - 1);
     }
     if (active) {
       double *roww = tile + r * c + f;
@@ -685,7 +689,7 @@ __global__ void __launch_bounds__(64 * LONG_WAVES) k_solve_long(double *F, int64
     double x[S];
 #pragma unroll
     for (int q = 0; q < S; ++q) x[q] = (active && q < nload) ? F[base + (f + q) * sp_] : 0.0;
-    partition_solve<S>(x, tb, f, nint);
+    partition_solve<S>(x, tb, f);
     yF[p * 64 + lane] = x[0];
     yL[p * 64 + lane] = pick<S>(x, nint - 1);
     Fs[p * 64 + lane] = x[S - 1];
@@ -1418,11 +1422,11 @@ void launch_rows_s(double *F, const Level &L, const Epi<T> &ep, Ctx &cx) {
   const DimTabs &d = L.d[2];
   const int64_t c = L.c[2], nrows = L.c[0] * L.c[1];
   // about 96 KB of LDS per workgroup: larger blocks of rows measured faster
-  const int budget = 96 * 1024 / (int)sizeof(double) - tables_size((int)c, d.P);
+  const int budget = 96 * 1024 / (int)sizeof(double) - tables_size(d.P * S, d.P);
   int R = std::min(64, ROWS_THR / d.P);
   R = std::min<int64_t>(R, budget / (c + 4 * d.P));
   R = std::max(R, 1);
-  const size_t lds = (size_t)(tables_size((int)c, d.P) + R * c + 4 * d.P * R) * sizeof(double);
+  const size_t lds = (size_t)(tables_size(d.P * S, d.P) + R * c + 4 * d.P * R) * sizeof(double);
   dim3 grid((unsigned)persistent_grid((nrows + R - 1) / R));
   TimedLaunch tl(cx.stream, std::string("k_solve_rows<") + tname<T>() + ", " + std::to_string(S) + ">" + epi_tag(ep.mode),
                  timing_enabled() ? solve_bytes<T>((double)nrows * c, ep.mode) : 0.0);

@@ -31,6 +31,7 @@
 
 #include <hip/hip_runtime_api.h>
 
+#include <algorithm>
 #include <array>
 #include <cmath>
 #include <cstring>
@@ -81,8 +82,8 @@ struct Image {
 };
 
 struct HostDim {
-  size_t nodal = 0, r = 0, W = 0, sub = 0, sup = 0, w = 0, invb = 0, Ls = 0, Rs = 0,
-         wr = 0, invbr = 0, gam = 0, tw = 0, tinvb = 0;
+  size_t nodal = 0, r = 0, W = 0, sub = 0, sup = 0, w = 0, invb = 0, supi = 0, Ls = 0, Rs = 0,
+         sepa = 0, sepe = 0, wr = 0, invbr = 0, gam = 0, tw = 0, tinvb = 0;
   bool has_solve = false;
 };
 
@@ -103,7 +104,7 @@ int pick_partition(int64_t c) {
 }
 
 struct SolveTabs {
-  std::vector<double> sub, sup, w, invb, Ls, Rs, wr, invbr, gam, tw, tinvb;
+  std::vector<double> sub, sup, w, invb, supi, Ls, Rs, sepa, sepe, wr, invbr, gam, tw, tinvb;
   int S = 0, P = 1;
 };
 
@@ -124,10 +125,13 @@ SolveTabs solve_tables(const std::vector<double> &X) {
   }
   t.sub = a;
   t.sup = e;
-  t.w.assign(c, 0.0);
-  t.invb.assign(c, 0.0);
-  t.Ls.assign(c, 0.0);
-  t.Rs.assign(c, 0.0);
+  // partition tables padded to P*S; separator and padding slots pass through
+  const int64_t cp = (int64_t)P * S;
+  t.w.assign(cp, 0.0);
+  t.invb.assign(cp, 1.0);
+  t.supi.assign(cp, 0.0);
+  t.Ls.assign(cp, 0.0);
+  t.Rs.assign(cp, 0.0);
   // interior [f, l] of partition p
   auto first = [&](int p) { return (int64_t)p * S; };
   auto last = [&](int p) { return p < P - 1 ? (int64_t)(p + 1) * S - 2 : c - 1; };
@@ -141,6 +145,7 @@ SolveTabs solve_tables(const std::vector<double> &X) {
       piv = b[i] - t.w[i] * e[i - 1];
       t.invb[i] = 1.0 / piv;
     }
+    for (int64_t i = f; i < l; ++i) t.supi[i] = e[i];
     // interior solve with the tables, as the kernels do it
     auto interior_solve = [&](std::vector<double> &d) {
       for (int64_t i = f + 1; i <= l; ++i) d[i] -= t.w[i] * d[i - 1];
@@ -161,10 +166,14 @@ SolveTabs solve_tables(const std::vector<double> &X) {
     }
   }
   // separator system
+  t.sepa.assign(std::max(P - 1, 1), 0.0);
+  t.sepe.assign(std::max(P - 1, 1), 0.0);
   if (P > 1) {
     std::vector<double> al(P - 1), be(P - 1), ga(P - 1);
     for (int p = 0; p < P - 1; ++p) {
       int64_t s = last(p) + 1;
+      t.sepa[p] = a[s];
+      t.sepe[p] = e[s];
       al[p] = -a[s] * t.Ls[s - 1];
       be[p] = b[s] - a[s] * t.Rs[s - 1] - e[s] * t.Ls[s + 1];
       ga[p] = -e[s] * t.Rs[s + 1];
@@ -290,6 +299,9 @@ std::unique_ptr<Plan> build_plan(int ndim, const int64_t n[kDims],
       h.sup = img.put(st.sup);
       h.w = img.put(st.w);
       h.invb = img.put(st.invb);
+      h.supi = img.put(st.supi);
+      h.sepa = img.put(st.sepa);
+      h.sepe = img.put(st.sepe);
       h.Ls = img.put(st.Ls);
       h.Rs = img.put(st.Rs);
       h.wr = img.put(st.wr);
@@ -399,6 +411,9 @@ std::unique_ptr<Plan> build_plan(int ndim, const int64_t n[kDims],
         d.sup = (const double *)(base + h.sup);
         d.w = (const double *)(base + h.w);
         d.invb = (const double *)(base + h.invb);
+        d.supi = (const double *)(base + h.supi);
+        d.sepa = (const double *)(base + h.sepa);
+        d.sepe = (const double *)(base + h.sepe);
         d.Ls = (const double *)(base + h.Ls);
         d.Rs = (const double *)(base + h.Rs);
         d.wr = (const double *)(base + h.wr);

@@ -25,10 +25,16 @@ struct DimTabs {
   // coarse mass-matrix solve, over coarse positions [c]
   const double *sub = nullptr;     // a_i  (coupling to i-1)
   const double *sup = nullptr;     // e_i  (coupling to i+1)
+  // Partition tables, [P*S] (padded past c).  Separator and padding slots
+  // hold w = 0, supi = 0, invb = 1, Ls = Rs = 0, so a branch-free interior
+  // solve over all S slots of a partition leaves them unchanged.
   const double *w = nullptr;       // block-local elimination factor
   const double *invb = nullptr;    // 1 / block-local pivot
+  const double *supi = nullptr;    // e_i inside a block (0 at its last interior position)
   const double *Ls = nullptr;      // response of a block to its left separator
   const double *Rs = nullptr;      // response of a block to its right separator
+  const double *sepa = nullptr;    // [P-1] a_s at the separators
+  const double *sepe = nullptr;    // [P-1] e_s at the separators
   const double *wr = nullptr;      // [P-1] separator-system elimination factor
   const double *invbr = nullptr;   // [P-1] 1 / separator-system pivot
   const double *gam = nullptr;     // [P-1] separator-system upper coupling
