@@ -756,13 +756,19 @@ __global__ void k_solve_seq(double *F, int64_t nlines, int64_t c, int axis, int6
 
 // Recomposition of one level: every node of the level grid gets its stored
 // coefficient plus the multilinear interpolant of the coarse values
-// (U_c = stored coarse grid - z).  A workgroup owns a (2TJ x 2TK) tile of
-// fine nodes in dims (1, 2) and a chunk of coarse planes along dim 0, and
-// walks plane pairs like k_loadvec: the coarse values of the tile (with a
-// one-node halo) are staged in LDS per coarse plane, the interpolant of each
-// owned node stays in registers for the fine plane after it, and the next
-// pair's coefficients and coarse values are prefetched into registers.  Each
-// coefficient is read once and each output written once.
+// (U_c = stored coarse grid - z).  A workgroup owns a tile of fine nodes in
+// dims (1, 2) -- whole rows wherever they fit, so that each workgroup streams
+// long contiguous row segments and no cache line is split between two
+// workgroups except at a segment's ends -- and a chunk of coarse planes
+// along dim 0.  It walks plane pairs like k_loadvec: the coarse values of the
+// tile (with a one-node halo) are staged in LDS per coarse plane, the
+// interpolant of each owned node stays in registers for the fine plane after
+// it, and the next pair's coefficients and coarse values are prefetched into
+// registers.  Each coefficient is read once and each output written once.
+constexpr int RC_EPT = 5;  // fine nodes per thread per plane
+constexpr int RC_EPC = 3;  // staged coarse nodes per thread
+constexpr int RC_NE = RC_EPT * NTHR, RC_NC = RC_EPC * NTHR;
+
 template <typename T>
 struct ReconArgs {
   const T *coef;  // stored coefficients (level grid positions)
@@ -772,20 +778,21 @@ struct ReconArgs {
   int64_t m0, m1, m2, c0, c1, c2;
   const double *r0, *r1, *r2;
   int64_t TI;
+  int TJ, TK;     // coarse rows / columns of a tile
   int gx, gy, gz;
 };
 
 template <typename T, bool NODALC, bool CO0, bool CO1, bool CO2>
 __global__ void __launch_bounds__(NTHR) k_reconstruct(ReconArgs<T> a) {
   constexpr int SJ = CO1 ? 2 : 1, SK = CO2 ? 2 : 1;
-  constexpr int FJ = SJ * TJ, FK = SK * TK;  // owned fine tile
-  constexpr int NE = FJ * FK;
-  constexpr int EPT = (NE + NTHR - 1) / NTHR;
-  constexpr int CJ = TJ + (CO1 ? 1 : 0), CK = TK + (CO2 ? 1 : 0);  // coarse tile with halo
-  constexpr int NC = CJ * CK;
-  constexpr int EPC = (NC + NTHR - 1) / NTHR;
-  __shared__ double sU[2][NC];  // coarse values of the current / previous coarse plane
-  __shared__ double sR1[FJ], sR2[FK];
+  const int FJ = SJ * a.TJ, FK = SK * a.TK;  // owned fine tile (host: FJ * FK <= RC_NE)
+  const int NE = FJ * FK;
+  const int CK = a.TK + (CO2 ? 1 : 0);       // coarse tile with halo (host: CJ * CK <= RC_NC)
+  const int NC = (a.TJ + (CO1 ? 1 : 0)) * CK;
+  __shared__ double sU[2][RC_NC];  // coarse values of the current / previous coarse plane
+  // interpolation weights of the tile's rows, then of its columns (FJ + FK <= RC_NE + 1)
+  __shared__ double sR[RC_NE + 1];
+  double *sR1 = sR, *sR2 = sR + FJ;
   // tables read inside the plane loop come from LDS or are loaded one step
   // ahead with the prefetch (see k_loadvec)
   __shared__ int64_t sPO[NODALC ? LV_MAXP : 1];  // nodal plane offsets of the coefficients
@@ -794,25 +801,26 @@ __global__ void __launch_bounds__(NTHR) k_reconstruct(ReconArgs<T> a) {
   const int tid = threadIdx.x;
   const int tile = xcd_tile(blockIdx.x, a.gx * a.gy * a.gz);
   const int tx = tile % a.gx, ty = (tile / a.gx) % a.gy, tz = tile / (a.gx * a.gy);
-  const int64_t J0 = (int64_t)ty * TJ, K0 = (int64_t)tx * TK;
+  const int64_t J0 = (int64_t)ty * a.TJ, K0 = (int64_t)tx * a.TK;
   const int64_t I0 = (int64_t)tz * a.TI;
   const int64_t I1 = min(I0 + a.TI, a.c0);
-  const bool lastJ = J0 + TJ >= a.c1, lastK = K0 + TK >= a.c2, lastI = I1 >= a.c0;
-  const int64_t fj0 = SJ * J0, fje = lastJ ? a.m1 : SJ * (J0 + TJ);
-  const int64_t fk0 = SK * K0, fke = lastK ? a.m2 : SK * (K0 + TK);
+  const bool lastJ = J0 + a.TJ >= a.c1, lastK = K0 + a.TK >= a.c2, lastI = I1 >= a.c0;
+  const int64_t fj0 = SJ * J0, fje = lastJ ? a.m1 : SJ * (J0 + a.TJ);
+  const int64_t fk0 = SK * K0, fke = lastK ? a.m2 : SK * (K0 + a.TK);
   const int64_t oib = (CO0 ? 2 : 1) * I0, oie = lastI ? a.m0 : (CO0 ? 2 : 1) * I1;
 
   enum : unsigned { F_IN = 1, F_C1 = 2, F_C2 = 4 };
   unsigned flags = 0;
-  int colC[EPT], colD[EPT];
-  int lo[EPT];  // coarse-tile index of the lower corner
+  int colC[RC_EPT], colD[RC_EPT];
+  int lo[RC_EPT];  // coarse-tile index of the lower corner
+  int jk[RC_EPT];  // tile row << 16 | tile column
 #pragma unroll
-  for (int i = 0; i < EPT; ++i) {
+  for (int i = 0; i < RC_EPT; ++i) {
     const int e = tid + i * NTHR;
     const int j = e / FK, k = e % FK;
     const int64_t gj = fj0 + j, gk = fk0 + k;
     unsigned f = 0;
-    colC[i] = colD[i] = lo[i] = 0;
+    colC[i] = colD[i] = lo[i] = jk[i] = 0;
     if (e < NE && gj < fje && gk < fke) {
       f |= F_IN;
       const bool c1 = coarse_pos<CO1>(gj, a.m1), c2 = coarse_pos<CO2>(gk, a.m2);
@@ -823,6 +831,7 @@ __global__ void __launch_bounds__(NTHR) k_reconstruct(ReconArgs<T> a) {
       lo[i] = (int)((a1 - J0) * CK + (a2 - K0));
       colC[i] = (int)(NODALC ? a.cmap.t1[gj] + a.cmap.t2[gk] : gj * a.m2 + gk);
       colD[i] = (int)(gj * a.m2 + gk);
+      jk[i] = (j << 16) | k;
     }
     flags |= f << (3 * i);
   }
@@ -837,9 +846,9 @@ __global__ void __launch_bounds__(NTHR) k_reconstruct(ReconArgs<T> a) {
   }
 
   // coarse-tile elements this thread stages
-  int ucol[EPC];
+  int ucol[RC_EPC];
 #pragma unroll
-  for (int i = 0; i < EPC; ++i) {
+  for (int i = 0; i < RC_EPC; ++i) {
     const int e = tid + i * NTHR;
     const int64_t J = J0 + e / CK, K = K0 + e % CK;
     ucol[i] = (e < NC && J < a.c1 && K < a.c2) ? (int)(J * a.c2 + K) : -1;
@@ -850,15 +859,15 @@ __global__ void __launch_bounds__(NTHR) k_reconstruct(ReconArgs<T> a) {
   __syncthreads();
 
   // branch-free loads (invalid elements read a valid node and are never used)
-  auto fetchC = [&](double (&v)[EPT], int64_t p) {
+  auto fetchC = [&](double (&v)[RC_EPT], int64_t p) {
     const T *base = a.coef + (NODALC ? sPO[p - pw0] : p * a.m1 * a.m2);
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) v[i] = (double)base[colC[i]];
+    for (int i = 0; i < RC_EPT; ++i) v[i] = (double)base[colC[i]];
   };
-  auto fetchU = [&](double (&v)[EPC], int64_t cp) {
+  auto fetchU = [&](double (&v)[RC_EPC], int64_t cp) {
     const T *base = a.uc + cp * a.c1 * a.c2;
 #pragma unroll
-    for (int i = 0; i < EPC; ++i) v[i] = (double)base[ucol[i] >= 0 ? ucol[i] : 0];
+    for (int i = 0; i < RC_EPC; ++i) v[i] = (double)base[ucol[i] >= 0 ? ucol[i] : 0];
   };
   double kv = 0.0;  // dim-0 weight of the fine plane of a step (thread 0), loaded a step ahead
   auto fetch_r0 = [&](int64_t pa) { kv = a.r0 ? a.r0[pa >= 0 ? pa : 0] : 0.0; };
@@ -866,14 +875,13 @@ __global__ void __launch_bounds__(NTHR) k_reconstruct(ReconArgs<T> a) {
   auto interp2 = [&](const double *s, int i) -> double {
     const unsigned f = flag_of(i);
     if (!(f & F_IN)) return 0.0;
-    const int e = tid + i * NTHR;
     const int l = lo[i];
     const bool c1 = f & F_C1, c2 = f & F_C2;
     if (c1 && c2) return s[l];
-    if (c1) return lerp(s[l], s[l + 1], sR2[e % FK]);
-    if (c2) return lerp(s[l], s[l + CK], sR1[e / FK]);
-    const double rk = sR2[e % FK];
-    return lerp(lerp(s[l], s[l + 1], rk), lerp(s[l + CK], s[l + CK + 1], rk), sR1[e / FK]);
+    const double rk = sR2[jk[i] & 0xffff], rj = sR1[jk[i] >> 16];
+    if (c1) return lerp(s[l], s[l + 1], rk);
+    if (c2) return lerp(s[l], s[l + CK], rj);
+    return lerp(lerp(s[l], s[l + 1], rk), lerp(s[l + CK], s[l + CK + 1], rk), rj);
   };
 
   // steps: with dim 0 coarsened, step I covers (a = 2I+1, b = 2I+2) for I in
@@ -889,10 +897,10 @@ __global__ void __launch_bounds__(NTHR) k_reconstruct(ReconArgs<T> a) {
     if (pa >= 0 && pb < 0) { pb = pa; pa = -1; }  // last plane of an even extent is coarse
   };
 
-  double ca[EPT], cb[EPT], uv[EPC];
-  double piPrev[EPT], piNext[EPT];
+  double ca[RC_EPT], cb[RC_EPT], uv[RC_EPC];
+  double piPrev[RC_EPT], piNext[RC_EPT];
 #pragma unroll
-  for (int i = 0; i < EPT; ++i) piPrev[i] = piNext[i] = 0.0;
+  for (int i = 0; i < RC_EPT; ++i) piPrev[i] = piNext[i] = 0.0;
   {
     int64_t pa, pb;
     planes(sbeg, pa, pb);
@@ -907,15 +915,15 @@ __global__ void __launch_bounds__(NTHR) k_reconstruct(ReconArgs<T> a) {
     double *s = sU[buf];
     if (pb >= 0) {
 #pragma unroll
-      for (int i = 0; i < EPC; ++i) {
+      for (int i = 0; i < RC_EPC; ++i) {
         const int e = tid + i * NTHR;
         if (e < NC) s[e] = ucol[i] >= 0 ? uv[i] : 0.0;
       }
     }
     if (tid == 0) sR0[buf] = kv;
-    double xb[EPT], xa[EPT];
+    double xb[RC_EPT], xa[RC_EPT];
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) {
+    for (int i = 0; i < RC_EPT; ++i) {
       xb[i] = cb[i];
       xa[i] = ca[i];
     }
@@ -931,7 +939,7 @@ __global__ void __launch_bounds__(NTHR) k_reconstruct(ReconArgs<T> a) {
       const bool own_p = pb >= oib && pb < oie;
       const int64_t po = pb * a.m1 * a.m2;
 #pragma unroll
-      for (int i = 0; i < EPT; ++i) {
+      for (int i = 0; i < RC_EPT; ++i) {
         piNext[i] = interp2(s, i);
         const unsigned f = flag_of(i);
         if (own_p && (f & F_IN)) {
@@ -944,12 +952,12 @@ __global__ void __launch_bounds__(NTHR) k_reconstruct(ReconArgs<T> a) {
       const bool own_p = pa >= oib && pa < oie;
       const int64_t po = pa * a.m1 * a.m2;
 #pragma unroll
-      for (int i = 0; i < EPT; ++i)
+      for (int i = 0; i < RC_EPT; ++i)
         if (own_p && (flag_of(i) & F_IN))
           a.dst[po + colD[i]] = (T)(xa[i] + lerp(piPrev[i], piNext[i], sR0[buf]));
     }
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) piPrev[i] = piNext[i];
+    for (int i = 0; i < RC_EPT; ++i) piPrev[i] = piNext[i];
     buf ^= 1;
   }
 }
@@ -1511,8 +1519,23 @@ void launch_reconstruct(const Level &L, const T *coef, Map3 cmap, const T *uc, T
   a.m0 = L.m[0]; a.m1 = L.m[1]; a.m2 = L.m[2];
   a.c0 = L.c[0]; a.c1 = L.c[1]; a.c2 = L.c[2];
   a.r0 = L.d[0].r; a.r1 = L.d[1].r; a.r2 = L.d[2].r;
-  a.gx = (int)((a.c2 + TK - 1) / TK);
-  a.gy = (int)((a.c1 + TJ - 1) / TJ);
+  // Tile: whole rows where a row fits (FK = SK * TK fine columns, at most
+  // half the per-thread slots), then as many coarse rows as the slots allow.
+  {
+    const int SJ = L.co[1] ? 2 : 1, SK = L.co[2] ? 2 : 1;
+    const int HJ = L.co[1] ? 1 : 0, HK = L.co[2] ? 1 : 0;
+    int64_t TKc = a.c2;
+    auto fits = [&](int64_t tj, int64_t tk) {
+      return SJ * tj * SK * tk <= RC_NE && (tj + HJ) * (tk + HK) <= RC_NC;
+    };
+    while (TKc > 1 && !fits(1, TKc)) TKc = (TKc + 1) / 2;
+    int64_t TJc = 1;
+    while (TJc < a.c1 && fits(TJc + 1, TKc)) ++TJc;
+    a.TK = (int)TKc;
+    a.TJ = (int)TJc;
+  }
+  a.gx = (int)((a.c2 + a.TK - 1) / a.TK);
+  a.gy = (int)((a.c1 + a.TJ - 1) / a.TJ);
   const int64_t n = L.m[0] * L.m[1] * L.m[2];
   const double nl = (double)n, nc = (double)L.c[0] * L.c[1] * L.c[2];
   // read the coefficients and the coarse grid, write the level grid
