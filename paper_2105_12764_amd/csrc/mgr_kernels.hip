@@ -70,7 +70,7 @@ __device__ __forceinline__ int64_t coarse_idx(int64_t g, int64_t m, int64_t c) {
 
 // ------------------------------------------------------- load-vector kernel
 
-constexpr int TJ = 8;        // coarse rows (dim 1) per tile
+constexpr int TJ = 16;       // coarse rows (dim 1) per tile
 constexpr int TK = 32;       // coarse columns (dim 2) per tile
 constexpr int NTHR = TJ * TK;
 #define LV_WAVES (DEC ? 1 : 5)
@@ -765,9 +765,10 @@ __global__ void k_solve_seq(double *F, int64_t nlines, int64_t c, int axis, int6
 // interpolant of each owned node stays in registers for the fine plane after
 // it, and the next pair's coefficients and coarse values are prefetched into
 // registers.  Each coefficient is read once and each output written once.
-constexpr int RC_EPT = 5;  // fine nodes per thread per plane
+constexpr int RC_THR = 256;  // threads of a reconstruct workgroup
+constexpr int RC_EPT = 5;    // fine nodes per thread per plane
 constexpr int RC_EPC = 3;  // staged coarse nodes per thread
-constexpr int RC_NE = RC_EPT * NTHR, RC_NC = RC_EPC * NTHR;
+constexpr int RC_NE = RC_EPT * RC_THR, RC_NC = RC_EPC * RC_THR;
 
 template <typename T>
 struct ReconArgs {
@@ -783,7 +784,7 @@ struct ReconArgs {
 };
 
 template <typename T, bool NODALC, bool CO0, bool CO1, bool CO2>
-__global__ void __launch_bounds__(NTHR) k_reconstruct(ReconArgs<T> a) {
+__global__ void __launch_bounds__(RC_THR) k_reconstruct(ReconArgs<T> a) {
   constexpr int SJ = CO1 ? 2 : 1, SK = CO2 ? 2 : 1;
   const int FJ = SJ * a.TJ, FK = SK * a.TK;  // owned fine tile (host: FJ * FK <= RC_NE)
   const int NE = FJ * FK;
@@ -816,7 +817,7 @@ __global__ void __launch_bounds__(NTHR) k_reconstruct(ReconArgs<T> a) {
   int jk[RC_EPT];  // tile row << 16 | tile column
 #pragma unroll
   for (int i = 0; i < RC_EPT; ++i) {
-    const int e = tid + i * NTHR;
+    const int e = tid + i * RC_THR;
     const int j = e / FK, k = e % FK;
     const int64_t gj = fj0 + j, gk = fk0 + k;
     unsigned f = 0;
@@ -836,11 +837,11 @@ __global__ void __launch_bounds__(NTHR) k_reconstruct(ReconArgs<T> a) {
     flags |= f << (3 * i);
   }
   auto flag_of = [&](int i) -> unsigned { return (flags >> (3 * i)) & 7u; };
-  for (int j = tid; j < FJ; j += NTHR) {
+  for (int j = tid; j < FJ; j += RC_THR) {
     const int64_t gj = fj0 + j;
     sR1[j] = (CO1 && gj < a.m1 && !coarse_pos<CO1>(gj, a.m1)) ? a.r1[gj] : 0.0;
   }
-  for (int k = tid; k < FK; k += NTHR) {
+  for (int k = tid; k < FK; k += RC_THR) {
     const int64_t gk = fk0 + k;
     sR2[k] = (CO2 && gk < a.m2 && !coarse_pos<CO2>(gk, a.m2)) ? a.r2[gk] : 0.0;
   }
@@ -849,13 +850,13 @@ __global__ void __launch_bounds__(NTHR) k_reconstruct(ReconArgs<T> a) {
   int ucol[RC_EPC];
 #pragma unroll
   for (int i = 0; i < RC_EPC; ++i) {
-    const int e = tid + i * NTHR;
+    const int e = tid + i * RC_THR;
     const int64_t J = J0 + e / CK, K = K0 + e % CK;
     ucol[i] = (e < NC && J < a.c1 && K < a.c2) ? (int)(J * a.c2 + K) : -1;
   }
   const int64_t pw0 = CO0 ? max<int64_t>(0, 2 * I0 - 1) : I0;  // plane window (host: 2 TI + 2 <= LV_MAXP)
   if (NODALC)
-    for (int q = tid; q < LV_MAXP; q += NTHR) sPO[q] = (pw0 + q < a.m0) ? a.cmap.t0[pw0 + q] : 0;
+    for (int q = tid; q < LV_MAXP; q += RC_THR) sPO[q] = (pw0 + q < a.m0) ? a.cmap.t0[pw0 + q] : 0;
   __syncthreads();
 
   // branch-free loads (invalid elements read a valid node and are never used)
@@ -916,7 +917,7 @@ __global__ void __launch_bounds__(NTHR) k_reconstruct(ReconArgs<T> a) {
     if (pb >= 0) {
 #pragma unroll
       for (int i = 0; i < RC_EPC; ++i) {
-        const int e = tid + i * NTHR;
+        const int e = tid + i * RC_THR;
         if (e < NC) s[e] = ucol[i] >= 0 ? uv[i] : 0.0;
       }
     }
@@ -1297,10 +1298,10 @@ int device_cus() {
   return ncu;
 }
 
-// Workgroups of `kernel` (NTHR threads, static LDS) resident on the device at once.
-int resident_slots(const void *kernel) {
+// Workgroups of `kernel` (`threads` threads, static LDS) resident on the device at once.
+int resident_slots(const void *kernel, int threads) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, NTHR, 0) != hipSuccess || nb < 1) {
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, 0) != hipSuccess || nb < 1) {
     (void)hipGetLastError();
     nb = 1;
   }
@@ -1328,7 +1329,7 @@ int64_t pick_chunk(int64_t c0, int64_t tiles, int64_t slots, int halo, int64_t m
 
 template <typename T, bool DEC, bool NODAL, bool C0, bool C1, bool C2>
 void launch_loadvec_t(LoadArgs<T> a, Ctx &cx) {
-  static const int slots = resident_slots((const void *)k_loadvec<T, DEC, NODAL, C0, C1, C2>);
+  static const int slots = resident_slots((const void *)k_loadvec<T, DEC, NODAL, C0, C1, C2>, NTHR);
   const int64_t tiles = (int64_t)a.gx * a.gy;
   // chunks short enough for the kernel's LDS plane window (2 TI + 3 planes)
   a.TI = pick_chunk(a.c0, tiles, slots, C0 ? 2 : 0, (LV_MAXP - 3) / 2);
@@ -1503,12 +1504,12 @@ void solve_all(double *F, const Level &L, const Epi<T> &last, Ctx &cx) {
 
 template <typename T, bool NC, bool C0, bool C1, bool C2>
 void launch_reconstruct_t(ReconArgs<T> a, Ctx &cx) {
-  static const int slots = resident_slots((const void *)k_reconstruct<T, NC, C0, C1, C2>);
+  static const int slots = resident_slots((const void *)k_reconstruct<T, NC, C0, C1, C2>, RC_THR);
   const int64_t tiles = (int64_t)a.gx * a.gy;
   // chunks short enough for the kernel's LDS plane window (2 TI + 2 planes)
   a.TI = pick_chunk(a.c0, tiles, slots, C0 ? 1 : 0, (LV_MAXP - 2) / 2);
   a.gz = (int)((a.c0 + a.TI - 1) / a.TI);
-  hipLaunchKernelGGL((k_reconstruct<T, NC, C0, C1, C2>), dim3((unsigned)(tiles * a.gz)), dim3(NTHR), 0,
+  hipLaunchKernelGGL((k_reconstruct<T, NC, C0, C1, C2>), dim3((unsigned)(tiles * a.gz)), dim3(RC_THR), 0,
                      cx.stream, a);
 }
 
