@@ -241,12 +241,28 @@ __global__ void __launch_bounds__(NTHR, LV_WAVES) k_loadvec(LoadArgs<T> a) {
   for (int e = tid; e < TJ * 5; e += NTHR)
     sW[e] = (CO1 && J0 + e / 5 < a.c1) ? a.W1[J0 * 5 + e] : 0.0;
   __syncthreads();
-  double w1[5], w2[5];
+  // Taps of this thread's dim-2 column and dim-1 row: kept in registers, or
+  // -- for the FP32 decomposition, which is issue-bound rather than
+  // memory-bound -- read from LDS where used, which brings it under 128
+  // VGPRs and two resident workgroups per CU (measured faster there, slower
+  // for the FP64 and recomposition kernels).
+  constexpr bool kTapsInLds = DEC && sizeof(T) == 4;
+  double w1r[kTapsInLds ? 1 : 5], w2r[kTapsInLds ? 1 : 5];
+  if constexpr (!kTapsInLds) {
 #pragma unroll
-  for (int o = 0; o < 5; ++o) {
-    w2[o] = sW[TJ * 5 + rK * 5 + o];
-    w1[o] = sW[hJ * 5 + o];
+    for (int o = 0; o < 5; ++o) {
+      w2r[o] = sW[TJ * 5 + rK * 5 + o];
+      w1r[o] = sW[hJ * 5 + o];
+    }
   }
+  auto w2 = [&](int o) -> double {
+    if constexpr (kTapsInLds) return sW[TJ * 5 + rK * 5 + o];
+    else return w2r[o];
+  };
+  auto w1 = [&](int o) -> double {
+    if constexpr (kTapsInLds) return sW[hJ * 5 + o];
+    else return w1r[o];
+  };
   auto reduce2 = [&](const double *s, int off) {
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
@@ -257,7 +273,7 @@ __global__ void __launch_bounds__(NTHR, LV_WAVES) k_loadvec(LoadArgs<T> a) {
           if (CO2) {
             const double *row = s + j * NK + 2 * rK;
 #pragma unroll
-            for (int o = 0; o < 5; ++o) g = fma(w2[o], row[o], g);
+            for (int o = 0; o < 5; ++o) g = fma(w2(o), row[o], g);
           } else {
             g = s[j * NK + rK];
           }
@@ -273,7 +289,7 @@ __global__ void __launch_bounds__(NTHR, LV_WAVES) k_loadvec(LoadArgs<T> a) {
       const double *col = sG + off + hK * NJ;
       if (CO1) {
 #pragma unroll
-        for (int o = 0; o < 5; ++o) h = fma(w1[o], col[2 * hJ + o], h);
+        for (int o = 0; o < 5; ++o) h = fma(w1(o), col[2 * hJ + o], h);
       } else {
         h = col[hJ];
       }
@@ -525,8 +541,12 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5))) 
   extern __shared__ double xs[];
   const int lane = threadIdx.x & 63;
   const int p = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t k = (int64_t)blockIdx.x * 64 + lane;
-  const int64_t outer = blockIdx.y;
+  // blocks of 64 lines in (outer, k-block) order, consecutive ones on one XCD:
+  // neighbouring k-blocks share the cache lines at their ends
+  const int nkb = (int)((nk + 63) / 64);
+  const int blk = xcd_tile(blockIdx.x, gridDim.x);
+  const int64_t k = (int64_t)(blk % nkb) * 64 + lane;
+  const int64_t outer = blk / nkb;
   const bool active = k < nk;
   const int64_t base = outer * so + k;
   const int64_t f = (int64_t)p * S;
@@ -1418,7 +1438,7 @@ void launch_strided_s(double *F, const Level &L, int axis, const Epi<T> &ep, Ctx
   int64_t sp_, so, nouter;
   if (axis == 0) { sp_ = c1 * c2; so = c2; nouter = c1; }
   else { sp_ = c2; so = c1 * c2; nouter = c0; }
-  dim3 grid((unsigned)((c2 + 63) / 64), (unsigned)nouter);
+  dim3 grid((unsigned)(((c2 + 63) / 64) * nouter));
   const size_t lds = (size_t)4 * d.P * 64 * sizeof(double);
   TimedLaunch tl(cx.stream, std::string("k_solve_strided<") + tname<T>() + ", " + std::to_string(S) + ">" + epi_tag(ep.mode),
                  timing_enabled() ? solve_bytes<T>((double)c0 * c1 * c2, ep.mode) : 0.0);
