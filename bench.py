@@ -13,7 +13,11 @@ Prints one JSON line:
   cpu_baseline the FP64 CPU oracle on the same workload (one step), GB/s in
                the same unit, with the number of threads it used.
 Extra keys: the algorithmic-byte rate of the whole step, per-kernel totals,
-the FP32 mode on the same grid, and the round-trip error of the timed data.
+the FP32 mode on the same grid, the round-trip error of the timed data, and
+`batched`: 64 mixed 2-D/3-D FP32/FP64 fields decomposed and recomposed one
+field per call, with the batched entry points, and with the batch replayed
+from a HIP graph (p50/p99 ms per batch, GB/s, and whether the batched results
+are bitwise those of the single calls).
 """
 from __future__ import annotations
 
@@ -166,6 +170,100 @@ def run_gpu(name: str, steps: int, warmup: int, graph_steps: int = 0):
     return res, u, coords, nlev
 
 
+def _pct(v, q):
+    v = sorted(v)
+    return v[min(len(v) - 1, int(round(q * (len(v) - 1))))]
+
+
+def run_batched(reps: int = 10, warmup: int = 2, nfields: int = 64):
+    """The mixed batch (synth.batch_specs): one field per call vs. the batched
+    entry points vs. the batch captured in a HIP graph."""
+    import torch
+
+    from paper_2105_12764_amd import mgr
+    from paper_2105_12764_amd.synth import batch_specs, make_input
+
+    specs = batch_specs(nfields)
+    dev = torch.device("cuda:0")
+    _log(f"[bench] batch: generating {nfields} fields")
+    xs = []
+    for shape, dtype, seed in specs:
+        u, _ = make_input(shape, seed, nonuniform=False, dtype=dtype)
+        xs.append(torch.from_numpy(u).to(dev))
+        del u
+    nbytes = sum(2 * x.numel() * x.element_size() for x in xs)
+    nlev = [mgr.max_levels(tuple(x.shape)) for x in xs]
+    d1 = [torch.empty_like(x) for x in xs]
+    r1 = [torch.empty_like(x) for x in xs]
+    d2 = [torch.empty_like(x) for x in xs]
+    r2 = [torch.empty_like(x) for x in xs]
+    ws1 = torch.empty(max(mgr.workspace_size(tuple(x.shape), x.dtype, n) for x, n in zip(xs, nlev)) + 1,
+                      dtype=torch.uint8, device=dev)
+    bd = mgr.Batch([(x, y, None, n) for x, y, n in zip(xs, d2, nlev)])
+    br = mgr.Batch([(y, z, None, n) for y, z, n in zip(d2, r2, nlev)])
+    ws2 = bd.alloc_workspace(dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def serial():
+        for x, y, z, n in zip(xs, d1, r1, nlev):
+            mgr.decompose(x, None, n, out=y, workspace=ws1, stream=stream)
+            mgr.recompose(y, None, n, out=z, workspace=ws1, stream=stream)
+
+    def batched(st=None):
+        mgr.decompose_batch(bd, ws2, stream=st or stream)
+        mgr.recompose_batch(br, ws2, stream=st or stream)
+
+    def timed(fn, n):
+        out = []
+        for _ in range(n):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn()
+            b.record(stream)
+            b.synchronize()
+            out.append(a.elapsed_time(b))
+        return out
+
+    for _ in range(warmup):
+        serial()
+        batched()
+    torch.cuda.synchronize()
+    t_serial = timed(serial, reps)
+    t_batch = timed(batched, reps)
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream(dev)
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            batched(side)
+    torch.cuda.synchronize()
+    for _ in range(warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    t_graph = timed(g.replay, reps)
+    same = all(torch.equal(a, b) for a, b in zip(d1, d2)) and all(torch.equal(a, b) for a, b in zip(r1, r2))
+    err = max(float((z.double() - x.double()).abs().max() / x.double().abs().max()) for x, z in zip(xs, r2))
+
+    def stats(v):
+        return {"p50": round(_pct(v, 0.5), 4), "p99": round(_pct(v, 0.99), 4),
+                "GBps": round(nbytes / (_pct(v, 0.5) * 1e-3) / 1e9, 1)}
+
+    res = {"fields": nfields, "shapes": "2-D sides 257..2049 and 3-D sides 33..257, log-uniform; "
+                                         "FP32/FP64 mixed; all levels; seeds 4000+i",
+           "n_2d": sum(1 for s in specs if len(s[0]) == 2),
+           "n_fp64": sum(1 for s in specs if s[1] == np.float64),
+           "bytes_per_batch": nbytes, "reps": reps,
+           "one_field_per_call_ms": stats(t_serial), "batched_ms": stats(t_batch),
+           "batched_graph_ms": stats(t_graph),
+           "speedup_batched_graph_vs_one_field_per_call": round(_pct(t_serial, 0.5) / _pct(t_graph, 0.5), 3),
+           "bitwise_equal_to_single_calls": bool(same), "roundtrip_max_rel_err": err}
+    _log(f"[bench] batch: one field per call {res['one_field_per_call_ms']['p50']:.3f} ms, batched "
+         f"{res['batched_ms']['p50']:.3f} ms, graph {res['batched_graph_ms']['p50']:.3f} ms")
+    del xs, d1, r1, d2, r2, ws1, ws2, g
+    torch.cuda.empty_cache()
+    return res
+
+
 def probe_bandwidth(nbytes: int = 1 << 30, reps: int = 10):
     """Achievable single-pass bandwidth: the library's streaming copy probe
     (one read + one write of every byte), 2 * bytes / time."""
@@ -221,6 +319,7 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--graph-steps", type=int, default=0,
                     help="also time this many replays of the step captured as a HIP graph")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-field batch")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -236,6 +335,7 @@ def main():
         r32, _, _, _ = run_gpu(args.fp32_workload, args.steps, args.warmup)
         fp32 = {k: r32[k] for k in ("workload", "value", "t_dec_ms", "t_rec_ms", "alg_GBps",
                                      "roundtrip_max_rel_err", "roofline")}
+    batched = None if args.no_batch else run_batched()
     cpu = None if args.no_cpu_baseline else cpu_baseline(u, coords, nlev)
 
     line = {
@@ -267,6 +367,7 @@ def main():
         "kernels": res["kernels"],
         "fp32": fp32,
         "graph": res["graph"],
+        "batched": batched,
     }
     print(json.dumps(line), flush=True)
 

@@ -114,6 +114,57 @@ const char *mgr_last_error(void);
  * sure no enqueued libmgr work is still pending. */
 void mgr_release_caches(void);
 
+/* ---- Batches of independent fields ----------------------------------------
+ * Many fields of different shapes, level counts and dtypes refactored by one
+ * call (the paper runs independent fields side by side, Sec. III-F; its
+ * evaluation refactors many fields, Sec. IV-D).  Each field's result is
+ * bitwise the result of mgr_decompose / mgr_recompose on that field alone. */
+
+/* One field of a batch; the members mean what the same-named arguments of
+ * mgr_decompose mean (shape: the first ndim entries are used). */
+typedef struct mgr_field {
+  int ndim;
+  int64_t shape[3];
+  const double *const *coords;
+  mgr_dtype dtype;
+  int nlevels;
+  const void *in;
+  void *out;
+} mgr_field;
+
+/* Number of internal streams a batch spreads its fields over. */
+#define MGR_BATCH_STREAMS 4
+
+/* Device workspace bytes for a batch: each field gets its own slice
+ * (mgr_workspace_size of the field, rounded up to 256 bytes), in order.
+ * Host only.  Returns the first invalid field's error (the detail names its
+ * index); nfields must be >= 1 and fields non-NULL. */
+mgr_status mgr_batch_workspace_size(int nfields, const mgr_field *fields, size_t *bytes);
+
+/* Decompose every field of the batch.
+ *   fields    : host array of nfields descriptors, read during the call.
+ *   workspace : device pointer, >= mgr_batch_workspace_size bytes, 256-byte
+ *               aligned, caller-owned; not overlapping any field's in or out.
+ *   stream    : the call is ordered on `stream` like a single call: its
+ *               work starts after the work already enqueued there, and work
+ *               enqueued there afterwards starts after all of it.  Inside,
+ *               the fields' level sequences are spread over
+ *               MGR_BATCH_STREAMS internal streams (default priority),
+ *               forked from `stream` and joined back with events, so small
+ *               fields run side by side and the whole call can be captured
+ *               into one HIP graph (plans must exist first: make one
+ *               uncaptured call with the same fields before capturing).
+ * Besides every check of mgr_decompose per field (the detail names the
+ * field), no field's out may overlap another field's in or out.  All checks
+ * happen before anything is enqueued; on error nothing is launched. */
+mgr_status mgr_decompose_batch(int nfields, const mgr_field *fields, void *workspace,
+                               size_t workspace_bytes, void *stream);
+
+/* Recompose every field of the batch (each field's `in` is its nodal
+ * representation, `out` the field).  As mgr_decompose_batch otherwise. */
+mgr_status mgr_recompose_batch(int nfields, const mgr_field *fields, void *workspace,
+                               size_t workspace_bytes, void *stream);
+
 /* ---- Instrumentation (benchmarking only; not part of the method) --------
  * While enabled, every kernel launch of later calls is bracketed by a pair of
  * HIP events recorded on the launch's own stream, and its algorithmic

@@ -3,6 +3,7 @@
 // kernels.  No exception crosses the boundary.
 #include <hip/hip_runtime_api.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <list>
@@ -180,6 +181,194 @@ mgr_status run(bool dec, int ndim, const int64_t *shape, const double *const *co
   }
 }
 
+// ------------------------------------------------------------ batches
+
+// Internal streams of one device for batched calls, created on first use and
+// kept until the process ends (a stream may still hold enqueued work).
+struct BatchStreams {
+  int device = -1;
+  hipStream_t s[MGR_BATCH_STREAMS] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[MGR_BATCH_STREAMS] = {};
+};
+std::mutex g_bmu;                 // guards g_batch and serialises batch enqueues
+std::list<BatchStreams> g_batch;  // stable addresses
+
+mgr_status batch_streams(int dev, BatchStreams *&out) {
+  for (auto &b : g_batch)
+    if (b.device == dev) {
+      out = &b;
+      return MGR_OK;
+    }
+  BatchStreams b;
+  b.device = dev;
+  bool ok = hipEventCreateWithFlags(&b.fork, hipEventDisableTiming) == hipSuccess;
+  for (int k = 0; ok && k < MGR_BATCH_STREAMS; ++k) {
+    ok = hipStreamCreateWithFlags(&b.s[k], hipStreamNonBlocking) == hipSuccess;
+    if (ok) ok = hipEventCreateWithFlags(&b.join[k], hipEventDisableTiming) == hipSuccess;
+  }
+  if (!ok) {
+    const hipError_t e = hipGetLastError();
+    for (int k = 0; k < MGR_BATCH_STREAMS; ++k) {
+      if (b.join[k]) (void)hipEventDestroy(b.join[k]);
+      if (b.s[k]) (void)hipStreamDestroy(b.s[k]);
+    }
+    if (b.fork) (void)hipEventDestroy(b.fork);
+    return fail(MGR_ERR_DEVICE, std::string("creating the batch streams: ") + hipGetErrorString(e));
+  }
+  g_batch.push_back(b);
+  out = &g_batch.back();
+  return MGR_OK;
+}
+
+struct FieldJob {
+  int64_t n[mgr::kDims];
+  std::vector<std::vector<double>> cx;
+  std::shared_ptr<mgr::Plan> plan;
+  size_t ws_off = 0, ws_need = 0, bytes = 0;
+};
+
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+std::string field_tag(int i) { return "field " + std::to_string(i) + ": "; }
+
+// Shape, dtype and level checks of every field and the workspace layout.
+mgr_status batch_layout(int nfields, const mgr_field *fields, std::vector<FieldJob> &jobs,
+                        size_t &total) {
+  if (nfields < 1) return fail(MGR_ERR_INVALID_ARG, "nfields must be >= 1");
+  if (!fields) return fail(MGR_ERR_INVALID_ARG, "fields is NULL");
+  jobs.assign(nfields, FieldJob{});
+  total = 0;
+  for (int i = 0; i < nfields; ++i) {
+    const mgr_field &f = fields[i];
+    std::string why;
+    if (!pad_shape(f.ndim, f.shape, jobs[i].n, why)) return fail(MGR_ERR_INVALID_ARG, field_tag(i) + why);
+    if (f.dtype != MGR_FLOAT32 && f.dtype != MGR_FLOAT64)
+      return fail(MGR_ERR_INVALID_ARG, field_tag(i) + "dtype must be MGR_FLOAT32 or MGR_FLOAT64");
+    const int ml = mgr::max_levels3(jobs[i].n);
+    if (f.nlevels < 0 || f.nlevels > ml)
+      return fail(MGR_ERR_INVALID_ARG,
+                  field_tag(i) + "nlevels must be in [0, " + std::to_string(ml) + "]");
+    const size_t esz = f.dtype == MGR_FLOAT64 ? 8 : 4;
+    jobs[i].bytes = (size_t)(jobs[i].n[0] * jobs[i].n[1] * jobs[i].n[2]) * esz;
+    jobs[i].ws_need = mgr::workspace_bytes(jobs[i].n, f.nlevels, esz);
+    jobs[i].ws_off = total;
+    total += align256(jobs[i].ws_need);
+  }
+  return MGR_OK;
+}
+
+bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
+  const char *x = (const char *)a, *y = (const char *)b;
+  return x < y + nb && y < x + na;
+}
+
+mgr_status run_batch(bool dec, int nfields, const mgr_field *fields, void *ws, size_t ws_bytes,
+                     void *stream) {
+  g_last_error.clear();
+  try {
+    std::vector<FieldJob> jobs;
+    size_t total = 0;
+    mgr_status s = batch_layout(nfields, fields, jobs, total);
+    if (s != MGR_OK) return s;
+    if (total > 0) {
+      if (!ws) return fail(MGR_ERR_WORKSPACE, "workspace is NULL");
+      if (ws_bytes < total)
+        return fail(MGR_ERR_WORKSPACE, "workspace too small: need " + std::to_string(total) + " bytes");
+      if ((uintptr_t)ws % 256 != 0) return fail(MGR_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    }
+    for (int i = 0; i < nfields; ++i) {
+      const mgr_field &f = fields[i];
+      void *wsi = ws ? (void *)((char *)ws + jobs[i].ws_off) : nullptr;
+      s = validate(f.ndim, f.shape, f.coords, (int)f.dtype, f.nlevels, f.in, f.out, wsi, jobs[i].ws_need,
+                   jobs[i].n, jobs[i].cx);
+      if (s != MGR_OK) return fail(s, field_tag(i) + g_last_error);
+      if (total > 0 && (overlaps(ws, total, f.in, jobs[i].bytes) || overlaps(ws, total, f.out, jobs[i].bytes)))
+        return fail(MGR_ERR_INVALID_ARG, field_tag(i) + "in or out overlaps the batch workspace");
+    }
+    for (int i = 0; i < nfields; ++i)
+      for (int j = 0; j < nfields; ++j) {
+        if (i == j) continue;
+        if (overlaps(fields[i].out, jobs[i].bytes, fields[j].out, jobs[j].bytes) ||
+            overlaps(fields[i].out, jobs[i].bytes, fields[j].in, jobs[j].bytes))
+          return fail(MGR_ERR_INVALID_ARG, field_tag(i) + "out overlaps the in or out of field " +
+                                               std::to_string(j));
+      }
+    for (int i = 0; i < nfields; ++i) {
+      s = get_plan(jobs[i].n, fields[i].ndim, fields[i].nlevels, jobs[i].cx, jobs[i].plan);
+      if (s != MGR_OK) return fail(s, field_tag(i) + g_last_error);
+    }
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) {
+      const hipError_t e = hipGetLastError();
+      return fail(MGR_ERR_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    }
+    // largest fields first, each to the least loaded stream
+    std::vector<int> order(nfields);
+    for (int i = 0; i < nfields; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return jobs[a].bytes > jobs[b].bytes; });
+    std::vector<int> lane(nfields);
+    double load[MGR_BATCH_STREAMS] = {};
+    for (int i : order) {
+      int k = 0;
+      for (int q = 1; q < MGR_BATCH_STREAMS; ++q)
+        if (load[q] < load[k]) k = q;
+      lane[i] = k;
+      load[k] += (double)jobs[i].bytes;
+    }
+    std::lock_guard<std::mutex> lk(g_bmu);
+    BatchStreams *bs = nullptr;
+    s = batch_streams(dev, bs);
+    if (s != MGR_OK) return s;
+    hipStream_t user = (hipStream_t)stream;
+    if (hipEventRecord(bs->fork, user) != hipSuccess) {
+      const hipError_t e = hipGetLastError();
+      return fail(MGR_ERR_DEVICE, std::string("hipEventRecord: ") + hipGetErrorString(e));
+    }
+    bool used[MGR_BATCH_STREAMS] = {};
+    for (int i = 0; i < nfields; ++i) used[lane[i]] = true;
+    std::string err;
+    bool ok = true;
+    for (int k = 0; k < MGR_BATCH_STREAMS && ok; ++k)
+      if (used[k] && hipStreamWaitEvent(bs->s[k], bs->fork, 0) != hipSuccess) {
+        ok = false;
+        err = std::string("hipStreamWaitEvent: ") + hipGetErrorString(hipGetLastError());
+      }
+    for (int i : order) {
+      if (!ok) break;
+      const bool f64 = fields[i].dtype == MGR_FLOAT64;
+      void *wsi = ws ? (void *)((char *)ws + jobs[i].ws_off) : nullptr;
+      std::string e;
+      const bool good = dec ? mgr::enqueue_decompose(*jobs[i].plan, f64, fields[i].in, fields[i].out, wsi,
+                                                     bs->s[lane[i]], e)
+                            : mgr::enqueue_recompose(*jobs[i].plan, f64, fields[i].in, fields[i].out, wsi,
+                                                     bs->s[lane[i]], e);
+      if (!good) {
+        ok = false;
+        err = field_tag(i) + e;
+      }
+    }
+    // join every stream that may hold work back to the caller's stream, also
+    // after a failure, so that later work on `stream` stays ordered
+    for (int k = 0; k < MGR_BATCH_STREAMS; ++k) {
+      if (!used[k]) continue;
+      if (hipEventRecord(bs->join[k], bs->s[k]) != hipSuccess ||
+          hipStreamWaitEvent(user, bs->join[k], 0) != hipSuccess) {
+        const hipError_t e = hipGetLastError();
+        if (ok) err = std::string("joining the batch streams: ") + hipGetErrorString(e);
+        ok = false;
+      }
+    }
+    if (!ok) return fail(MGR_ERR_DEVICE, err);
+    return MGR_OK;
+  } catch (const std::bad_alloc &) {
+    return fail(MGR_ERR_OUT_OF_MEMORY, "host allocation failed");
+  } catch (...) {
+    return fail(MGR_ERR_DEVICE, "unexpected internal failure");
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -222,6 +411,31 @@ mgr_status mgr_recompose(int ndim, const int64_t *shape, const double *const *co
                          size_t workspace_bytes, void *stream) {
   return run(false, ndim, shape, coords, (int)dtype, nlevels, in, out, workspace, workspace_bytes,
              stream);
+}
+
+mgr_status mgr_batch_workspace_size(int nfields, const mgr_field *fields, size_t *bytes) {
+  g_last_error.clear();
+  if (!bytes) return fail(MGR_ERR_INVALID_ARG, "bytes is NULL");
+  try {
+    std::vector<FieldJob> jobs;
+    size_t total = 0;
+    const mgr_status s = batch_layout(nfields, fields, jobs, total);
+    if (s != MGR_OK) return s;
+    *bytes = total;
+    return MGR_OK;
+  } catch (const std::bad_alloc &) {
+    return fail(MGR_ERR_OUT_OF_MEMORY, "host allocation failed");
+  }
+}
+
+mgr_status mgr_decompose_batch(int nfields, const mgr_field *fields, void *workspace,
+                               size_t workspace_bytes, void *stream) {
+  return run_batch(true, nfields, fields, workspace, workspace_bytes, stream);
+}
+
+mgr_status mgr_recompose_batch(int nfields, const mgr_field *fields, void *workspace,
+                               size_t workspace_bytes, void *stream) {
+  return run_batch(false, nfields, fields, workspace, workspace_bytes, stream);
 }
 
 mgr_status mgr_probe_copy(const void *src, void *dst, size_t bytes, void *stream) {

@@ -27,7 +27,20 @@ MGR_ERR_DEVICE = 5
 MGR_FLOAT32 = 0
 MGR_FLOAT64 = 1
 
+MGR_BATCH_STREAMS = 4
+
 _lib = None
+
+
+class MgrField(ctypes.Structure):
+    """Mirror of ``mgr_field`` (include/mgr.h)."""
+    _fields_ = [("ndim", ctypes.c_int),
+                ("shape", ctypes.c_int64 * 3),
+                ("coords", ctypes.c_void_p),
+                ("dtype", ctypes.c_int),
+                ("nlevels", ctypes.c_int),
+                ("in_", ctypes.c_void_p),
+                ("out", ctypes.c_void_p)]
 
 
 class MgrError(RuntimeError):
@@ -62,6 +75,12 @@ def lib() -> ctypes.CDLL:
         L.mgr_last_error.restype = ctypes.c_char_p
         L.mgr_release_caches.argtypes = []
         L.mgr_release_caches.restype = None
+        fp = ctypes.POINTER(MgrField)
+        L.mgr_batch_workspace_size.argtypes = [ctypes.c_int, fp, ctypes.POINTER(ctypes.c_size_t)]
+        L.mgr_batch_workspace_size.restype = ctypes.c_int
+        for fn in (L.mgr_decompose_batch, L.mgr_recompose_batch):
+            fn.argtypes = [ctypes.c_int, fp, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+            fn.restype = ctypes.c_int
         L.mgr_probe_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                      ctypes.c_void_p]
         L.mgr_probe_copy.restype = ctypes.c_int
@@ -177,6 +196,89 @@ def decompose(x, coords=None, nlevels: Optional[int] = None, out=None, workspace
 def recompose(x, coords=None, nlevels: Optional[int] = None, out=None, workspace=None, stream=None):
     """mgr_recompose (inverse of :func:`decompose`); returns ``out``."""
     return _call(lib().mgr_recompose, x, coords, nlevels, out, workspace, stream)
+
+
+class Batch:
+    """Descriptors of a batch of independent fields for the batched entry points.
+
+    ``items`` is a sequence of ``(in_tensor, out_tensor, coords, nlevels)``;
+    coords may be None (uniform) and nlevels None (all levels).  The object
+    keeps the coordinate arrays alive for the calls.
+    """
+
+    def __init__(self, items):
+        n = len(items)
+        self.fields = (MgrField * n)()
+        self._keep = []
+        self.tensors = []
+        for i, (x, y, coords, nlevels) in enumerate(items):
+            if not (x.is_cuda and y.is_cuda and x.is_contiguous() and y.is_contiguous()):
+                raise ValueError(f"field {i}: in and out must be contiguous HIP tensors")
+            if x.shape != y.shape or x.dtype != y.dtype:
+                raise ValueError(f"field {i}: in and out must match in shape and dtype")
+            shape = tuple(x.shape)
+            f = self.fields[i]
+            f.ndim = len(shape)
+            for k, v in enumerate(shape):
+                f.shape[k] = int(v)
+            carr, keep = _coords_arg(shape, coords)
+            self._keep.append((carr, keep))
+            f.coords = ctypes.cast(carr, ctypes.c_void_p) if carr is not None else None
+            f.dtype = _dtype_code(x.dtype)
+            f.nlevels = int(max_levels(shape) if nlevels is None else nlevels)
+            f.in_ = x.data_ptr()
+            f.out = y.data_ptr()
+            self.tensors.append((x, y))
+
+    def __len__(self):
+        return len(self.fields)
+
+    def swapped(self):
+        """The same fields with in and out exchanged (recompose what was decomposed)."""
+        b = Batch.__new__(Batch)
+        n = len(self.fields)
+        b.fields = (MgrField * n)()
+        ctypes.memmove(b.fields, self.fields, ctypes.sizeof(self.fields))
+        for i in range(n):
+            b.fields[i].in_, b.fields[i].out = self.fields[i].out, self.fields[i].in_
+        b._keep = self._keep
+        b.tensors = [(y, x) for (x, y) in self.tensors]
+        return b
+
+    def workspace_size(self) -> int:
+        out = ctypes.c_size_t(0)
+        s = lib().mgr_batch_workspace_size(len(self.fields), self.fields, ctypes.byref(out))
+        if s != MGR_OK:
+            raise MgrError(s, last_error())
+        return int(out.value)
+
+    def alloc_workspace(self, device=None):
+        import torch
+        return torch.empty(max(self.workspace_size(), 1), dtype=torch.uint8, device=device or "cuda")
+
+
+def _call_batch(fn, batch: Batch, workspace, stream):
+    import torch
+    dev = batch.tensors[0][0].device
+    if workspace is None:
+        workspace = batch.alloc_workspace(dev)
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    with torch.cuda.device(dev):
+        s = fn(len(batch.fields), batch.fields, ctypes.c_void_p(workspace.data_ptr()),
+               ctypes.c_size_t(workspace.numel()), ctypes.c_void_p(stream.cuda_stream))
+    if s != MGR_OK:
+        raise MgrError(s, last_error())
+
+
+def decompose_batch(batch: Batch, workspace=None, stream=None) -> None:
+    """mgr_decompose_batch: every field's in decomposed into its out."""
+    _call_batch(lib().mgr_decompose_batch, batch, workspace, stream)
+
+
+def recompose_batch(batch: Batch, workspace=None, stream=None) -> None:
+    """mgr_recompose_batch: every field's in (a representation) recomposed into its out."""
+    _call_batch(lib().mgr_recompose_batch, batch, workspace, stream)
 
 
 def release_caches() -> None:

@@ -81,3 +81,20 @@ WORKLOADS = {
     "cube513_f32": ((513, 513, 513), 1002, False, np.float32, 9),
     "box400x300x250_f32": ((400, 300, 250), 1003, True, np.float32, 8),
 }
+
+
+def batch_specs(nfields: int = 64, seed0: int = 4000):
+    """Shapes and dtypes of the mixed batch: field i draws, from its own
+    generator seeded (seed0, i), a rank of 2 or 3 (probability 1/2 each), FP32
+    or FP64 (1/2 each) and a side length log-uniform over [257, 2049] (2-D) or
+    [33, 257] (3-D); its values come from make_input with seed seed0 + i.
+    Returns [(shape, dtype, seed)]."""
+    out = []
+    for i in range(nfields):
+        rng = np.random.default_rng([seed0, i])
+        dim = 2 if rng.random() < 0.5 else 3
+        dtype = np.float32 if rng.random() < 0.5 else np.float64
+        lo, hi = (257, 2049) if dim == 2 else (33, 257)
+        side = int(round(float(np.exp(rng.uniform(np.log(lo), np.log(hi))))))
+        out.append(((side,) * dim, dtype, seed0 + i))
+    return out

@@ -95,3 +95,55 @@ def test_status_strings():
     for s in range(6):
         assert mgr.status_string(s)
     assert mgr.status_string(0) == "ok"
+
+
+def _fields(specs):
+    """ctypes mgr_field array from (shape, dtype code, nlevels, in address, out address)."""
+    arr = (mgr.MgrField * len(specs))()
+    for i, (shape, dt, nl, inp, out) in enumerate(specs):
+        arr[i].ndim = len(shape)
+        for k, v in enumerate(shape):
+            arr[i].shape[k] = v
+        arr[i].coords = None
+        arr[i].dtype = dt
+        arr[i].nlevels = nl
+        arr[i].in_ = inp
+        arr[i].out = out
+    return arr
+
+
+def test_batch_workspace_is_the_aligned_sum_of_the_fields():
+    specs = [((33, 33, 33), mgr.MGR_FLOAT64, 4, 1 << 30, 2 << 30),
+             ((300, 41), mgr.MGR_FLOAT32, 3, 3 << 30, 4 << 30),
+             ((9, 9, 9), mgr.MGR_FLOAT64, 0, 5 << 30, 6 << 30)]
+    al = lambda b: (b + 255) // 256 * 256
+    want = sum(al(mgr.workspace_size(s, np.float64 if d == mgr.MGR_FLOAT64 else np.float32, n))
+               for s, d, n, _, _ in specs)
+    out = ctypes.c_size_t(0)
+    assert mgr.lib().mgr_batch_workspace_size(3, _fields(specs), ctypes.byref(out)) == mgr.MGR_OK
+    assert out.value == want
+
+
+@pytest.mark.parametrize("fn", ["mgr_decompose_batch", "mgr_recompose_batch"])
+def test_batch_rejects_bad_fields_before_any_device_call(fn):
+    L = mgr.lib()
+    E = mgr.MGR_ERR_INVALID_ARG
+    ok = ((9, 9, 9), mgr.MGR_FLOAT64, 2, 1 << 30, 2 << 30)
+    call = lambda specs, ws=1 << 34, wsb=1 << 30: getattr(L, fn)(
+        len(specs), _fields(specs), ctypes.c_void_p(ws), ctypes.c_size_t(wsb), None)
+    assert getattr(L, fn)(0, _fields([ok]), ctypes.c_void_p(1 << 34), ctypes.c_size_t(1 << 30), None) == E
+    assert getattr(L, fn)(1, None, ctypes.c_void_p(1 << 34), ctypes.c_size_t(1 << 30), None) == E
+    # the detail names the failing field
+    bad_shape = ((9, 1, 9), mgr.MGR_FLOAT64, 1, 3 << 30, 4 << 30)
+    assert call([ok, ok[:3] + (5 << 30, 6 << 30), bad_shape]) == E
+    assert mgr.last_error().startswith("field 2:")
+    bad_levels = ((9, 9, 9), mgr.MGR_FLOAT64, 9, 3 << 30, 4 << 30)
+    assert call([ok, bad_levels]) == E and mgr.last_error().startswith("field 1:")
+    # one field's out overlapping another field's in or out
+    clash = ((9, 9, 9), mgr.MGR_FLOAT64, 2, 3 << 30, (2 << 30) + 64)
+    assert call([ok, clash]) == E and "overlaps" in mgr.last_error()
+    clash_in = ((9, 9, 9), mgr.MGR_FLOAT64, 2, 3 << 30, (1 << 30) + 8)  # its out over field 1's in
+    assert call([clash_in, ok]) == E and "overlaps" in mgr.last_error()
+    # workspace too small, or overlapping a field
+    assert call([ok], wsb=16) == mgr.MGR_ERR_WORKSPACE
+    assert call([ok], ws=(1 << 30)) == E
