@@ -62,7 +62,7 @@ def _log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
-def run_gpu(name: str, steps: int, warmup: int, graph_steps: int = 0):
+def run_gpu(name: str, steps: int, warmup: int, graph_steps: int = 0, tune: bool = True):
     import torch
 
     from paper_2105_12764_amd import mgr
@@ -88,6 +88,25 @@ def run_gpu(name: str, steps: int, warmup: int, graph_steps: int = 0):
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
+
+    untuned = None
+    report = None
+    if tune:
+        # the built-in launch shapes first, then the autotuned ones (the plan
+        # keeps them; the timed regions below use them)
+        a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        n0 = max(3, steps // 2)
+        a0.record(stream)
+        for _ in range(n0):
+            step()
+        a1.record(stream)
+        torch.cuda.synchronize()
+        untuned = a0.elapsed_time(a1) / n0
+        report = mgr.autotune(x, coords, nlev, out=r, workspace=ws)
+        for _ in range(max(1, warmup)):
+            step()
+        torch.cuda.synchronize()
+        _log(f"[bench] {name}: untuned {untuned:.3f} ms/step; autotuned")
 
     # timed region 1: the throughput (events only at decompose/recompose boundaries)
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
@@ -164,6 +183,10 @@ def run_gpu(name: str, steps: int, warmup: int, graph_steps: int = 0):
         "alg_GBps": alg_bytes_step / ((t_dec + t_rec) * 1e-3) / 1e9,
         "roundtrip_max_rel_err": rt_err, "kernels": kernels, "roofline": roofline,
         "graph": graph,
+        "autotune": None if not tune else {
+            "untuned_ms_per_step": round(untuned, 4),
+            "untuned_value": round(2.0 * n * esz / (untuned * 1e-3) / 1e9, 2),
+            "report": report.strip().splitlines()},
     }
     del x, d, r, ws
     torch.cuda.empty_cache()
@@ -203,6 +226,10 @@ def run_batched(reps: int = 10, warmup: int = 2, nfields: int = 64):
     br = mgr.Batch([(y, z, None, n) for y, z, n in zip(d2, r2, nlev)])
     ws2 = bd.alloc_workspace(dev)
     stream = torch.cuda.current_stream(dev)
+
+    for x, y, n in zip(xs, d1, nlev):  # autotuned launch shapes for every field's plan
+        mgr.autotune(x, None, n, out=y, workspace=ws1, stream=stream)
+    torch.cuda.synchronize()
 
     def serial():
         for x, y, z, n in zip(xs, d1, r1, nlev):
@@ -249,7 +276,7 @@ def run_batched(reps: int = 10, warmup: int = 2, nfields: int = 64):
                 "GBps": round(nbytes / (_pct(v, 0.5) * 1e-3) / 1e9, 1)}
 
     res = {"fields": nfields, "shapes": "2-D sides 257..2049 and 3-D sides 33..257, log-uniform; "
-                                         "FP32/FP64 mixed; all levels; seeds 4000+i",
+                                         "FP32/FP64 mixed; all levels; seeds 4000+i; autotuned",
            "n_2d": sum(1 for s in specs if len(s[0]) == 2),
            "n_fp64": sum(1 for s in specs if s[1] == np.float64),
            "bytes_per_batch": nbytes, "reps": reps,
@@ -335,6 +362,7 @@ def main():
         r32, _, _, _ = run_gpu(args.fp32_workload, args.steps, args.warmup)
         fp32 = {k: r32[k] for k in ("workload", "value", "t_dec_ms", "t_rec_ms", "alg_GBps",
                                      "roundtrip_max_rel_err", "roofline")}
+        fp32["untuned_value"] = r32["autotune"]["untuned_value"] if r32.get("autotune") else None
     batched = None if args.no_batch else run_batched()
     cpu = None if args.no_cpu_baseline else cpu_baseline(u, coords, nlev)
 
@@ -353,7 +381,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{res['workload']}: {'x'.join(map(str, res['shape']))} "
                                f"{res['dtype']}, {res['nlevels']} levels, one decompose + one "
-                               "recompose per step",
+                               "recompose per step, autotuned launch shapes",
                    "shape": res["shape"], "nlevels": res["nlevels"]},
         "t_dec_ms": round(res["t_dec_ms"], 4),
         "t_rec_ms": round(res["t_rec_ms"], 4),
@@ -367,6 +395,7 @@ def main():
         "kernels": res["kernels"],
         "fp32": fp32,
         "graph": res["graph"],
+        "autotune": res["autotune"],
         "batched": batched,
     }
     print(json.dumps(line), flush=True)

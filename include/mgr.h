@@ -114,6 +114,27 @@ const char *mgr_last_error(void);
  * sure no enqueued libmgr work is still pending. */
 void mgr_release_caches(void);
 
+/* Autotune the launch shapes for this request (the paper's per-size tuning,
+ * Sec. III-B): for every level the library ranks candidate shapes -- the
+ * coarse planes each workgroup marches through and the reconstruction tile --
+ * with a model of the 128-byte memory lines they touch and the rounds of
+ * resident workgroups they need, times the three best on the GPU and keeps
+ * the fastest in the plan it caches for (shape, coords, nlevels) on this
+ * device.  Later mgr_decompose / mgr_recompose calls with that plan, and
+ * batches containing it, use the tuned shapes.  Results are bitwise those of
+ * the untuned calls: no shape changes any node's arithmetic.
+ * Arguments as for mgr_decompose; `in` is only read (its values do not
+ * matter), `out` and the workspace are overwritten with meaningless data.
+ * Synchronous: returns after the timed launches on `stream` have finished;
+ * not for use under stream capture. */
+mgr_status mgr_autotune(int ndim, const int64_t *shape, const double *const *coords,
+                        mgr_dtype dtype, int nlevels, const void *in, void *out,
+                        void *workspace, size_t workspace_bytes, void *stream);
+
+/* The calling thread's last mgr_autotune decisions, one line per choice
+ * ("" if none).  Valid until the thread's next mgr_autotune call. */
+const char *mgr_autotune_report(void);
+
 /* ---- Batches of independent fields ----------------------------------------
  * Many fields of different shapes, level counts and dtypes refactored by one
  * call (the paper runs independent fields side by side, Sec. III-F; its

@@ -19,6 +19,7 @@
 namespace {
 
 thread_local std::string g_last_error;
+thread_local std::string g_tune_report;
 
 mgr_status fail(mgr_status s, const std::string &msg) {
   g_last_error = msg;
@@ -412,6 +413,32 @@ mgr_status mgr_recompose(int ndim, const int64_t *shape, const double *const *co
   return run(false, ndim, shape, coords, (int)dtype, nlevels, in, out, workspace, workspace_bytes,
              stream);
 }
+
+mgr_status mgr_autotune(int ndim, const int64_t *shape, const double *const *coords, mgr_dtype dtype,
+                        int nlevels, const void *in, void *out, void *workspace, size_t workspace_bytes,
+                        void *stream) {
+  g_last_error.clear();
+  try {
+    int64_t n[mgr::kDims];
+    std::vector<std::vector<double>> cx;
+    mgr_status s = validate(ndim, shape, coords, (int)dtype, nlevels, in, out, workspace, workspace_bytes, n, cx);
+    if (s != MGR_OK) return s;
+    std::shared_ptr<mgr::Plan> plan;
+    s = get_plan(n, ndim, nlevels, cx, plan);
+    if (s != MGR_OK) return s;
+    std::string err, report;
+    if (!mgr::enqueue_autotune(*plan, dtype == MGR_FLOAT64, in, out, workspace, stream, err, report))
+      return fail(MGR_ERR_DEVICE, err);
+    g_tune_report = report;
+    return MGR_OK;
+  } catch (const std::bad_alloc &) {
+    return fail(MGR_ERR_OUT_OF_MEMORY, "host allocation failed");
+  } catch (...) {
+    return fail(MGR_ERR_DEVICE, "unexpected internal failure");
+  }
+}
+
+const char *mgr_autotune_report(void) { return g_tune_report.c_str(); }
 
 mgr_status mgr_batch_workspace_size(int nfields, const mgr_field *fields, size_t *bytes) {
   g_last_error.clear();

@@ -1287,6 +1287,11 @@ struct Ctx {
   hipStream_t stream;
   std::string *err;
   bool ok = true;
+  // per-launch requests and reports of the plane-marching launches
+  int ti_req = 0;     // coarse planes per workgroup requested (0: the built-in rule)
+  bool dry = false;   // compute the launch shape only, launch nothing
+  int slots_out = 0;  // resident workgroups of the kernel instance chosen
+  int ti_out = 0;     // coarse planes per workgroup chosen
   void check(const char *what) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess && ok) {
@@ -1352,7 +1357,12 @@ void launch_loadvec_t(LoadArgs<T> a, Ctx &cx) {
   static const int slots = resident_slots((const void *)k_loadvec<T, DEC, NODAL, C0, C1, C2>, NTHR);
   const int64_t tiles = (int64_t)a.gx * a.gy;
   // chunks short enough for the kernel's LDS plane window (2 TI + 3 planes)
-  a.TI = pick_chunk(a.c0, tiles, slots, C0 ? 2 : 0, (LV_MAXP - 3) / 2);
+  const int64_t maxti = (LV_MAXP - 3) / 2;
+  a.TI = cx.ti_req > 0 ? std::min<int64_t>(std::min<int64_t>(cx.ti_req, maxti), a.c0)
+                       : pick_chunk(a.c0, tiles, slots, C0 ? 2 : 0, maxti);
+  cx.slots_out = slots;
+  cx.ti_out = (int)a.TI;
+  if (cx.dry) return;
   a.gz = (int)((a.c0 + a.TI - 1) / a.TI);
   const dim3 grid((unsigned)(tiles * a.gz));
   double bytes = 0.0;
@@ -1527,33 +1537,51 @@ void launch_reconstruct_t(ReconArgs<T> a, Ctx &cx) {
   static const int slots = resident_slots((const void *)k_reconstruct<T, NC, C0, C1, C2>, RC_THR);
   const int64_t tiles = (int64_t)a.gx * a.gy;
   // chunks short enough for the kernel's LDS plane window (2 TI + 2 planes)
-  a.TI = pick_chunk(a.c0, tiles, slots, C0 ? 1 : 0, (LV_MAXP - 2) / 2);
+  const int64_t maxti = (LV_MAXP - 2) / 2;
+  a.TI = cx.ti_req > 0 ? std::min<int64_t>(std::min<int64_t>(cx.ti_req, maxti), a.c0)
+                       : pick_chunk(a.c0, tiles, slots, C0 ? 1 : 0, maxti);
+  cx.slots_out = slots;
+  cx.ti_out = (int)a.TI;
+  if (cx.dry) return;
   a.gz = (int)((a.c0 + a.TI - 1) / a.TI);
   hipLaunchKernelGGL((k_reconstruct<T, NC, C0, C1, C2>), dim3((unsigned)(tiles * a.gz)), dim3(RC_THR), 0,
                      cx.stream, a);
 }
 
+// Whether a reconstruct tile of tj coarse rows and tk coarse columns fits the
+// kernel's per-thread slots and its LDS coarse tile.
+bool recon_tile_fits(const Level &L, int64_t tj, int64_t tk) {
+  const int SJ = L.co[1] ? 2 : 1, SK = L.co[2] ? 2 : 1;
+  const int HJ = L.co[1] ? 1 : 0, HK = L.co[2] ? 1 : 0;
+  return tj >= 1 && tk >= 1 && tj <= L.c[1] && tk <= L.c[2] && SJ * tj * SK * tk <= RC_NE &&
+         (tj + HJ) * (tk + HK) <= RC_NC;
+}
+
+// The built-in reconstruct tile: whole rows where a row fits, then as many
+// coarse rows as the slots allow.
+void recon_tile_rule(const Level &L, int &tj, int &tk) {
+  int64_t TKc = L.c[2];
+  while (TKc > 1 && !recon_tile_fits(L, 1, TKc)) TKc = (TKc + 1) / 2;
+  int64_t TJc = 1;
+  while (TJc < L.c[1] && recon_tile_fits(L, TJc + 1, TKc)) ++TJc;
+  tj = (int)TJc;
+  tk = (int)TKc;
+}
+
 template <typename T>
-void launch_reconstruct(const Level &L, const T *coef, Map3 cmap, const T *uc, T *dst, Ctx &cx) {
+void launch_reconstruct(const Level &L, const T *coef, Map3 cmap, const T *uc, T *dst, Ctx &cx,
+                        int tj_req = 0, int tk_req = 0) {
   ReconArgs<T> a{};
   a.coef = coef; a.cmap = cmap; a.uc = uc; a.dst = dst;
   a.m0 = L.m[0]; a.m1 = L.m[1]; a.m2 = L.m[2];
   a.c0 = L.c[0]; a.c1 = L.c[1]; a.c2 = L.c[2];
   a.r0 = L.d[0].r; a.r1 = L.d[1].r; a.r2 = L.d[2].r;
-  // Tile: whole rows where a row fits (FK = SK * TK fine columns, at most
-  // half the per-thread slots), then as many coarse rows as the slots allow.
-  {
-    const int SJ = L.co[1] ? 2 : 1, SK = L.co[2] ? 2 : 1;
-    const int HJ = L.co[1] ? 1 : 0, HK = L.co[2] ? 1 : 0;
-    int64_t TKc = a.c2;
-    auto fits = [&](int64_t tj, int64_t tk) {
-      return SJ * tj * SK * tk <= RC_NE && (tj + HJ) * (tk + HK) <= RC_NC;
-    };
-    while (TKc > 1 && !fits(1, TKc)) TKc = (TKc + 1) / 2;
-    int64_t TJc = 1;
-    while (TJc < a.c1 && fits(TJc + 1, TKc)) ++TJc;
-    a.TK = (int)TKc;
-    a.TJ = (int)TJc;
+  // tile: a requested (autotuned) shape if it fits, else the built-in rule
+  if (tj_req > 0 && tk_req > 0 && recon_tile_fits(L, tj_req, tk_req)) {
+    a.TJ = tj_req;
+    a.TK = tk_req;
+  } else {
+    recon_tile_rule(L, a.TJ, a.TK);
   }
   a.gx = (int)((a.c2 + a.TK - 1) / a.TK);
   a.gy = (int)((a.c1 + a.TJ - 1) / a.TJ);
@@ -1563,7 +1591,7 @@ void launch_reconstruct(const Level &L, const T *coef, Map3 cmap, const T *uc, T
   TimedLaunch tl(cx.stream,
                  std::string("k_reconstruct<") + tname<T>() + ", " + bname(cmap.t0 != nullptr) + ", " +
                      bname(L.co[0]) + ", " + bname(L.co[1]) + ", " + bname(L.co[2]) + ">",
-                 timing_enabled() ? ((nl - nc) + nc + nl) * sizeof(T) : 0.0);
+                 (timing_enabled() && !cx.dry) ? ((nl - nc) + nc + nl) * sizeof(T) : 0.0);
   const int key = (cmap.t0 ? 8 : 0) | (L.co[0] ? 4 : 0) | (L.co[1] ? 2 : 0) | (L.co[2] ? 1 : 0);
 #define MGR_RECON(NC, C0, C1, C2) launch_reconstruct_t<T, NC, C0, C1, C2>(a, cx)
   switch (key) {
@@ -1634,6 +1662,7 @@ bool decompose_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t stre
   const T *src = in;
   Map3 smap = compact_map(pl.n[1], pl.n[2]);
   const int st = std::min(pl.tail_start, pl.nlev);
+  const std::vector<LevelTune> tune = pl.tune_snapshot();
   for (int s = 0; s < st && cx.ok; ++s) {
     const Level &L = pl.lev[s];
     T *next = (T *)w.buf[s % 2];
@@ -1643,7 +1672,9 @@ bool decompose_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t stre
     a.out = out;
     a.omap = (s == 0) ? compact_map(pl.n[1], pl.n[2]) : nodal_map(L);
     a.F = w.F;
+    cx.ti_req = s < (int)tune.size() ? tune[s].lv_ti[0] : 0;
     launch_loadvec<T, true>(L, a, cx);
+    cx.ti_req = 0;
     Epi<T> ep{};
     if (s + 1 < pl.nlev) {
       ep.mode = EPI_STORE_COMPACT;
@@ -1689,26 +1720,234 @@ bool recompose_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t stre
                        nodal_map(Lc), V, Lc.m[0], Lc.m[1], Lc.m[2]);
     cx.check("k_gather launch");
   }
+  const std::vector<LevelTune> tune = pl.tune_snapshot();
   for (int s = st - 1; s >= 0 && cx.ok; --s) {
     const Level &L = pl.lev[s];
+    const LevelTune lt = s < (int)tune.size() ? tune[s] : LevelTune{};
     const Map3 cmap = (s == 0) ? compact_map(pl.n[1], pl.n[2]) : nodal_map(L);
     LoadArgs<T> a{};
     a.src = in;
     a.smap = cmap;
     a.F = w.F;
+    cx.ti_req = lt.lv_ti[1];
     launch_loadvec<T, false>(L, a, cx);
+    cx.ti_req = 0;
     Epi<T> ep{};
     ep.mode = EPI_SUB_COMPACT;
     ep.dst = V;
     solve_all<T>(w.F, L, ep, cx);
     T *dst = (s == 0) ? out : (T *)w.buf[s % 2];
-    launch_reconstruct<T>(L, in, cmap, V, dst, cx);
+    cx.ti_req = lt.rc_ti;
+    launch_reconstruct<T>(L, in, cmap, V, dst, cx, lt.rc_tj, lt.rc_tk);
+    cx.ti_req = 0;
     V = dst;
   }
   return cx.ok;
 }
 
+// ------------------------------------------------------------ autotuner
+//
+// The paper tunes its kernels' launch shapes per problem size by ranking
+// candidates with a model of their memory transactions and profiling the
+// best few (Sec. III-B).  Here the tunable shapes are the dim-0 chunk length
+// of the load-vector and reconstruct kernels and the reconstruct tile; the
+// model counts the 128-byte lines (the CDNA4 cache line) a launch touches --
+// halo planes re-read per chunk, and row segments split between tiles, are
+// counted once per tile that touches them -- and adds a per-plane-step
+// latency for each round of resident workgroups.  The three best candidates
+// by the model run on the GPU, and the fastest is kept in the plan.  No
+// candidate changes any node's arithmetic.
+
+constexpr double kModelBytesPerSec = 4.5e12;  // streaming rate of a plain copy on MI355X
+constexpr double kModelStepSec = 0.6e-6;       // one plane step of a resident workgroup
+
+// 128-byte lines touched by the byte range [off, off + len).
+inline int64_t lines128(int64_t off, int64_t len) {
+  return len <= 0 ? 0 : (off + len - 1) / 128 - off / 128 + 1;
+}
+
+// Modelled seconds of a plane-marching launch over `tiles` tile columns and
+// c0 coarse planes in chunks of ti (halo: extra coarse planes per chunk),
+// moving bytes_per_plane per coarse plane of the whole grid.
+double model_march(int64_t c0, int64_t tiles, int slots, int halo, int64_t ti, double bytes_per_plane) {
+  const int64_t nch = (c0 + ti - 1) / ti, nwg = tiles * nch;
+  const int64_t rounds = (nwg + slots - 1) / std::max(slots, 1);
+  const double bytes = bytes_per_plane * (double)nch * (double)(ti + halo);
+  return std::max(bytes / kModelBytesPerSec, (double)rounds * (double)(ti + halo) * kModelStepSec);
+}
+
+// Bytes the reconstruct moves per coarse plane for tile (tj, tk): the fine
+// rows' coefficient reads and level-grid writes, line by line per tile
+// (nodal coefficients use half of every line), and the coarse tiles.
+double recon_bytes_per_plane(const Level &L, bool nodal, size_t es, int64_t tj, int64_t tk) {
+  const int64_t SJ = L.co[1] ? 2 : 1, SK = L.co[2] ? 2 : 1, s0 = L.co[0] ? 2 : 1;
+  const int64_t gx = (L.c[2] + tk - 1) / tk, gy = (L.c[1] + tj - 1) / tj;
+  int64_t fine = 0;
+  for (int64_t j = 0; j < L.m[1]; ++j)
+    for (int64_t tx = 0; tx < gx; ++tx) {
+      const int64_t k0 = SK * tx * tk, k1 = std::min(L.m[2], SK * (tx + 1) * tk);
+      const int64_t off = (j * L.m[2] + k0) * (int64_t)es, len = (k1 - k0) * (int64_t)es;
+      fine += lines128(off, len) + (nodal ? 2 * (len + 127) / 128 : lines128(off, len));
+    }
+  int64_t coarse = 0;
+  for (int64_t ty = 0; ty < gy; ++ty)
+    for (int64_t tx = 0; tx < gx; ++tx) {
+      const int64_t rows = std::min(tj + 1, L.c[1] - ty * tj), cols = std::min(tk + 1, L.c[2] - tx * tk);
+      for (int64_t r = 0; r < rows; ++r)
+        coarse += lines128(((ty * tj + r) * L.c[2] + tx * tk) * (int64_t)es, cols * (int64_t)es);
+    }
+  return 128.0 * ((double)fine * (double)s0 + (double)coarse);
+}
+
+template <typename T>
+bool autotune_t(Plan &pl, const T *in, T *out, void *ws, hipStream_t stream, std::string &err,
+                std::string &report) {
+  Ctx cx{stream, &err};
+  if (pl.nlev == 0) return true;
+  Workspace w = carve(pl, ws, sizeof(T));
+  const int nt = std::min(pl.tail_start, pl.nlev);
+  std::vector<LevelTune> tune(pl.nlev);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    (void)hipGetLastError();
+    if (e0) (void)hipEventDestroy(e0);
+    err = "hipEventCreate failed";
+    return false;
+  }
+  // best of three launches, in milliseconds
+  auto time_ms = [&](auto &&launch) -> double {
+    double best = 1e30;
+    for (int r = 0; r < 3 && cx.ok; ++r) {
+      (void)hipEventRecord(e0, stream);
+      launch();
+      (void)hipEventRecord(e1, stream);
+      if (hipEventSynchronize(e1) != hipSuccess) {
+        cx.ok = false;
+        err = "autotune: kernel failed";
+        break;
+      }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      best = std::min(best, (double)ms);
+    }
+    return best;
+  };
+  // times the model's three cheapest candidates and the built-in rule's
+  // (`rule`), returns the fastest
+  auto choose = [&](std::vector<std::pair<double, int>> cand, int rule, auto &&run, const char *what, int s) {
+    std::sort(cand.begin(), cand.end());
+    std::vector<int> timed;
+    for (size_t q = 0; q < cand.size() && q < 3; ++q) timed.push_back(cand[q].second);
+    if (std::find(timed.begin(), timed.end(), rule) == timed.end()) timed.push_back(rule);
+    int best = -1;
+    double best_ms = 1e30;
+    for (size_t q = 0; q < timed.size() && cx.ok; ++q) {
+      const int id = timed[q];
+      const double ms = time_ms([&] { run(id); });
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = id;
+      }
+    }
+    report += "level " + std::to_string(s) + " " + what + ": candidate " + std::to_string(best) + " (" +
+              std::to_string(best_ms * 1e3) + " us)\n";
+    return best;
+  };
+  const size_t es = sizeof(T);
+  for (int s = 0; s < nt && cx.ok; ++s) {
+    const Level &L = pl.lev[s];
+    const double nl = (double)L.m[0] * L.m[1] * L.m[2];
+    const int64_t tiles_lv = ((L.c[2] + TK - 1) / TK) * ((L.c[1] + TJ - 1) / TJ);
+    const int halo_lv = L.co[0] ? 2 : 0;
+    for (int dec = 1; dec >= 0 && cx.ok; --dec) {
+      LoadArgs<T> a{};
+      a.src = dec ? (s == 0 ? in : (const T *)w.buf[(s + 1) % 2]) : in;
+      a.smap = (dec || s == 0) ? compact_map(L.m[1], L.m[2]) : nodal_map(L);
+      a.out = out;
+      a.omap = s == 0 ? compact_map(L.m[1], L.m[2]) : nodal_map(L);
+      a.F = w.F;
+      cx.dry = true;
+      cx.ti_req = 0;
+      if (dec) launch_loadvec<T, true>(L, a, cx);
+      else launch_loadvec<T, false>(L, a, cx);
+      cx.dry = false;
+      const int slots = cx.slots_out, ti0 = cx.ti_out;
+      const double per_plane = (dec ? 2.0 * nl * es : nl * es) / (double)L.c[0];
+      std::vector<std::pair<double, int>> cand;
+      const int64_t maxti = std::min<int64_t>((LV_MAXP - 3) / 2, L.c[0]);
+      for (int64_t ti : {(int64_t)ti0, (int64_t)1, (int64_t)2, (int64_t)4, (int64_t)6, (int64_t)8, (int64_t)12,
+                         (int64_t)16, (int64_t)24, (int64_t)32, (int64_t)48, maxti}) {
+        if (ti < 1 || ti > maxti) continue;
+        bool dup = false;
+        for (auto &c : cand) dup |= c.second == (int)ti;
+        if (!dup) cand.push_back({model_march(L.c[0], tiles_lv, slots, halo_lv, ti, per_plane), (int)ti});
+      }
+      const int best = choose(cand, ti0, [&](int ti) {
+        cx.ti_req = ti;
+        if (dec) launch_loadvec<T, true>(L, a, cx);
+        else launch_loadvec<T, false>(L, a, cx);
+        cx.ti_req = 0;
+      }, dec ? "decompose load vector planes per workgroup" : "recompose load vector planes per workgroup", s);
+      tune[s].lv_ti[dec ? 0 : 1] = best > 0 ? best : 0;
+    }
+    // reconstruct tile
+    {
+      const bool nodal = s > 0;
+      const Map3 cmap = nodal ? nodal_map(L) : compact_map(L.m[1], L.m[2]);
+      const T *uc = (const T *)w.buf[(s + 1) % 2];
+      T *dst = s == 0 ? out : (T *)w.buf[s % 2];
+      int tj0 = 0, tk0 = 0;
+      recon_tile_rule(L, tj0, tk0);
+      std::vector<std::pair<int, int>> shapes = {{tj0, tk0}};
+      for (int64_t tk : {L.c[2], (L.c[2] + 1) / 2, (L.c[2] + 3) / 4, (int64_t)128, (int64_t)64, (int64_t)32,
+                         (int64_t)16}) {
+        if (tk < 1 || tk > L.c[2]) continue;
+        int64_t tj = 1;
+        if (!recon_tile_fits(L, 1, tk)) continue;
+        while (tj < L.c[1] && recon_tile_fits(L, tj + 1, tk)) ++tj;
+        for (int64_t t : {tj, std::max<int64_t>(1, tj / 2)}) {
+          bool dup = false;
+          for (auto &p : shapes) dup |= (p.first == (int)t && p.second == (int)tk);
+          if (!dup) shapes.push_back({(int)t, (int)tk});
+        }
+      }
+      std::vector<std::pair<double, int>> cand;
+      for (size_t q = 0; q < shapes.size(); ++q) {
+        cx.dry = true;
+        launch_reconstruct<T>(L, in, cmap, uc, dst, cx, shapes[q].first, shapes[q].second);
+        cx.dry = false;
+        const int64_t tiles = ((L.c[2] + shapes[q].second - 1) / shapes[q].second) *
+                              ((L.c[1] + shapes[q].first - 1) / shapes[q].first);
+        const double bpp = recon_bytes_per_plane(L, nodal, es, shapes[q].first, shapes[q].second);
+        cand.push_back({model_march(L.c[0], tiles, cx.slots_out, L.co[0] ? 1 : 0, cx.ti_out, bpp), (int)q});
+      }
+      const int best = choose(cand, 0, [&](int q) {
+        launch_reconstruct<T>(L, in, cmap, uc, dst, cx, shapes[q].first, shapes[q].second);
+      }, "reconstruct tile index", s);
+      if (best >= 0) {
+        tune[s].rc_tj = shapes[best].first;
+        tune[s].rc_tk = shapes[best].second;
+        report += "level " + std::to_string(s) + " reconstruct tile " + std::to_string(tune[s].rc_tj) + " x " +
+                  std::to_string(tune[s].rc_tk) + " coarse rows x columns\n";
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (!cx.ok) return false;
+  std::lock_guard<std::mutex> lk(pl.tune_mu);
+  pl.tune = tune;
+  return true;
+}
+
 }  // namespace
+
+bool enqueue_autotune(Plan &pl, bool f64, const void *in, void *out, void *ws, void *stream, std::string &err,
+                      std::string &report) {
+  hipStream_t st = (hipStream_t)stream;
+  return f64 ? autotune_t<double>(pl, (const double *)in, (double *)out, ws, st, err, report)
+             : autotune_t<float>(pl, (const float *)in, (float *)out, ws, st, err, report);
+}
 
 bool enqueue_copy_probe(const void *src, void *dst, size_t bytes, void *stream, std::string &err) {
   hipStream_t st = (hipStream_t)stream;

@@ -16,4 +16,10 @@ bool enqueue_copy_probe(const void *src, void *dst, size_t bytes, void *stream, 
 bool enqueue_recompose(const Plan &pl, bool f64, const void *in, void *out, void *ws, void *stream,
                        std::string &err);
 
+// Tune the plan's launch shapes on `stream` (synchronous: waits for the
+// timed launches) and store them in the plan.  Reads `in`; overwrites `out`
+// and `ws`.  `report` gets one line per decision.
+bool enqueue_autotune(Plan &pl, bool f64, const void *in, void *out, void *ws, void *stream, std::string &err,
+                      std::string &report);
+
 }  // namespace mgr

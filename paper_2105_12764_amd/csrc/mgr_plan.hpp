@@ -6,6 +6,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -70,6 +71,13 @@ struct TailLevel {
   int nodal[kDims], r[kDims], W[kDims], sup[kDims], tw[kDims], tinvb[kDims];
 };
 
+// Launch shapes of one level chosen by the autotuner; 0 keeps the built-in
+// rule.  None of them changes any node's arithmetic.
+struct LevelTune {
+  int lv_ti[2] = {0, 0};  // load-vector coarse planes per workgroup: decompose, recompose
+  int rc_tj = 0, rc_tk = 0, rc_ti = 0;  // reconstruct tile (coarse rows, columns) and planes
+};
+
 struct Plan {
   int ndim = 0;                 // caller's rank
   int64_t n[kDims];             // finest shape, padded to rank 3
@@ -84,6 +92,14 @@ struct Plan {
   const int64_t *dev_tail_off = nullptr;  // packed nodal offsets of the tail levels
   const double *dev_tail_dbl = nullptr;   // packed FP64 tables of the tail levels
   int tail_noff = 0, tail_ndbl = 0;
+  // autotuned launch shapes per level (empty: none); written by the
+  // autotuner, read as one snapshot per call
+  mutable std::mutex tune_mu;
+  std::vector<LevelTune> tune;
+  std::vector<LevelTune> tune_snapshot() const {
+    std::lock_guard<std::mutex> lk(tune_mu);
+    return tune;
+  }
   ~Plan();
 };
 

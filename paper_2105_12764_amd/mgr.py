@@ -75,6 +75,11 @@ def lib() -> ctypes.CDLL:
         L.mgr_last_error.restype = ctypes.c_char_p
         L.mgr_release_caches.argtypes = []
         L.mgr_release_caches.restype = None
+        L.mgr_autotune.argtypes = [ctypes.c_int, i64p, dpp, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+        L.mgr_autotune.restype = ctypes.c_int
+        L.mgr_autotune_report.argtypes = []
+        L.mgr_autotune_report.restype = ctypes.c_char_p
         fp = ctypes.POINTER(MgrField)
         L.mgr_batch_workspace_size.argtypes = [ctypes.c_int, fp, ctypes.POINTER(ctypes.c_size_t)]
         L.mgr_batch_workspace_size.restype = ctypes.c_int
@@ -279,6 +284,13 @@ def decompose_batch(batch: Batch, workspace=None, stream=None) -> None:
 def recompose_batch(batch: Batch, workspace=None, stream=None) -> None:
     """mgr_recompose_batch: every field's in (a representation) recomposed into its out."""
     _call_batch(lib().mgr_recompose_batch, batch, workspace, stream)
+
+
+def autotune(x, coords=None, nlevels: Optional[int] = None, out=None, workspace=None, stream=None) -> str:
+    """mgr_autotune for the field shape of ``x`` (values unused; ``out`` and the
+    workspace are overwritten).  Returns the library's report of its choices."""
+    _call(lib().mgr_autotune, x, coords, nlevels, out, workspace, stream)
+    return lib().mgr_autotune_report().decode()
 
 
 def release_caches() -> None:

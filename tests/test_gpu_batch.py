@@ -150,3 +150,29 @@ def test_batch_is_stream_ordered():
     torch.cuda.synchronize()
     for i, (a, b) in enumerate(zip(singles, copies)):
         assert torch.equal(a, b), f"field {i}: stream order broken"
+
+
+@pytest.mark.parametrize("shape,nonuni,dtype", [((129, 100, 77), True, np.float64),
+                                                ((97, 65, 80), False, np.float32),
+                                                ((600, 130), True, np.float64)])
+def test_autotuned_shapes_leave_results_bitwise_unchanged(shape, nonuni, dtype):
+    print(f"\n[case] autotune {shape} {np.dtype(dtype).name}", flush=True)
+    mgr.release_caches()
+    u, coords = make_input(shape, 77, nonuniform=nonuni, dtype=dtype)
+    nlev = oracle.max_levels(shape)
+    x = torch.from_numpy(u).cuda()
+    d0 = mgr.decompose(x, coords, nlev)
+    r0 = mgr.recompose(d0, coords, nlev)
+    torch.cuda.synchronize()
+    scratch = torch.empty_like(x)
+    report = mgr.autotune(x, coords, nlev, out=scratch)
+    print(report, flush=True)
+    assert "level 0" in report
+    d1 = mgr.decompose(x, coords, nlev)
+    r1 = mgr.recompose(d1, coords, nlev)
+    torch.cuda.synchronize()
+    assert torch.equal(d0, d1)
+    assert torch.equal(r0, r1)
+    ref = oracle.decompose(u.astype(np.float64), coords, nlev)
+    tol = 1e-12 if dtype == np.float64 else 1e-5
+    assert _err(d1.cpu().numpy(), ref, dtype) <= tol
