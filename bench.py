@@ -13,7 +13,9 @@ Prints one JSON line:
   cpu_baseline the FP64 CPU oracle on the same workload (one step), GB/s in
                the same unit, with the number of threads it used.
 Extra keys: the algorithmic-byte rate of the whole step, per-kernel totals,
-the FP32 mode on the same grid, the round-trip error of the timed data, and
+the FP32 mode on the same grid, the round-trip error of the timed data,
+`progressive`: the time and relative L2 error of recomposing from the k
+coarsest coefficient classes, k = 0..nlevels, and
 `batched`: 64 mixed 2-D/3-D FP32/FP64 fields decomposed and recomposed one
 field per call, with the batched entry points, and with the batch replayed
 from a HIP graph (p50/p99 ms per batch, GB/s, and whether the batched results
@@ -162,6 +164,20 @@ def run_gpu(name: str, steps: int, warmup: int, graph_steps: int = 0, tune: bool
         _log(f"[bench] {name}: graph replay {gms:.3f} ms/step")
 
     rt_err = float((r.double() - x.double()).abs().max() / x.double().abs().max())
+
+    # progressive recomposition: error and time with the nkeep coarsest classes
+    progressive = []
+    xn = float(x.double().norm())
+    for nkeep in range(nlev + 1):
+        mgr.recompose_partial(d, nkeep, coords, nlev, out=r, workspace=ws, stream=stream)
+        p0, p1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        p0.record(stream)
+        for _ in range(3):
+            mgr.recompose_partial(d, nkeep, coords, nlev, out=r, workspace=ws, stream=stream)
+        p1.record(stream)
+        torch.cuda.synchronize()
+        progressive.append({"classes_kept": nkeep, "ms": round(p0.elapsed_time(p1) / 3, 4),
+                            "rel_l2_error": float((r.double() - x.double()).norm()) / xn})
     n = int(np.prod(shape))
     esz = np.dtype(dtype).itemsize
     ms_step = wall * 1e3 / steps
@@ -183,6 +199,7 @@ def run_gpu(name: str, steps: int, warmup: int, graph_steps: int = 0, tune: bool
         "alg_GBps": alg_bytes_step / ((t_dec + t_rec) * 1e-3) / 1e9,
         "roundtrip_max_rel_err": rt_err, "kernels": kernels, "roofline": roofline,
         "graph": graph,
+        "progressive": progressive,
         "autotune": None if not tune else {
             "untuned_ms_per_step": round(untuned, 4),
             "untuned_value": round(2.0 * n * esz / (untuned * 1e-3) / 1e9, 2),
@@ -396,6 +413,7 @@ def main():
         "fp32": fp32,
         "graph": res["graph"],
         "autotune": res["autotune"],
+        "progressive": res["progressive"],
         "batched": batched,
     }
     print(json.dumps(line), flush=True)

@@ -103,6 +103,23 @@ mgr_status mgr_recompose(int ndim, const int64_t *shape,
                          void *workspace, size_t workspace_bytes,
                          void *stream);
 
+/* Progressive (partial) recomposition (Sec. II-A: the coarse representation
+ * plus the first classes of coefficients give an approximation whose error
+ * falls as classes are added).  Recomposes with only the `nkeep` coarsest
+ * coefficient classes of the representation `in` -- the coarsest values
+ * plus the coefficients of levels nlevels-1 down to nlevels-nkeep -- and the
+ * finer classes taken as zero: exactly mgr_recompose of `in` with those
+ * coefficients set to zero, without reading them.  The result has the full
+ * shape: below the kept levels it is the multilinear interpolant.
+ * nkeep in 0..nlevels (nkeep == nlevels is mgr_recompose; 0 interpolates the
+ * coarsest values).  Other arguments, ownership and errors as for
+ * mgr_recompose; nkeep out of range is MGR_ERR_INVALID_ARG. */
+mgr_status mgr_recompose_partial(int ndim, const int64_t *shape,
+                                 const double *const *coords, mgr_dtype dtype,
+                                 int nlevels, int nkeep, const void *in, void *out,
+                                 void *workspace, size_t workspace_bytes,
+                                 void *stream);
+
 /* Static English name of a status code. */
 const char *mgr_status_string(mgr_status s);
 

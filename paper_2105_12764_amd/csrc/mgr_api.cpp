@@ -159,20 +159,23 @@ mgr_status get_plan(const int64_t n[mgr::kDims], int ndim, int nlevels,
 }
 
 mgr_status run(bool dec, int ndim, const int64_t *shape, const double *const *coords, int dtype,
-               int nlevels, const void *in, void *out, void *ws, size_t ws_bytes, void *stream) {
+               int nlevels, const void *in, void *out, void *ws, size_t ws_bytes, void *stream,
+               int nkeep = -1) {
   g_last_error.clear();
   try {
     int64_t n[mgr::kDims];
     std::vector<std::vector<double>> cx;
     mgr_status s = validate(ndim, shape, coords, dtype, nlevels, in, out, ws, ws_bytes, n, cx);
     if (s != MGR_OK) return s;
+    if (nkeep != -1 && (nkeep < 0 || nkeep > nlevels))
+      return fail(MGR_ERR_INVALID_ARG, "nkeep must be in [0, nlevels]");
     std::shared_ptr<mgr::Plan> plan;
     s = get_plan(n, ndim, nlevels, cx, plan);
     if (s != MGR_OK) return s;
     std::string err;
     const bool f64 = dtype == MGR_FLOAT64;
     const bool ok = dec ? mgr::enqueue_decompose(*plan, f64, in, out, ws, stream, err)
-                        : mgr::enqueue_recompose(*plan, f64, in, out, ws, stream, err);
+                        : mgr::enqueue_recompose(*plan, f64, in, out, ws, stream, err, nkeep);
     if (!ok) return fail(MGR_ERR_DEVICE, err);
     return MGR_OK;
   } catch (const std::bad_alloc &) {
@@ -412,6 +415,17 @@ mgr_status mgr_recompose(int ndim, const int64_t *shape, const double *const *co
                          size_t workspace_bytes, void *stream) {
   return run(false, ndim, shape, coords, (int)dtype, nlevels, in, out, workspace, workspace_bytes,
              stream);
+}
+
+mgr_status mgr_recompose_partial(int ndim, const int64_t *shape, const double *const *coords,
+                                 mgr_dtype dtype, int nlevels, int nkeep, const void *in, void *out,
+                                 void *workspace, size_t workspace_bytes, void *stream) {
+  if (nkeep < 0 || nkeep > nlevels) {
+    g_last_error = "nkeep must be in [0, nlevels]";
+    return MGR_ERR_INVALID_ARG;
+  }
+  return run(false, ndim, shape, coords, (int)dtype, nlevels, in, out, workspace, workspace_bytes, stream,
+             nkeep);
 }
 
 mgr_status mgr_autotune(int ndim, const int64_t *shape, const double *const *coords, mgr_dtype dtype,

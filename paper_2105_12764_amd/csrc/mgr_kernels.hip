@@ -792,7 +792,7 @@ constexpr int RC_NE = RC_EPT * RC_THR, RC_NC = RC_EPC * RC_THR;
 
 template <typename T>
 struct ReconArgs {
-  const T *coef;  // stored coefficients (level grid positions)
+  const T *coef;  // stored coefficients (level grid positions); nullptr: all zero
   Map3 cmap;
   const T *uc;    // coarse values U_c, compact next-level grid
   T *dst;         // level grid, compact
@@ -879,8 +879,14 @@ __global__ void __launch_bounds__(RC_THR) k_reconstruct(ReconArgs<T> a) {
     for (int q = tid; q < LV_MAXP; q += RC_THR) sPO[q] = (pw0 + q < a.m0) ? a.cmap.t0[pw0 + q] : 0;
   __syncthreads();
 
-  // branch-free loads (invalid elements read a valid node and are never used)
+  // branch-free loads (invalid elements read a valid node and are never used);
+  // a level whose coefficients are dropped (partial recomposition) reads none
   auto fetchC = [&](double (&v)[RC_EPT], int64_t p) {
+    if (!a.coef) {
+#pragma unroll
+      for (int i = 0; i < RC_EPT; ++i) v[i] = 0.0;
+      return;
+    }
     const T *base = a.coef + (NODALC ? sPO[p - pw0] : p * a.m1 * a.m2);
 #pragma unroll
     for (int i = 0; i < RC_EPT; ++i) v[i] = (double)base[colC[i]];
@@ -1031,6 +1037,7 @@ struct TailArgs {
   const int64_t *off;    // packed nodal offsets
   const double *dbl;     // packed FP64 tables
   int noff, ndbl, nt;
+  int t_drop;            // recomposition: tail levels below this one take zero coefficients
 };
 
 // LDS of a tail kernel: three level grids and the packed tables.
@@ -1237,33 +1244,38 @@ __global__ void __launch_bounds__(TAIL_THR) k_tail_rec(const T *__restrict__ in,
   for (int s = a.nt - 1; s >= 0; --s) {
     const TailLevel L = a.lv[s];
     const int n = L.m[0] * L.m[1] * L.m[2];
+    const bool keep = s >= a.t_drop;  // this level's coefficients are used
     // this level's coefficients (zero at the coarse nodes), all loads in flight at once
     double cf[TAIL_PER];
 #pragma unroll
     for (int u = 0; u < TAIL_PER; ++u) {
       const int t = threadIdx.x + u * TAIL_THR;
       cf[u] = 0.0;
-      if (t < n) {
+      if (keep && t < n) {
         int i, j, k;
         tail_split(t, L.m[1], L.m[2], i, j, k);
         if (!tail_coarse_all(L, i, j, k)) cf[u] = (double)in[tail_off(L, sm.o, i, j, k)];
       }
     }
-    double *Cb = buf((ia + 1) % 3);
-#pragma unroll
-    for (int u = 0; u < TAIL_PER; ++u) {
-      const int t = threadIdx.x + u * TAIL_THR;
-      if (t < n) Cb[t] = cf[u];
-    }
-    __syncthreads();
-    const double *F = tail_project(L, sm.d, Cb, buf((ia + 2) % 3), Cb);
-    // coarse values before the correction: V - z
     double *V = buf(ia);
-    const int nc = L.c[0] * L.c[1] * L.c[2];
-    for (int t = threadIdx.x; t < nc; t += TAIL_THR) V[t] -= F[t];
-    __syncthreads();
+    int ig = (ia + 1) % 3;
+    if (keep) {
+      double *Cb = buf((ia + 1) % 3);
+#pragma unroll
+      for (int u = 0; u < TAIL_PER; ++u) {
+        const int t = threadIdx.x + u * TAIL_THR;
+        if (t < n) Cb[t] = cf[u];
+      }
+      __syncthreads();
+      const double *F = tail_project(L, sm.d, Cb, buf((ia + 2) % 3), Cb);
+      // coarse values before the correction: V - z
+      const int nc = L.c[0] * L.c[1] * L.c[2];
+      for (int t = threadIdx.x; t < nc; t += TAIL_THR) V[t] -= F[t];
+      __syncthreads();
+      ig = (F == buf((ia + 1) % 3)) ? (ia + 2) % 3 : (ia + 1) % 3;
+    }
+    __syncthreads();  // V complete (also after the gather when the first level is dropped)
     // level grid: coefficient plus interpolant of the coarse values
-    const int ig = (F == buf((ia + 1) % 3)) ? (ia + 2) % 3 : (ia + 1) % 3;
     double *G = buf(ig);
 #pragma unroll
     for (int u = 0; u < TAIL_PER; ++u) {
@@ -1620,14 +1632,14 @@ void launch_reconstruct(const Level &L, const T *coef, Map3 cmap, const T *uc, T
 // compact level grid of level tail_start, dst the caller's output.
 // Recompose: src is the caller's input, dst the compact level grid.
 template <typename T, bool DEC>
-void launch_tail(const Plan &pl, const T *src, T *dst, Ctx &cx) {
+void launch_tail(const Plan &pl, const T *src, T *dst, Ctx &cx, int t_drop = 0) {
   const int nt = pl.nlev - pl.tail_start;
   const Level &L = pl.lev[pl.tail_start];
   const double n = (double)L.m[0] * L.m[1] * L.m[2];
   // read the level grid (or the coefficients), write the coefficients (or the level grid)
   TimedLaunch tl(cx.stream, std::string(DEC ? "k_tail_dec<" : "k_tail_rec<") + tname<T>() + ">",
                  timing_enabled() ? 2.0 * n * sizeof(T) : 0.0);
-  const TailArgs ta{pl.dev_tail, pl.dev_tail_off, pl.dev_tail_dbl, pl.tail_noff, pl.tail_ndbl, nt};
+  const TailArgs ta{pl.dev_tail, pl.dev_tail_off, pl.dev_tail_dbl, pl.tail_noff, pl.tail_ndbl, nt, t_drop};
   if (DEC)
     hipLaunchKernelGGL((k_tail_dec<T>), dim3(1), dim3(TAIL_THR), 0, cx.stream, src, dst, ta);
   else
@@ -1692,8 +1704,12 @@ bool decompose_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t stre
   return cx.ok;
 }
 
+// nkeep: coefficient classes used, coarsest first (nlev: all of them); the
+// finer levels' coefficients are taken as zero, so those levels need no load
+// vector and no solve (z = 0) and only interpolate.
 template <typename T>
-bool recompose_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t stream, std::string &err) {
+bool recompose_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t stream, std::string &err,
+                 int nkeep) {
   Ctx cx{stream, &err};
   const int64_t total = pl.n[0] * pl.n[1] * pl.n[2];
   if (pl.nlev == 0) {
@@ -1705,11 +1721,12 @@ bool recompose_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t stre
   }
   Workspace w = carve(pl, ws, sizeof(T));
   const int st = std::min(pl.tail_start, pl.nlev);
+  const int drop = pl.nlev - std::max(0, std::min(nkeep, pl.nlev));  // levels below take zero coefficients
   T *V = nullptr;
   if (st < pl.nlev) {
     // the coarsest levels in one workgroup, up to the level grid of level st
     V = (st == 0) ? out : (T *)w.buf[st % 2];
-    launch_tail<T, false>(pl, in, V, cx);
+    launch_tail<T, false>(pl, in, V, cx, std::max(0, drop - st));
   } else {
     // coarsest grid values, gathered compactly
     const Level &Lc = pl.lev[pl.nlev];
@@ -1725,6 +1742,14 @@ bool recompose_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t stre
     const Level &L = pl.lev[s];
     const LevelTune lt = s < (int)tune.size() ? tune[s] : LevelTune{};
     const Map3 cmap = (s == 0) ? compact_map(pl.n[1], pl.n[2]) : nodal_map(L);
+    T *dst = (s == 0) ? out : (T *)w.buf[s % 2];
+    if (s < drop) {  // dropped class: the level grid is the interpolant of U_c = V
+      cx.ti_req = lt.rc_ti;
+      launch_reconstruct<T>(L, (const T *)nullptr, cmap, V, dst, cx, lt.rc_tj, lt.rc_tk);
+      cx.ti_req = 0;
+      V = dst;
+      continue;
+    }
     LoadArgs<T> a{};
     a.src = in;
     a.smap = cmap;
@@ -1736,7 +1761,6 @@ bool recompose_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t stre
     ep.mode = EPI_SUB_COMPACT;
     ep.dst = V;
     solve_all<T>(w.F, L, ep, cx);
-    T *dst = (s == 0) ? out : (T *)w.buf[s % 2];
     cx.ti_req = lt.rc_ti;
     launch_reconstruct<T>(L, in, cmap, V, dst, cx, lt.rc_tj, lt.rc_tk);
     cx.ti_req = 0;
@@ -1973,10 +1997,11 @@ bool enqueue_decompose(const Plan &pl, bool f64, const void *in, void *out, void
 }
 
 bool enqueue_recompose(const Plan &pl, bool f64, const void *in, void *out, void *ws, void *stream,
-                       std::string &err) {
+                       std::string &err, int nkeep) {
   hipStream_t st = (hipStream_t)stream;
-  return f64 ? recompose_t<double>(pl, (const double *)in, (double *)out, ws, st, err)
-             : recompose_t<float>(pl, (const float *)in, (float *)out, ws, st, err);
+  if (nkeep < 0) nkeep = pl.nlev;
+  return f64 ? recompose_t<double>(pl, (const double *)in, (double *)out, ws, st, err, nkeep)
+             : recompose_t<float>(pl, (const float *)in, (float *)out, ws, st, err, nkeep);
 }
 
 }  // namespace mgr

@@ -13,8 +13,9 @@ namespace mgr {
 bool enqueue_decompose(const Plan &pl, bool f64, const void *in, void *out, void *ws, void *stream,
                        std::string &err);
 bool enqueue_copy_probe(const void *src, void *dst, size_t bytes, void *stream, std::string &err);
+// nkeep: coefficient classes used, coarsest first (< 0: all).
 bool enqueue_recompose(const Plan &pl, bool f64, const void *in, void *out, void *ws, void *stream,
-                       std::string &err);
+                       std::string &err, int nkeep = -1);
 
 // Tune the plan's launch shapes on `stream` (synchronous: waits for the
 // timed launches) and store them in the plan.  Reads `in`; overwrites `out`

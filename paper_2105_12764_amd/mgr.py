@@ -75,6 +75,10 @@ def lib() -> ctypes.CDLL:
         L.mgr_last_error.restype = ctypes.c_char_p
         L.mgr_release_caches.argtypes = []
         L.mgr_release_caches.restype = None
+        L.mgr_recompose_partial.argtypes = [ctypes.c_int, i64p, dpp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                            ctypes.c_void_p]
+        L.mgr_recompose_partial.restype = ctypes.c_int
         L.mgr_autotune.argtypes = [ctypes.c_int, i64p, dpp, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
         L.mgr_autotune.restype = ctypes.c_int
@@ -284,6 +288,20 @@ def decompose_batch(batch: Batch, workspace=None, stream=None) -> None:
 def recompose_batch(batch: Batch, workspace=None, stream=None) -> None:
     """mgr_recompose_batch: every field's in (a representation) recomposed into its out."""
     _call_batch(lib().mgr_recompose_batch, batch, workspace, stream)
+
+
+def recompose_partial(x, nkeep: int, coords=None, nlevels: Optional[int] = None, out=None, workspace=None,
+                      stream=None):
+    """mgr_recompose_partial: recompose from the coarsest values and the ``nkeep``
+    coarsest coefficient classes (finer classes taken as zero)."""
+    import torch
+    if nlevels is None:
+        nlevels = max_levels(tuple(x.shape))
+    L = lib()
+
+    def fn(nd, sh, carr, dt, nl, a, b, w, wb, st):
+        return L.mgr_recompose_partial(nd, sh, carr, dt, nl, int(nkeep), a, b, w, wb, st)
+    return _call(fn, x, coords, nlevels, out, workspace, stream)
 
 
 def autotune(x, coords=None, nlevels: Optional[int] = None, out=None, workspace=None, stream=None) -> str:

@@ -147,3 +147,14 @@ def test_batch_rejects_bad_fields_before_any_device_call(fn):
     # workspace too small, or overlapping a field
     assert call([ok], wsb=16) == mgr.MGR_ERR_WORKSPACE
     assert call([ok], ws=(1 << 30)) == E
+
+
+def test_partial_recompose_rejects_nkeep_out_of_range():
+    L = mgr.lib()
+    sh = mgr._shape((9, 9, 9))
+    for nkeep in (-1, 3):
+        s = L.mgr_recompose_partial(3, sh, None, mgr.MGR_FLOAT64, 2, nkeep, ctypes.c_void_p(1 << 30),
+                                    ctypes.c_void_p(2 << 30), ctypes.c_void_p(1 << 34),
+                                    ctypes.c_size_t(1 << 30), None)
+        assert s == mgr.MGR_ERR_INVALID_ARG
+        assert "nkeep" in mgr.last_error()
