@@ -120,6 +120,31 @@ mgr_status mgr_recompose_partial(int ndim, const int64_t *shape,
                                  void *workspace, size_t workspace_bytes,
                                  void *stream);
 
+/* Class-contiguous layout of a nodal representation (the paper's reordered
+ * layout, Sec. III-C, used here as an exchange format for progressive
+ * access): first the coarsest grid's values, then the coefficient class of
+ * each level -- the level's nodes that are not in the next coarser grid --
+ * from the coarsest level to the finest, each in C order of its level grid.
+ * A prefix of the buffer that ends at a class boundary therefore holds the
+ * coarse representation plus the coarsest classes; importing the prefix with
+ * the rest zero and recomposing equals mgr_recompose_partial.
+ * mgr_export_classes reorders the nodal array `in` into `out`;
+ * mgr_import_classes is its inverse.  Both arrays hold prod(shape) elements
+ * of dtype (device, caller-owned, not overlapping); no workspace.  Shape,
+ * dtype and nlevels as for mgr_decompose (coordinates do not matter).
+ * Stream-ordered; errors as for mgr_decompose. */
+mgr_status mgr_export_classes(int ndim, const int64_t *shape, mgr_dtype dtype, int nlevels,
+                              const void *in, void *out, void *stream);
+
+/* Element counts of the class-contiguous layout's parts, in buffer order:
+ * sizes[0] = the coarsest grid's nodes, sizes[1 + t] = the class of level
+ * nlevels-1-t (coarsest class first); nlevels + 1 entries in all, written to
+ * the caller's host array.  Host only.  MGR_ERR_INVALID_ARG for a bad shape
+ * or level count or sizes == NULL. */
+mgr_status mgr_class_sizes(int ndim, const int64_t *shape, int nlevels, int64_t *sizes);
+mgr_status mgr_import_classes(int ndim, const int64_t *shape, mgr_dtype dtype, int nlevels,
+                              const void *in, void *out, void *stream);
+
 /* Static English name of a status code. */
 const char *mgr_status_string(mgr_status s);
 

@@ -428,6 +428,75 @@ mgr_status mgr_recompose_partial(int ndim, const int64_t *shape, const double *c
              nkeep);
 }
 
+static mgr_status run_classes(bool export_, int ndim, const int64_t *shape, mgr_dtype dtype, int nlevels,
+                              const void *in, void *out, void *stream) {
+  g_last_error.clear();
+  try {
+    int64_t n[mgr::kDims];
+    std::string why;
+    if (!pad_shape(ndim, shape, n, why)) return fail(MGR_ERR_INVALID_ARG, why);
+    if (dtype != MGR_FLOAT32 && dtype != MGR_FLOAT64)
+      return fail(MGR_ERR_INVALID_ARG, "dtype must be MGR_FLOAT32 or MGR_FLOAT64");
+    const int ml = mgr::max_levels3(n);
+    if (nlevels < 0 || nlevels > ml)
+      return fail(MGR_ERR_INVALID_ARG, "nlevels must be in [0, " + std::to_string(ml) + "]");
+    if (!in || !out) return fail(MGR_ERR_INVALID_ARG, "in and out must be non-NULL device pointers");
+    const size_t bytes = (size_t)(n[0] * n[1] * n[2]) * (dtype == MGR_FLOAT64 ? 8 : 4);
+    if (overlaps(in, bytes, out, bytes)) return fail(MGR_ERR_INVALID_ARG, "in and out overlap");
+    // the layout depends on the level structure only: the plan of uniform coordinates
+    std::vector<std::vector<double>> cx(mgr::kDims);
+    for (int k = 0; k < mgr::kDims; ++k) {
+      cx[k].resize(n[k]);
+      for (int64_t i = 0; i < n[k]; ++i) cx[k][i] = (double)i;
+    }
+    std::shared_ptr<mgr::Plan> plan;
+    mgr_status s = get_plan(n, ndim, nlevels, cx, plan);
+    if (s != MGR_OK) return s;
+    std::string err;
+    if (!mgr::enqueue_classes(*plan, dtype == MGR_FLOAT64, export_, in, out, stream, err))
+      return fail(MGR_ERR_DEVICE, err);
+    return MGR_OK;
+  } catch (const std::bad_alloc &) {
+    return fail(MGR_ERR_OUT_OF_MEMORY, "host allocation failed");
+  } catch (...) {
+    return fail(MGR_ERR_DEVICE, "unexpected internal failure");
+  }
+}
+
+mgr_status mgr_class_sizes(int ndim, const int64_t *shape, int nlevels, int64_t *sizes) {
+  g_last_error.clear();
+  int64_t n[mgr::kDims];
+  std::string why;
+  if (!pad_shape(ndim, shape, n, why)) return fail(MGR_ERR_INVALID_ARG, why);
+  const int ml = mgr::max_levels3(n);
+  if (nlevels < 0 || nlevels > ml)
+    return fail(MGR_ERR_INVALID_ARG, "nlevels must be in [0, " + std::to_string(ml) + "]");
+  if (!sizes) return fail(MGR_ERR_INVALID_ARG, "sizes is NULL");
+  // node counts of the level grids: a dimension of m >= 3 nodes keeps m/2 + 1
+  std::vector<int64_t> grid(nlevels + 1);
+  int64_t m[mgr::kDims] = {n[0], n[1], n[2]};
+  for (int s = 0; s <= nlevels; ++s) {
+    grid[s] = m[0] * m[1] * m[2];
+    for (int k = 0; k < mgr::kDims; ++k) m[k] = mgr::coarse_count(m[k]);
+  }
+  sizes[0] = grid[nlevels];
+  for (int t = 0; t < nlevels; ++t) {
+    const int s = nlevels - 1 - t;
+    sizes[1 + t] = grid[s] - grid[s + 1];
+  }
+  return MGR_OK;
+}
+
+mgr_status mgr_export_classes(int ndim, const int64_t *shape, mgr_dtype dtype, int nlevels, const void *in,
+                              void *out, void *stream) {
+  return run_classes(true, ndim, shape, dtype, nlevels, in, out, stream);
+}
+
+mgr_status mgr_import_classes(int ndim, const int64_t *shape, mgr_dtype dtype, int nlevels, const void *in,
+                              void *out, void *stream) {
+  return run_classes(false, ndim, shape, dtype, nlevels, in, out, stream);
+}
+
 mgr_status mgr_autotune(int ndim, const int64_t *shape, const double *const *coords, mgr_dtype dtype,
                         int nlevels, const void *in, void *out, void *workspace, size_t workspace_bytes,
                         void *stream) {

@@ -1000,6 +1000,36 @@ __global__ void __launch_bounds__(256) k_gather(const T *src, Map3 smap, T *dst,
   }
 }
 
+// Class-contiguous layout of a nodal representation: the coarsest grid's
+// values, then each level's coefficient class (its nodes that are not in the
+// next coarser grid) from the coarsest level to the finest, each in C order
+// of its level grid.  A node's place in its class is its level-grid index
+// minus the number of nodes before it that belong to the coarser grid, which
+// has a closed form: coarse positions along a coarsened dimension are the
+// even ones and the last, so (x + 1) / 2 of them precede position x.
+// EXPORT gathers the class from the nodal array; otherwise it scatters back.
+template <typename T, bool EXPORT>
+__global__ void __launch_bounds__(256) k_classes(const T *__restrict__ src, T *__restrict__ dst, Map3 nmap,
+                                                 int64_t m0, int64_t m1, int64_t m2, int64_t c1, int64_t c2,
+                                                 int co0, int co1, int co2, int64_t class_off, int coarsest) {
+  const int64_t n = m0 * m1 * m2;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t k = e % m2, row = e / m2, j = row % m1, i = row / m1;
+    int64_t pos = e;
+    if (!coarsest) {
+      const bool ci = !co0 || (i % 2 == 0) || i == m0 - 1;
+      const bool cj = !co1 || (j % 2 == 0) || j == m1 - 1;
+      const bool ck = !co2 || (k % 2 == 0) || k == m2 - 1;
+      if (ci && cj && ck) continue;  // belongs to the coarser grid
+      const int64_t ni = co0 ? (i + 1) / 2 : i, nj = co1 ? (j + 1) / 2 : j, nk = co2 ? (k + 1) / 2 : k;
+      pos = e - (ni * c1 * c2 + (ci ? nj * c2 + (cj ? nk : 0) : 0));
+    }
+    const int64_t node = moff(nmap, i, j, k);
+    if (EXPORT) dst[class_off + pos] = src[node];
+    else dst[node] = src[class_off + pos];
+  }
+}
+
 // Streaming copy of 16-byte words, four independent loads in flight per
 // thread (the single-pass bandwidth probe).
 __global__ void __launch_bounds__(256) k_copy_probe(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
@@ -1964,7 +1994,37 @@ bool autotune_t(Plan &pl, const T *in, T *out, void *ws, hipStream_t stream, std
   return true;
 }
 
+template <typename T, bool EXPORT>
+bool classes_t(const Plan &pl, const T *src, T *dst, hipStream_t stream, std::string &err) {
+  Ctx cx{stream, &err};
+  int64_t off = 0;
+  for (int s = pl.nlev; s >= 0 && cx.ok; --s) {  // coarsest grid first, then classes coarse to fine
+    const Level &L = pl.lev[s];
+    const bool coarsest = s == pl.nlev;
+    const int64_t n = L.m[0] * L.m[1] * L.m[2];
+    const int64_t nc = coarsest ? 0 : L.c[0] * L.c[1] * L.c[2];
+    TimedLaunch tl(stream, std::string(EXPORT ? "k_classes<" : "k_classes_import<") + tname<T>() + ">",
+                   timing_enabled() ? 2.0 * (double)(n - nc) * sizeof(T) : 0.0);
+    hipLaunchKernelGGL((k_classes<T, EXPORT>), dim3((unsigned)grid_1d(n, 256)), dim3(256), 0, stream, src, dst,
+                       nodal_map(L), L.m[0], L.m[1], L.m[2], L.c[1], L.c[2], L.co[0] ? 1 : 0, L.co[1] ? 1 : 0,
+                       L.co[2] ? 1 : 0, off, coarsest ? 1 : 0);
+    cx.check("k_classes launch");
+    off += n - nc;
+  }
+  return cx.ok;
+}
+
 }  // namespace
+
+bool enqueue_classes(const Plan &pl, bool f64, bool export_, const void *src, void *dst, void *stream,
+                     std::string &err) {
+  hipStream_t st = (hipStream_t)stream;
+  if (f64)
+    return export_ ? classes_t<double, true>(pl, (const double *)src, (double *)dst, st, err)
+                   : classes_t<double, false>(pl, (const double *)src, (double *)dst, st, err);
+  return export_ ? classes_t<float, true>(pl, (const float *)src, (float *)dst, st, err)
+                 : classes_t<float, false>(pl, (const float *)src, (float *)dst, st, err);
+}
 
 bool enqueue_autotune(Plan &pl, bool f64, const void *in, void *out, void *ws, void *stream, std::string &err,
                       std::string &report) {

@@ -17,6 +17,11 @@ bool enqueue_copy_probe(const void *src, void *dst, size_t bytes, void *stream, 
 bool enqueue_recompose(const Plan &pl, bool f64, const void *in, void *out, void *ws, void *stream,
                        std::string &err, int nkeep = -1);
 
+// Reorder a nodal representation into class-contiguous order (export) or
+// back (import); src and dst hold prod(shape) elements each.
+bool enqueue_classes(const Plan &pl, bool f64, bool export_, const void *src, void *dst, void *stream,
+                     std::string &err);
+
 // Tune the plan's launch shapes on `stream` (synchronous: waits for the
 // timed launches) and store them in the plan.  Reads `in`; overwrites `out`
 // and `ws`.  `report` gets one line per decision.

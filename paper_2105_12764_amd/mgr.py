@@ -79,6 +79,12 @@ def lib() -> ctypes.CDLL:
                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                             ctypes.c_void_p]
         L.mgr_recompose_partial.restype = ctypes.c_int
+        L.mgr_class_sizes.argtypes = [ctypes.c_int, i64p, ctypes.c_int, i64p]
+        L.mgr_class_sizes.restype = ctypes.c_int
+        for fn in (L.mgr_export_classes, L.mgr_import_classes):
+            fn.argtypes = [ctypes.c_int, i64p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                           ctypes.c_void_p]
+            fn.restype = ctypes.c_int
         L.mgr_autotune.argtypes = [ctypes.c_int, i64p, dpp, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
         L.mgr_autotune.restype = ctypes.c_int
@@ -302,6 +308,48 @@ def recompose_partial(x, nkeep: int, coords=None, nlevels: Optional[int] = None,
     def fn(nd, sh, carr, dt, nl, a, b, w, wb, st):
         return L.mgr_recompose_partial(nd, sh, carr, dt, nl, int(nkeep), a, b, w, wb, st)
     return _call(fn, x, coords, nlevels, out, workspace, stream)
+
+
+def _classes(fn, x, nlevels, out, stream):
+    import torch
+    if not (x.is_cuda and x.is_contiguous()):
+        raise ValueError("input must be a contiguous HIP tensor")
+    shape = tuple(x.shape)
+    if nlevels is None:
+        nlevels = max_levels(shape)
+    if out is None:
+        out = torch.empty_like(x)
+    if stream is None:
+        stream = torch.cuda.current_stream(x.device)
+    with torch.cuda.device(x.device):
+        s = fn(len(shape), _shape(shape), _dtype_code(x.dtype), int(nlevels), ctypes.c_void_p(x.data_ptr()),
+               ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(stream.cuda_stream))
+    if s != MGR_OK:
+        raise MgrError(s, last_error())
+    return out
+
+
+def export_classes(rep, nlevels: Optional[int] = None, out=None, stream=None):
+    """mgr_export_classes: nodal representation -> class-contiguous order."""
+    return _classes(lib().mgr_export_classes, rep, nlevels, out, stream)
+
+
+def import_classes(buf, nlevels: Optional[int] = None, out=None, stream=None):
+    """mgr_import_classes: class-contiguous order -> nodal representation."""
+    return _classes(lib().mgr_import_classes, buf, nlevels, out, stream)
+
+
+def class_sizes(shape, nlevels: Optional[int] = None):
+    """mgr_class_sizes: element counts of the class-contiguous layout's parts,
+    the coarsest grid first, then the classes from the coarsest level to the
+    finest."""
+    if nlevels is None:
+        nlevels = max_levels(shape)
+    out = (ctypes.c_int64 * (int(nlevels) + 1))()
+    s = lib().mgr_class_sizes(len(shape), _shape(shape), int(nlevels), out)
+    if s != MGR_OK:
+        raise MgrError(s, last_error())
+    return [int(v) for v in out]
 
 
 def autotune(x, coords=None, nlevels: Optional[int] = None, out=None, workspace=None, stream=None) -> str:

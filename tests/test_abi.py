@@ -158,3 +158,32 @@ def test_partial_recompose_rejects_nkeep_out_of_range():
                                     ctypes.c_size_t(1 << 30), None)
         assert s == mgr.MGR_ERR_INVALID_ARG
         assert "nkeep" in mgr.last_error()
+
+
+@pytest.mark.parametrize("shape", [(513, 513, 513), (66, 70, 45), (300, 41), (1000,), (2, 2, 2), (5, 2, 9)])
+def test_class_sizes_follow_the_level_grids(shape):
+    nlev = mgr.max_levels(shape)
+    sizes = mgr.class_sizes(shape, nlev)
+    assert sum(sizes) == int(np.prod(shape))
+    # level grids from the coarsening rule written out here: even positions and the last
+    dims = [list(range(n)) for n in shape]
+    grids = []
+    for _ in range(nlev + 1):
+        grids.append(int(np.prod([len(d) for d in dims])))
+        dims = [[p for i, p in enumerate(d) if i % 2 == 0 or i == len(d) - 1] if len(d) >= 3 else d
+                for d in dims]
+    assert sizes[0] == grids[nlev]
+    assert sizes[1:] == [grids[s] - grids[s + 1] for s in range(nlev - 1, -1, -1)]
+    with pytest.raises(mgr.MgrError):
+        mgr.class_sizes(shape, nlev + 1)
+
+
+def test_class_export_rejects_bad_arguments_without_a_device():
+    L = mgr.lib()
+    sh = mgr._shape((9, 9, 9))
+    E = mgr.MGR_ERR_INVALID_ARG
+    for fn in (L.mgr_export_classes, L.mgr_import_classes):
+        assert fn(3, sh, mgr.MGR_FLOAT64, 4, ctypes.c_void_p(1 << 30), ctypes.c_void_p(2 << 30), None) == E
+        assert fn(3, sh, 5, 2, ctypes.c_void_p(1 << 30), ctypes.c_void_p(2 << 30), None) == E
+        assert fn(3, sh, mgr.MGR_FLOAT64, 2, ctypes.c_void_p(1 << 30), ctypes.c_void_p((1 << 30) + 8), None) == E
+        assert fn(3, sh, mgr.MGR_FLOAT64, 2, None, ctypes.c_void_p(2 << 30), None) == E

@@ -74,3 +74,65 @@ def test_partial_recompose_matches_oracle_with_dropped_classes(shape, nonuni, dt
         print(f"  nkeep {nkeep}: vs oracle {e:.2e}, relative L2 error to the field {err_u:.3e}")
     for a, b in zip(errs, errs[1:]):
         assert b <= a * (1 + 1e-9) + 1e-12, errs
+
+
+def _classes_reference(rep, nlev):
+    """Class-contiguous order written out from its definition: the coarsest
+    grid's values, then per level (coarsest first) the nodes of its grid that
+    are not in the next coarser grid, in C order of the level grid."""
+    parts = []
+    grids = [tuple(_level_positions(n, s) for n in rep.shape) for s in range(nlev + 1)]
+    parts.append(rep[np.ix_(*grids[nlev])].ravel())
+    for s in range(nlev - 1, -1, -1):
+        g, c = grids[s], grids[s + 1]
+        vals = rep[np.ix_(*g)]
+        inside = np.ones(vals.shape, dtype=bool)
+        for k, (gk, ck) in enumerate(zip(g, c)):
+            sh = [1] * rep.ndim
+            sh[k] = len(gk)
+            inside &= np.isin(gk, ck).reshape(sh)
+        parts.append(vals[~inside])
+    return np.concatenate(parts)
+
+
+@pytest.mark.parametrize("shape,nlev,dtype", [((65, 65, 65), None, np.float64),
+                                              ((66, 70, 45), 5, np.float32),
+                                              ((300, 41), None, np.float64),
+                                              ((1000,), 4, np.float64),
+                                              ((5, 2, 9), None, np.float64),
+                                              ((9, 9, 9), 0, np.float32)])
+def test_class_export_layout_and_import(shape, nlev, dtype):
+    print(f"\n[case] class export {shape} nlev={nlev} {np.dtype(dtype).name}", flush=True)
+    if nlev is None:
+        nlev = oracle.max_levels(shape)
+    rng = np.random.default_rng(5)
+    rep = rng.standard_normal(shape).astype(dtype)
+    x = torch.from_numpy(rep).cuda()
+    buf = mgr.export_classes(x, nlev)
+    back = mgr.import_classes(buf, nlev)
+    torch.cuda.synchronize()
+    ref = _classes_reference(rep, nlev)
+    assert np.array_equal(buf.cpu().numpy().ravel(), ref)
+    assert torch.equal(back, x)
+    sizes = mgr.class_sizes(shape, nlev)
+    assert sum(sizes) == x.numel()
+
+
+@pytest.mark.parametrize("shape,nonuni", [((65, 65, 65), False), ((66, 70, 45), True)])
+def test_class_prefix_recomposes_like_partial_recompose(shape, nonuni):
+    print(f"\n[case] class prefix vs partial recompose {shape}", flush=True)
+    u, coords = make_input(shape, 21, nonuniform=nonuni, dtype=np.float64)
+    nlev = oracle.max_levels(shape)
+    x = torch.from_numpy(u).cuda()
+    d = mgr.decompose(x, coords, nlev)
+    buf = mgr.export_classes(d, nlev)
+    sizes = mgr.class_sizes(shape, nlev)
+    for nkeep in range(nlev + 1):
+        prefix = sum(sizes[:1 + nkeep])
+        cut = torch.zeros_like(buf)
+        cut.view(-1)[:prefix] = buf.view(-1)[:prefix]
+        rep = mgr.import_classes(cut, nlev)
+        full = mgr.recompose(rep, coords, nlev)
+        part = mgr.recompose_partial(d, nkeep, coords, nlev)
+        torch.cuda.synchronize()
+        assert torch.equal(full, part), nkeep
