@@ -19,7 +19,9 @@ coarsest coefficient classes, k = 0..nlevels, and
 `batched`: 64 mixed 2-D/3-D FP32/FP64 fields decomposed and recomposed one
 field per call, with the batched entry points, and with the batch replayed
 from a HIP graph (p50/p99 ms per batch, GB/s, and whether the batched results
-are bitwise those of the single calls).
+are bitwise those of the single calls), and
+`service`: Poisson streams of mixed-size decompose/recompose requests served
+under an HBM budget (p50/p99 latency, GB/s) next to the plain path.
 """
 from __future__ import annotations
 
@@ -308,6 +310,116 @@ def run_batched(reps: int = 10, warmup: int = 2, nfields: int = 64):
     return res
 
 
+def run_service(nreq: int = 300, rates=(50, 100, 200, 500, 1000, 2000), budget_gb: float = 64.0,
+                nstreams: int = 4, pool: int = 4, tight_gb: float = 4.0):
+    """The refactoring service (mgr_service_*) under Poisson arrivals.
+
+    Requests come from synth.service_requests (3-D cubes, side log-uniform
+    over [17, 513], FP32:FP64 = 3:1, decompose:recompose = 1:1, seed 5000).
+    Every (side, dtype) has one seeded input field and `pool` output buffers
+    used in turn (a buffer is reused only after its previous request is done).
+    Latency is submit -> completion seen by the service's waiter thread.
+    Also timed: the plain path (the same requests back to back, one call per
+    request on one stream) and the service with every request submitted at
+    once, under the stated budget and under a tight one."""
+    import torch
+
+    from paper_2105_12764_amd import mgr
+    from paper_2105_12764_amd.synth import SERVICE_SIDES, service_requests
+
+    dev = torch.device("cuda:0")
+    reqs = service_requests(nreq)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(5000)
+    fields, outs = {}, {}
+    for side in SERVICE_SIDES:
+        for dt in (torch.float32, torch.float64):
+            fields[(side, dt)] = torch.randn((side,) * 3, dtype=dt, device=dev, generator=gen)
+            outs[(side, dt)] = [torch.empty((side,) * 3, dtype=dt, device=dev) for _ in range(pool)]
+    tdt = [torch.float32 if r[1] == np.float32 else torch.float64 for r in reqs]
+    nbytes = sum(2 * fields[(r[0], d)].numel() * fields[(r[0], d)].element_size() for r, d in zip(reqs, tdt))
+    stream = torch.cuda.current_stream(dev)
+    ws = torch.empty(mgr.workspace_size((513,) * 3, torch.float64, mgr.max_levels((513,) * 3)) + 1,
+                     dtype=torch.uint8, device=dev)
+
+    def plain():
+        for i, (r, d) in enumerate(zip(reqs, tdt)):
+            x, y = fields[(r[0], d)], outs[(r[0], d)][i % pool]
+            (mgr.recompose if r[2] else mgr.decompose)(x, None, None, out=y, workspace=ws, stream=stream)
+
+    _log(f"[bench] service: {nreq} requests, {nbytes / 1e9:.2f} GB moved per pass")
+    plain()  # builds every plan
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    plain()
+    b.record(stream)
+    b.synchronize()
+    t_plain = a.elapsed_time(b)
+
+    def serve(rate, budget):
+        svc = mgr.Service(int(budget), nstreams=nstreams)
+        last = {}
+        tickets, t_sub, lags = [], [], []
+        t0 = time.perf_counter()
+        t_arr = 0.0
+        for i, (r, d) in enumerate(zip(reqs, tdt)):
+            if rate:
+                t_arr += r[3] / rate
+                while True:
+                    wait = t0 + t_arr - time.perf_counter()
+                    if wait <= 0:
+                        break
+                    if wait > 2e-4:
+                        time.sleep(wait - 1e-4)
+            key, slot = (r[0], d), i % pool
+            prev = last.get((key, slot))
+            while prev is not None and not svc.result(prev)[0]:
+                time.sleep(5e-5)  # that output buffer's previous request is still running
+            ts = time.perf_counter()
+            lags.append(ts - (t0 + t_arr) if rate else 0.0)
+            t = svc.submit(bool(r[2]), fields[key], outs[key][slot], None, None)
+            last[(key, slot)] = t
+            tickets.append(t)
+            t_sub.append(ts)
+        svc.wait_all()
+        res = [svc.result(t) for t in tickets]
+        svc.close()
+        bad = sum(1 for r in res if not r[0] or r[1] != mgr.MGR_OK)
+        lat = [r[3] for r in res]
+        que = [r[2] for r in res]
+        span = max(ts + r[3] * 1e-3 for ts, r in zip(t_sub, res)) - min(t_sub)
+        out = {"latency_ms": {"p50": round(_pct(lat, 0.5), 4), "p99": round(_pct(lat, 0.99), 4),
+                              "max": round(max(lat), 4)},
+               "queue_ms": {"p50": round(_pct(que, 0.5), 4), "p99": round(_pct(que, 0.99), 4)},
+               "GBps": round(nbytes / span / 1e9, 1), "span_s": round(span, 4), "failed": bad}
+        if rate:
+            out["offered_GBps"] = round(nbytes * rate / sum(r[3] for r in reqs) / 1e9, 1)
+            out["arrival_lag_ms_p99"] = round(1e3 * _pct(lags, 0.99), 4)
+        return out
+
+    budget = budget_gb * 1e9
+    sat = serve(None, budget)
+    _log(f"[bench] service: plain path {nbytes / (t_plain * 1e-3) / 1e9:.1f} GB/s, service all-at-once "
+         f"{sat['GBps']} GB/s, p99 {sat['latency_ms']['p99']} ms")
+    tight = serve(None, tight_gb * 1e9)
+    per_rate = {}
+    for rate in rates:
+        per_rate[str(rate)] = serve(rate, budget)
+        _log(f"[bench] service: {rate}/s p50 {per_rate[str(rate)]['latency_ms']['p50']} ms, "
+             f"p99 {per_rate[str(rate)]['latency_ms']['p99']} ms")
+    res = {"requests": nreq, "seed": 5000,
+           "mix": "3-D cubes, side log-uniform over [17, 513] (11 geometric sides), FP32:FP64 = 3:1, "
+                  "decompose:recompose = 1:1, all levels, built-in launch shapes",
+           "bytes_per_pass": nbytes, "budget_GB": budget_gb, "streams": nstreams,
+           "plain_one_call_per_request": {"ms": round(t_plain, 3),
+                                          "GBps": round(nbytes / (t_plain * 1e-3) / 1e9, 1)},
+           "all_at_once": sat, f"all_at_once_budget_{tight_gb:g}GB": tight, "poisson": per_rate}
+    del fields, outs, ws
+    torch.cuda.empty_cache()
+    return res
+
+
 def probe_bandwidth(nbytes: int = 1 << 30, reps: int = 10):
     """Achievable single-pass bandwidth: the library's streaming copy probe
     (one read + one write of every byte), 2 * bytes / time."""
@@ -364,6 +476,9 @@ def main():
     ap.add_argument("--graph-steps", type=int, default=0,
                     help="also time this many replays of the step captured as a HIP graph")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-field batch")
+    ap.add_argument("--no-service", action="store_true", help="skip the service sweep")
+    ap.add_argument("--service-requests", type=int, default=300,
+                    help="requests per arrival rate in the service sweep")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -381,6 +496,7 @@ def main():
                                      "roundtrip_max_rel_err", "roofline")}
         fp32["untuned_value"] = r32["autotune"]["untuned_value"] if r32.get("autotune") else None
     batched = None if args.no_batch else run_batched()
+    service = None if args.no_service else run_service(args.service_requests)
     cpu = None if args.no_cpu_baseline else cpu_baseline(u, coords, nlev)
 
     line = {
@@ -415,6 +531,7 @@ def main():
         "autotune": res["autotune"],
         "progressive": res["progressive"],
         "batched": batched,
+        "service": service,
     }
     print(json.dumps(line), flush=True)
 

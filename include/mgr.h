@@ -228,6 +228,53 @@ mgr_status mgr_decompose_batch(int nfields, const mgr_field *fields, void *works
 mgr_status mgr_recompose_batch(int nfields, const mgr_field *fields, void *workspace,
                                size_t workspace_bytes, void *stream);
 
+/* ---- Refactoring service ----------------------------------------------------
+ * A stream of independent decompose / recompose requests on caller-owned
+ * device buffers, admitted first-in first-out by HBM footprint: a request
+ * starts only while the in-flight footprint -- input + output + workspace
+ * bytes of every admitted, unfinished request -- stays within the budget.
+ * Workspace comes from an arena allocated at creation (half the budget plus
+ * 1 MiB, at most the budget), so requests allocate nothing.  The operations
+ * are those of mgr_decompose / mgr_recompose; the service is the stream of
+ * many independent fields refactored inside a workflow (Sec. III-F, IV)
+ * with admission by memory footprint.  Admitted requests run on
+ * `nstreams` internal streams (default priority), least-loaded first; one
+ * host thread per stream retires them in order.  All calls on one service
+ * from the device current at creation.  Thread-safe. */
+typedef struct mgr_service mgr_service;
+
+/* Create a service on the current device.  budget_bytes >= 4096;
+ * nstreams in 1..16.  MGR_ERR_OUT_OF_MEMORY if the arena cannot be
+ * allocated, MGR_ERR_DEVICE without a usable device. */
+mgr_status mgr_service_create(size_t budget_bytes, int nstreams, mgr_service **svc);
+
+/* Submit one request (recompose != 0: recomposition).  Arguments as for
+ * mgr_decompose minus the workspace and stream; coordinates are copied.
+ * `in` must stay unchanged and `out` unused by the caller until the request
+ * is done.  Returns at once with a ticket (1, 2, ...); the request waits if
+ * it does not fit yet.  MGR_ERR_UNSUPPORTED for a request whose footprint
+ * exceeds the budget (or its workspace the arena); argument errors as for
+ * mgr_decompose are reported by mgr_service_result. */
+mgr_status mgr_service_submit(mgr_service *svc, int recompose, int ndim, const int64_t *shape,
+                              const double *const *coords, mgr_dtype dtype, int nlevels,
+                              const void *in, void *out, uint64_t *ticket);
+
+/* Block until every submitted request is done. */
+mgr_status mgr_service_wait_all(mgr_service *svc);
+
+/* State of a request: done (0/1), its status, milliseconds from submission
+ * to being enqueued (queue_ms; -1 while waiting) and to completion as seen
+ * by the service (latency_ms; -1 until done).  Any output pointer may be
+ * NULL.  MGR_ERR_INVALID_ARG for an unknown ticket. */
+mgr_status mgr_service_result(mgr_service *svc, uint64_t ticket, int *done, mgr_status *status,
+                              double *queue_ms, double *latency_ms);
+
+/* Wait for every request, stop the threads and free the arena and streams. */
+mgr_status mgr_service_destroy(mgr_service *svc);
+
+/* Detail of the calling thread's last service failure ("" if none). */
+const char *mgr_service_last_error(void);
+
 /* ---- Instrumentation (benchmarking only; not part of the method) --------
  * While enabled, every kernel launch of later calls is bracketed by a pair of
  * HIP events recorded on the launch's own stream, and its algorithmic

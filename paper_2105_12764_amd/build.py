@@ -11,7 +11,7 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libmgr.so")
 OBJDIR = os.path.join(PKG, "_build")
 
-SOURCES = ["mgr_plan.cpp", "mgr_api.cpp", "mgr_timing.cpp", "mgr_kernels.hip"]
+SOURCES = ["mgr_plan.cpp", "mgr_api.cpp", "mgr_timing.cpp", "mgr_service.cpp", "mgr_kernels.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

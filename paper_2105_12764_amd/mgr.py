@@ -75,6 +75,22 @@ def lib() -> ctypes.CDLL:
         L.mgr_last_error.restype = ctypes.c_char_p
         L.mgr_release_caches.argtypes = []
         L.mgr_release_caches.restype = None
+        vp = ctypes.c_void_p
+        L.mgr_service_create.argtypes = [ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(vp)]
+        L.mgr_service_create.restype = ctypes.c_int
+        L.mgr_service_submit.argtypes = [vp, ctypes.c_int, ctypes.c_int, i64p, dpp, ctypes.c_int, ctypes.c_int,
+                                         vp, vp, ctypes.POINTER(ctypes.c_uint64)]
+        L.mgr_service_submit.restype = ctypes.c_int
+        L.mgr_service_wait_all.argtypes = [vp]
+        L.mgr_service_wait_all.restype = ctypes.c_int
+        L.mgr_service_result.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int),
+                                         ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_double)]
+        L.mgr_service_result.restype = ctypes.c_int
+        L.mgr_service_destroy.argtypes = [vp]
+        L.mgr_service_destroy.restype = ctypes.c_int
+        L.mgr_service_last_error.argtypes = []
+        L.mgr_service_last_error.restype = ctypes.c_char_p
         L.mgr_recompose_partial.argtypes = [ctypes.c_int, i64p, dpp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                             ctypes.c_void_p]
@@ -357,6 +373,54 @@ def autotune(x, coords=None, nlevels: Optional[int] = None, out=None, workspace=
     workspace are overwritten).  Returns the library's report of its choices."""
     _call(lib().mgr_autotune, x, coords, nlevels, out, workspace, stream)
     return lib().mgr_autotune_report().decode()
+
+
+class Service:
+    """mgr_service: requests admitted by HBM footprint, run on internal streams."""
+
+    def __init__(self, budget_bytes: int, nstreams: int = 4):
+        self._h = ctypes.c_void_p()
+        s = lib().mgr_service_create(ctypes.c_size_t(int(budget_bytes)), int(nstreams), ctypes.byref(self._h))
+        if s != MGR_OK:
+            raise MgrError(s, lib().mgr_service_last_error().decode())
+        self._keep = {}
+
+    def submit(self, recompose: bool, x, out, coords=None, nlevels: Optional[int] = None) -> int:
+        shape = tuple(x.shape)
+        if nlevels is None:
+            nlevels = max_levels(shape)
+        carr, keep = _coords_arg(shape, coords)
+        t = ctypes.c_uint64(0)
+        s = lib().mgr_service_submit(self._h, 1 if recompose else 0, len(shape), _shape(shape), carr,
+                                     _dtype_code(x.dtype), int(nlevels), ctypes.c_void_p(x.data_ptr()),
+                                     ctypes.c_void_p(out.data_ptr()), ctypes.byref(t))
+        if s != MGR_OK:
+            raise MgrError(s, lib().mgr_service_last_error().decode())
+        return int(t.value)
+
+    def wait_all(self) -> None:
+        lib().mgr_service_wait_all(self._h)
+
+    def result(self, ticket: int):
+        """(done, status, queue_ms, latency_ms) of a request."""
+        d, st = ctypes.c_int(), ctypes.c_int()
+        q, lat = ctypes.c_double(), ctypes.c_double()
+        s = lib().mgr_service_result(self._h, ctypes.c_uint64(ticket), ctypes.byref(d), ctypes.byref(st),
+                                     ctypes.byref(q), ctypes.byref(lat))
+        if s != MGR_OK:
+            raise MgrError(s, lib().mgr_service_last_error().decode())
+        return bool(d.value), int(st.value), float(q.value), float(lat.value)
+
+    def close(self) -> None:
+        if self._h:
+            lib().mgr_service_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def release_caches() -> None:

@@ -187,3 +187,18 @@ def test_class_export_rejects_bad_arguments_without_a_device():
         assert fn(3, sh, 5, 2, ctypes.c_void_p(1 << 30), ctypes.c_void_p(2 << 30), None) == E
         assert fn(3, sh, mgr.MGR_FLOAT64, 2, ctypes.c_void_p(1 << 30), ctypes.c_void_p((1 << 30) + 8), None) == E
         assert fn(3, sh, mgr.MGR_FLOAT64, 2, None, ctypes.c_void_p(2 << 30), None) == E
+
+
+def test_service_rejects_bad_arguments_without_a_device():
+    L = mgr.lib()
+    h = ctypes.c_void_p()
+    E = mgr.MGR_ERR_INVALID_ARG
+    assert L.mgr_service_create(ctypes.c_size_t(16), 2, ctypes.byref(h)) == E
+    assert L.mgr_service_create(ctypes.c_size_t(1 << 30), 0, ctypes.byref(h)) == E
+    assert L.mgr_service_create(ctypes.c_size_t(1 << 30), 17, ctypes.byref(h)) == E
+    assert L.mgr_service_create(ctypes.c_size_t(1 << 30), 2, None) == E
+    t = ctypes.c_uint64()
+    assert L.mgr_service_submit(None, 0, 3, mgr._shape((9, 9, 9)), None, mgr.MGR_FLOAT64, 2,
+                                ctypes.c_void_p(1), ctypes.c_void_p(2), ctypes.byref(t)) == E
+    assert L.mgr_service_wait_all(None) == E
+    assert L.mgr_service_destroy(None) == mgr.MGR_OK
