@@ -66,7 +66,8 @@ def _log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
-def run_gpu(name: str, steps: int, warmup: int, graph_steps: int = 0, tune: bool = True):
+def run_gpu(name: str, steps: int, warmup: int, graph_steps: int = 0, tune: bool = True,
+            progressive_on: bool = True):
     import torch
 
     from paper_2105_12764_amd import mgr
@@ -170,7 +171,7 @@ def run_gpu(name: str, steps: int, warmup: int, graph_steps: int = 0, tune: bool
     # progressive recomposition: error and time with the nkeep coarsest classes
     progressive = []
     xn = float(x.double().norm())
-    for nkeep in range(nlev + 1):
+    for nkeep in range(nlev + 1 if progressive_on else 0):
         mgr.recompose_partial(d, nkeep, coords, nlev, out=r, workspace=ws, stream=stream)
         p0, p1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         p0.record(stream)
@@ -477,6 +478,8 @@ def main():
                     help="also time this many replays of the step captured as a HIP graph")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-field batch")
     ap.add_argument("--no-service", action="store_true", help="skip the service sweep")
+    ap.add_argument("--no-progressive", action="store_true",
+                    help="skip the partial recompositions (the timed step's kernels are then the last ones)")
     ap.add_argument("--service-requests", type=int, default=300,
                     help="requests per arrival rate in the service sweep")
     args = ap.parse_args()
@@ -488,10 +491,12 @@ def main():
 
     probe = probe_bandwidth()
     _log(f"[bench] copy probe: {probe['GBps']:.0f} GB/s")
-    res, u, coords, nlev = run_gpu(args.workload, args.steps, args.warmup, args.graph_steps)
+    res, u, coords, nlev = run_gpu(args.workload, args.steps, args.warmup, args.graph_steps,
+                                   progressive_on=not args.no_progressive)
     fp32 = None
     if not args.no_fp32 and args.fp32_workload:
-        r32, _, _, _ = run_gpu(args.fp32_workload, args.steps, args.warmup)
+        r32, _, _, _ = run_gpu(args.fp32_workload, args.steps, args.warmup,
+                              progressive_on=not args.no_progressive)
         fp32 = {k: r32[k] for k in ("workload", "value", "t_dec_ms", "t_rec_ms", "alg_GBps",
                                      "roundtrip_max_rel_err", "roofline")}
         fp32["untuned_value"] = r32["autotune"]["untuned_value"] if r32.get("autotune") else None

@@ -38,6 +38,9 @@ DENSE_CASES = [
     ((33,), 5, False),          # 1-D full depth
     ((40,), 6, True),           # 1-D even size, non-uniform
     ((3, 4, 3), 1, True),       # smallest coarsenable sizes
+    ((5, 5, 5, 5), 2, False),   # 4-D (time as a fourth dimension), dyadic
+    ((6, 5, 3, 7), 1, True),    # 4-D, non-dyadic, non-uniform
+    ((2, 5, 9, 3), 2, True),    # 4-D with a size-2 dimension
 ]
 
 
@@ -111,7 +114,8 @@ def _multilinear_from_coarse(shape, coords, nlev, rng):
 
 
 @pytest.mark.parametrize("shape,nlev,nonuni", [((17, 17, 17), 3, False), ((12, 9, 14), 2, True),
-                                                ((65, 33), 4, True), ((100,), 6, True)])
+                                                ((65, 33), 4, True), ((100,), 6, True),
+                                                ((9, 13, 7, 10), 2, True)])
 def test_multilinear_field_has_zero_coefficients(shape, nlev, nonuni):
     rng = np.random.default_rng(21)
     _, c = make_input(shape, 2, nonuniform=nonuni)
@@ -137,7 +141,8 @@ def test_multilinear_field_has_zero_coefficients(shape, nlev, nonuni):
 # --------------------------------------------------------------- invariants
 
 @pytest.mark.parametrize("shape,nlev,nonuni", [((65, 65, 65), 5, False), ((40, 30, 25), 5, True),
-                                                ((129, 70), 7, True), ((1000,), 9, True)])
+                                                ((129, 70), 7, True), ((1000,), 9, True),
+                                                ((17, 20, 13, 11), 4, True)])
 def test_round_trip(shape, nlev, nonuni):
     u, c = make_input(shape, 1001, nonuniform=nonuni)
     d = oracle.decompose(u, c, nlev)
@@ -159,14 +164,15 @@ def test_affine_coordinates():
     assert rel(oracle.decompose(u, c2, 3), oracle.decompose(u, c, 3)) < 1e-12
 
 
-def test_separable_field_coarsest_is_outer_product():
-    """Q = Q^x (x) Q^y (x) Q^z on tensor grids, so the coarsest values of a
-    separable field are the outer product of the 1-D coarsest values."""
+@pytest.mark.parametrize("shape,nlev", [((33, 17, 21), 4), ((9, 17, 11, 13), 3)])
+def test_separable_field_coarsest_is_outer_product(shape, nlev):
+    """Q = Q^x (x) Q^y (x) Q^z (x) ... on tensor grids, so the coarsest values
+    of a separable field are the outer product of the 1-D coarsest values."""
     rng = np.random.default_rng(8)
-    shape, nlev = (33, 17, 21), 4
     coords = [np.cumsum(rng.uniform(0.5, 1.5, n)) for n in shape]
     g = [rng.standard_normal(n) for n in shape]
-    u = np.einsum("i,j,k->ijk", *g)
+    sub = "ijkl"[:len(shape)]
+    u = np.einsum(",".join(sub) + "->" + sub, *g)
     full = oracle.decompose(u, coords, nlev)
     idx, ones = [], []
     for k, n in enumerate(shape):
@@ -175,7 +181,7 @@ def test_separable_field_coarsest_is_outer_product():
             lev = lev[coarse_positions(len(lev))]
         idx.append(lev)
         ones.append(oracle.decompose(g[k], [coords[k]], nlev)[lev])
-    want = np.einsum("i,j,k->ijk", *ones)
+    want = np.einsum(",".join(sub) + "->" + sub, *ones)
     assert rel(full[np.ix_(*idx)], want) < 1e-12
 
 
