@@ -21,7 +21,9 @@ field per call, with the batched entry points, and with the batch replayed
 from a HIP graph (p50/p99 ms per batch, GB/s, and whether the batched results
 are bitwise those of the single calls), and
 `service`: Poisson streams of mixed-size decompose/recompose requests served
-under an HBM budget (p50/p99 latency, GB/s) next to the plain path.
+under an HBM budget (p50/p99 latency, GB/s) next to the plain path, and
+`spatiotemporal`: T = 1..16 time steps of a 400^3 FP64 field refactored
+together as one 4-D field.
 """
 from __future__ import annotations
 
@@ -421,6 +423,71 @@ def run_service(nreq: int = 300, rates=(50, 100, 200, 500, 1000, 2000), budget_g
     return res
 
 
+def run_spatiotemporal(side: int = 400, steps=(1, 2, 4, 8, 16), reps: int = 3):
+    """4-D refactoring (time as a fourth dimension, Sec. III-F, V-F): T time
+    steps of a side^3 FP64 field (512 MB per step at side 400) refactored
+    together as one (T, side, side, side) field, all levels; T = 1 is the
+    3-D path on one step.  GB/s = 2 x bytes / (t_dec + t_rec), best of reps;
+    per-kernel totals of one T = max(steps) pass."""
+    import torch
+
+    from paper_2105_12764_amd import mgr
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(6000)
+    tmax = max(steps)
+    full = torch.randn((tmax, side, side, side), dtype=torch.float64, device=dev, generator=gen)
+    out = {}
+    kern = None
+    for T in steps:
+        x = full[0] if T == 1 else full[:T]
+        shape = tuple(x.shape)
+        nlev = mgr.max_levels(shape)
+        d = torch.empty_like(x)
+        r = torch.empty_like(x)
+        ws = mgr.alloc_workspace(shape, x.dtype, nlev, device=dev)
+        mgr.decompose(x, None, nlev, out=d, workspace=ws, stream=stream)
+        mgr.recompose(d, None, nlev, out=r, workspace=ws, stream=stream)
+        torch.cuda.synchronize()
+        best = None
+        for _ in range(reps):
+            e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+            e0.record(stream)
+            mgr.decompose(x, None, nlev, out=d, workspace=ws, stream=stream)
+            e1.record(stream)
+            mgr.recompose(d, None, nlev, out=r, workspace=ws, stream=stream)
+            e2.record(stream)
+            torch.cuda.synchronize()
+            t = (e0.elapsed_time(e1), e1.elapsed_time(e2))
+            if best is None or sum(t) < sum(best):
+                best = t
+        if T == tmax:
+            mgr.timing_reset()
+            mgr.timing_enable(True)
+            mgr.decompose(x, None, nlev, out=d, workspace=ws, stream=stream)
+            mgr.recompose(d, None, nlev, out=r, workspace=ws, stream=stream)
+            torch.cuda.synchronize()
+            mgr.timing_enable(False)
+            kern = {k: {"launches": v[0], "ms": round(v[1], 4),
+                        "alg_GBps": round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[1] > 0 else None}
+                    for k, v in sorted(mgr.timing_totals().items(), key=lambda kv: -kv[1][1])[:10]}
+        err = float((r - x).abs().max() / x.abs().max())
+        nbytes = x.numel() * 8
+        out[str(T)] = {"shape": list(shape), "nlevels": nlev, "t_dec_ms": round(best[0], 3),
+                       "t_rec_ms": round(best[1], 3),
+                       "GBps": round(2.0 * nbytes / (sum(best) * 1e-3) / 1e9, 1), "roundtrip_max_rel_err": err}
+        _log(f"[bench] spatiotemporal T={T}: dec {best[0]:.2f} ms rec {best[1]:.2f} ms "
+             f"{out[str(T)]['GBps']} GB/s")
+        del d, r, ws
+    del full
+    torch.cuda.empty_cache()
+    return {"space": f"{side}^3 FP64 per time step ({side ** 3 * 8 / 2 ** 20:.0f} MiB)",
+            "data": "torch.randn, seed 6000 (time does not depend on values)", "per_T": out,
+            "kernels_at_max_T": kern}
+
+
 def probe_bandwidth(nbytes: int = 1 << 30, reps: int = 10):
     """Achievable single-pass bandwidth: the library's streaming copy probe
     (one read + one write of every byte), 2 * bytes / time."""
@@ -478,6 +545,7 @@ def main():
                     help="also time this many replays of the step captured as a HIP graph")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-field batch")
     ap.add_argument("--no-service", action="store_true", help="skip the service sweep")
+    ap.add_argument("--no-4d", action="store_true", help="skip the spatiotemporal (4-D) sweep")
     ap.add_argument("--no-progressive", action="store_true",
                     help="skip the partial recompositions (the timed step's kernels are then the last ones)")
     ap.add_argument("--service-requests", type=int, default=300,
@@ -502,6 +570,7 @@ def main():
         fp32["untuned_value"] = r32["autotune"]["untuned_value"] if r32.get("autotune") else None
     batched = None if args.no_batch else run_batched()
     service = None if args.no_service else run_service(args.service_requests)
+    spatiotemporal = None if args.no_4d else run_spatiotemporal()
     cpu = None if args.no_cpu_baseline else cpu_baseline(u, coords, nlev)
 
     line = {
@@ -537,6 +606,7 @@ def main():
         "progressive": res["progressive"],
         "batched": batched,
         "service": service,
+        "spatiotemporal": spatiotemporal,
     }
     print(json.dumps(line), flush=True)
 

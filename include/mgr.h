@@ -57,7 +57,7 @@ typedef enum { MGR_FLOAT32 = 0, MGR_FLOAT64 = 1 } mgr_dtype;
 
 /* Largest valid level count for `shape`: the number of coarsening steps of
  * its deepest dimension (a dimension of m >= 3 nodes goes to m/2 + 1).
- * ndim in 1..3, every shape[k] >= 2.  Returns -MGR_ERR_INVALID_ARG on a bad
+ * ndim in 1..4, every shape[k] >= 2.  Returns -MGR_ERR_INVALID_ARG on a bad
  * shape.  Host only, no GPU needed. */
 int mgr_max_levels(int ndim, const int64_t *shape);
 
@@ -68,7 +68,13 @@ mgr_status mgr_workspace_size(int ndim, const int64_t *shape, mgr_dtype dtype,
                               int nlevels, size_t *bytes);
 
 /* Decompose `in` into its nodal multilevel representation `out`.
- *   ndim, shape : 1..3 dimensions, each >= 2 nodes, C order.
+ *   ndim, shape : 1..4 dimensions, each >= 2 nodes, C order.  A 4-D shape
+ *                 is (time, then three space dims): the decomposition in
+ *                 four tensor-product dims of Sec. III-F, time coarsening
+ *                 like space; the product of the three space dims must be
+ *                 below 2^31.  4-D fields are taken by mgr_decompose,
+ *                 mgr_recompose, mgr_workspace_size and mgr_max_levels;
+ *                 the other entry points reject them.
  *   coords      : host pointer to ndim host arrays of shape[k] doubles,
  *                 strictly increasing and finite; coords == NULL or
  *                 coords[k] == NULL selects 0..shape[k]-1.  Read during the

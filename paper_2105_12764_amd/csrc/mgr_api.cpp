@@ -30,6 +30,7 @@ struct CacheEntry {
   int device;
   int ndim;
   int64_t n[mgr::kDims];
+  int64_t nt;  // time extent of a 4-D field (1 otherwise)
   int nlev;
   std::vector<std::vector<double>> coords;
   std::shared_ptr<mgr::Plan> plan;
@@ -42,7 +43,9 @@ constexpr size_t kCacheMax = 64;
 // Pads the caller's shape to rank 3 with leading 1s.
 bool pad_shape(int ndim, const int64_t *shape, int64_t n[mgr::kDims], std::string &why) {
   if (ndim < 1 || ndim > 3) {
-    why = "ndim must be 1, 2 or 3 (got " + std::to_string(ndim) + ")";
+    why = ndim == 4 ? "4-D fields are taken by mgr_decompose, mgr_recompose, mgr_workspace_size and "
+                      "mgr_max_levels only"
+                    : "ndim must be 1, 2, 3 or 4 (got " + std::to_string(ndim) + ")";
     return false;
   }
   if (!shape) {
@@ -73,28 +76,66 @@ bool pad_shape(int ndim, const int64_t *shape, int64_t n[mgr::kDims], std::strin
   return true;
 }
 
+// Shapes of 1 to 4 dims.  A 4-D shape is (time, then three space dims): n
+// gets the space dims and nt the time extent (1 below 4-D).
+bool split_shape(int ndim, const int64_t *shape, int64_t n[mgr::kDims], int64_t &nt, std::string &why) {
+  nt = 1;
+  if (ndim != 4) return pad_shape(ndim, shape, n, why);
+  if (!shape) {
+    why = "shape is NULL";
+    return false;
+  }
+  for (int k = 0; k < 4; ++k) {
+    if (shape[k] < 2) {
+      why = "shape[" + std::to_string(k) + "] must be >= 2";
+      return false;
+    }
+    if (shape[k] > (int64_t)1 << 31) {
+      why = "shape[" + std::to_string(k) + "] too large";
+      return false;
+    }
+  }
+  if (!pad_shape(3, shape + 1, n, why)) return false;
+  const int64_t slice = n[0] * n[1] * n[2];
+  if (slice >= ((int64_t)1 << 31)) {
+    why = "a time slice (product of the last three dimensions) must hold fewer than 2^31 nodes";
+    return false;
+  }
+  if (shape[0] > (((int64_t)1 << 40) / slice)) {
+    why = "total element count out of range";
+    return false;
+  }
+  nt = shape[0];
+  return true;
+}
+
 mgr_status validate(int ndim, const int64_t *shape, const double *const *coords, int dtype,
                     int nlevels, const void *in, void *out, void *ws, size_t ws_bytes,
-                    int64_t n[mgr::kDims], std::vector<std::vector<double>> &cx) {
+                    int64_t n[mgr::kDims], std::vector<std::vector<double>> &cx, int64_t *nt_out = nullptr) {
   std::string why;
-  if (!pad_shape(ndim, shape, n, why)) return fail(MGR_ERR_INVALID_ARG, why);
+  int64_t nt = 1;
+  if (!split_shape(ndim, shape, n, nt, why)) return fail(MGR_ERR_INVALID_ARG, why);
+  if (nt_out) *nt_out = nt;
   if (dtype != MGR_FLOAT32 && dtype != MGR_FLOAT64)
     return fail(MGR_ERR_INVALID_ARG, "dtype must be MGR_FLOAT32 or MGR_FLOAT64");
-  const int ml = mgr::max_levels3(n);
+  const int ml = ndim == 4 ? mgr::max_levels4(nt, n) : mgr::max_levels3(n);
   if (nlevels < 0 || nlevels > ml)
     return fail(MGR_ERR_INVALID_ARG, "nlevels must be in [0, " + std::to_string(ml) + "]");
   if (nlevels > mgr::kMaxLevels) return fail(MGR_ERR_UNSUPPORTED, "too many levels");
   if (!in || !out) return fail(MGR_ERR_INVALID_ARG, "in and out must be non-NULL device pointers");
   const size_t esz = dtype == MGR_FLOAT64 ? 8 : 4;
-  const size_t bytes = (size_t)(n[0] * n[1] * n[2]) * esz;
+  const size_t bytes = (size_t)(nt * n[0] * n[1] * n[2]) * esz;
   const char *a = (const char *)in, *b = (const char *)out;
   if (a < b + bytes && b < a + bytes) return fail(MGR_ERR_INVALID_ARG, "in and out overlap");
-  cx.assign(mgr::kDims, {});
-  for (int k = 0; k < mgr::kDims; ++k) {
-    const int uk = k - (mgr::kDims - ndim);
+  // per-dim coordinates: the padded rank-3 dims, or (4-D) time then space
+  const int nc = ndim == 4 ? 4 : mgr::kDims;
+  cx.assign(nc, {});
+  for (int k = 0; k < nc; ++k) {
+    const int uk = ndim == 4 ? k : k - (mgr::kDims - ndim);
+    const int64_t ext = ndim == 4 ? (k == 0 ? nt : n[k - 1]) : n[k];
     const double *src = (uk >= 0 && coords) ? coords[uk] : nullptr;
-    cx[k].resize(n[k]);
-    for (int64_t i = 0; i < n[k]; ++i) {
+    cx[k].resize(ext);
+    for (int64_t i = 0; i < ext; ++i) {
       const double v = src ? src[i] : (double)i;
       if (!std::isfinite(v))
         return fail(MGR_ERR_INVALID_ARG, "coords[" + std::to_string(uk) + "] has a non-finite value");
@@ -104,7 +145,7 @@ mgr_status validate(int ndim, const int64_t *shape, const double *const *coords,
       cx[k][i] = v;
     }
   }
-  const size_t need = mgr::workspace_bytes(n, nlevels, esz);
+  const size_t need = ndim == 4 ? mgr::workspace_bytes4(nt, n, nlevels, esz) : mgr::workspace_bytes(n, nlevels, esz);
   if (need > 0) {
     if (!ws) return fail(MGR_ERR_WORKSPACE, "workspace is NULL");
     if (ws_bytes < need)
@@ -118,7 +159,8 @@ mgr_status validate(int ndim, const int64_t *shape, const double *const *coords,
 }
 
 mgr_status get_plan(const int64_t n[mgr::kDims], int ndim, int nlevels,
-                    const std::vector<std::vector<double>> &cx, std::shared_ptr<mgr::Plan> &out) {
+                    const std::vector<std::vector<double>> &cx, std::shared_ptr<mgr::Plan> &out,
+                    int64_t nt = 1) {
   int dev = -1;
   hipError_t he = hipGetDevice(&dev);
   if (he != hipSuccess) {
@@ -127,7 +169,7 @@ mgr_status get_plan(const int64_t n[mgr::kDims], int ndim, int nlevels,
   }
   std::lock_guard<std::mutex> lk(g_mu);
   for (auto it = g_cache.begin(); it != g_cache.end(); ++it) {
-    if (it->device != dev || it->ndim != ndim || it->nlev != nlevels) continue;
+    if (it->device != dev || it->ndim != ndim || it->nlev != nlevels || it->nt != nt) continue;
     if (std::memcmp(it->n, n, sizeof(it->n)) != 0) continue;
     if (it->coords != cx) continue;
     out = it->plan;
@@ -138,7 +180,7 @@ mgr_status get_plan(const int64_t n[mgr::kDims], int ndim, int nlevels,
   int st = 0;
   std::unique_ptr<mgr::Plan> p;
   try {
-    p = mgr::build_plan(ndim, n, cx, nlevels, err, st);
+    p = ndim == 4 ? mgr::build_plan4(nt, n, cx, nlevels, err, st) : mgr::build_plan(ndim, n, cx, nlevels, err, st);
   } catch (const std::bad_alloc &) {
     return fail(MGR_ERR_OUT_OF_MEMORY, "host allocation failed while building the plan");
   } catch (...) {
@@ -148,6 +190,7 @@ mgr_status get_plan(const int64_t n[mgr::kDims], int ndim, int nlevels,
   CacheEntry e;
   e.device = dev;
   e.ndim = ndim;
+  e.nt = nt;
   std::memcpy(e.n, n, sizeof(e.n));
   e.nlev = nlevels;
   e.coords = cx;
@@ -163,14 +206,16 @@ mgr_status run(bool dec, int ndim, const int64_t *shape, const double *const *co
                int nkeep = -1) {
   g_last_error.clear();
   try {
-    int64_t n[mgr::kDims];
+    int64_t n[mgr::kDims], nt = 1;
     std::vector<std::vector<double>> cx;
-    mgr_status s = validate(ndim, shape, coords, dtype, nlevels, in, out, ws, ws_bytes, n, cx);
+    mgr_status s = validate(ndim, shape, coords, dtype, nlevels, in, out, ws, ws_bytes, n, cx, &nt);
     if (s != MGR_OK) return s;
     if (nkeep != -1 && (nkeep < 0 || nkeep > nlevels))
       return fail(MGR_ERR_INVALID_ARG, "nkeep must be in [0, nlevels]");
+    if (nkeep != -1 && ndim == 4)
+      return fail(MGR_ERR_UNSUPPORTED, "partial recomposition of 4-D fields is not supported");
     std::shared_ptr<mgr::Plan> plan;
-    s = get_plan(n, ndim, nlevels, cx, plan);
+    s = get_plan(n, ndim, nlevels, cx, plan, nt);
     if (s != MGR_OK) return s;
     std::string err;
     const bool f64 = dtype == MGR_FLOAT64;
@@ -378,28 +423,29 @@ mgr_status run_batch(bool dec, int nfields, const mgr_field *fields, void *ws, s
 extern "C" {
 
 int mgr_max_levels(int ndim, const int64_t *shape) {
-  int64_t n[mgr::kDims];
+  int64_t n[mgr::kDims], nt = 1;
   std::string why;
-  if (!pad_shape(ndim, shape, n, why)) {
+  if (!split_shape(ndim, shape, n, nt, why)) {
     g_last_error = why;
     return -MGR_ERR_INVALID_ARG;
   }
-  return mgr::max_levels3(n);
+  return ndim == 4 ? mgr::max_levels4(nt, n) : mgr::max_levels3(n);
 }
 
 mgr_status mgr_workspace_size(int ndim, const int64_t *shape, mgr_dtype dtype, int nlevels,
                               size_t *bytes) {
   g_last_error.clear();
-  int64_t n[mgr::kDims];
+  int64_t n[mgr::kDims], nt = 1;
   std::string why;
   if (!bytes) return fail(MGR_ERR_INVALID_ARG, "bytes is NULL");
-  if (!pad_shape(ndim, shape, n, why)) return fail(MGR_ERR_INVALID_ARG, why);
+  if (!split_shape(ndim, shape, n, nt, why)) return fail(MGR_ERR_INVALID_ARG, why);
   if (dtype != MGR_FLOAT32 && dtype != MGR_FLOAT64)
     return fail(MGR_ERR_INVALID_ARG, "dtype must be MGR_FLOAT32 or MGR_FLOAT64");
-  const int ml = mgr::max_levels3(n);
+  const int ml = ndim == 4 ? mgr::max_levels4(nt, n) : mgr::max_levels3(n);
   if (nlevels < 0 || nlevels > ml)
     return fail(MGR_ERR_INVALID_ARG, "nlevels must be in [0, " + std::to_string(ml) + "]");
-  *bytes = mgr::workspace_bytes(n, nlevels, dtype == MGR_FLOAT64 ? 8 : 4);
+  const size_t es = dtype == MGR_FLOAT64 ? 8 : 4;
+  *bytes = ndim == 4 ? mgr::workspace_bytes4(nt, n, nlevels, es) : mgr::workspace_bytes(n, nlevels, es);
   return MGR_OK;
 }
 
@@ -504,6 +550,7 @@ mgr_status mgr_autotune(int ndim, const int64_t *shape, const double *const *coo
   try {
     int64_t n[mgr::kDims];
     std::vector<std::vector<double>> cx;
+    if (ndim == 4) return fail(MGR_ERR_UNSUPPORTED, "autotuning of 4-D fields is not supported");
     mgr_status s = validate(ndim, shape, coords, (int)dtype, nlevels, in, out, workspace, workspace_bytes, n, cx);
     if (s != MGR_OK) return s;
     std::shared_ptr<mgr::Plan> plan;

@@ -88,6 +88,11 @@ struct LoadArgs {
   const double *W0, *W1, *W2;
   int64_t TI;     // coarse planes per workgroup along dim 0
   int gx, gy, gz; // tile grid (dims 2, 1, 0)
+  // Time slices of a 4-D level (k_tfine covers the rest of their nodes):
+  // decompose with out == nullptr forms the load vector only; recompose with
+  // keep_coarse stages the nodes coarse in space too, for a slice all of
+  // whose nodes hold coefficients.
+  int keep_coarse;
 };
 
 // Tile id of this workgroup.  Hardware hands consecutive workgroup ids to
@@ -144,7 +149,8 @@ __global__ void __launch_bounds__(NTHR, LV_WAVES) k_loadvec(LoadArgs<T> a) {
   const bool lastJ = J0 + TJ >= a.c1, lastK = K0 + TK >= a.c2, lastI = I1 >= a.c0;
   const int64_t ojb = SJ * J0, oje = lastJ ? a.m1 : SJ * (J0 + TJ);
   const int64_t okb = SK * K0, oke = lastK ? a.m2 : SK * (K0 + TK);
-  const int64_t oib = (CO0 ? 2 : 1) * I0, oie = lastI ? a.m0 : (CO0 ? 2 : 1) * I1;
+  const int64_t oib = (CO0 ? 2 : 1) * I0;
+  const int64_t oie = (DEC && a.out == nullptr) ? oib : (lastI ? a.m0 : (CO0 ? 2 : 1) * I1);
 
   // per-element constants of this thread's tile elements (same for every plane)
   enum : unsigned { F_IN = 1, F_OWN = 2, F_C1 = 4, F_C2 = 8 };
@@ -341,7 +347,7 @@ __global__ void __launch_bounds__(NTHR, LV_WAVES) k_loadvec(LoadArgs<T> a) {
     int64_t pa, pb;
     planes(I, pa, pb);
     const bool b_in_a_slot = CO0 && pb >= 0 && pb == 2 * I + 1;  // coarse plane in the fine slot
-    if (pb >= 0) stage(sA, vb, !DEC);
+    if (pb >= 0) stage(sA, vb, !DEC && !a.keep_coarse);
     if (pa >= 0) stage(sB, va, false);
     double *kst = sStep[I & 1];
     if (tid < 6) kst[tid] = kv;
@@ -1000,6 +1006,140 @@ __global__ void __launch_bounds__(256) k_gather(const T *src, Map3 smap, T *dst,
   }
 }
 
+// ------------------------------------------------------------ 4-D levels
+//
+// A 4-D field is refactored as one more tensor-product dimension (Sec.
+// III-F): dim 0 (time) coarsens with the same nesting rule, interpolation is
+// multilinear in all four dims, and the load vector and the correction solves
+// act along time as along space.  Space is processed per time slice by the
+// 3-D kernels (time over launches), time by the kernels below with the three
+// space dims flattened.
+
+// Load vector along time: row J of P^T M along dim 0 applied to the per-slice
+// space load vectors G (tm slices of ncs entries),
+// F[J] = sum_o W[5 J + o] G[2 J - 2 + o].  A thread walks a run of TL_JC
+// consecutive J for one space entry with a five-slice register window, so each
+// slice of G is read about once.
+constexpr int TL_JC = 8;
+__global__ void __launch_bounds__(256) k_tload(const double *__restrict__ G, int64_t tm,
+                                               const double *__restrict__ W, double *__restrict__ F,
+                                               int64_t ct, int64_t ncs) {
+  const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (x >= ncs) return;
+  const int64_t nrun = (ct + TL_JC - 1) / TL_JC;
+  for (int64_t run = blockIdx.y; run < nrun; run += gridDim.y) {
+    const int64_t J0 = run * TL_JC, J1 = min(J0 + TL_JC, ct);
+    auto ld = [&](int64_t p) -> double { return (p >= 0 && p < tm) ? G[p * ncs + x] : 0.0; };
+    double g0 = ld(2 * J0 - 2), g1 = ld(2 * J0 - 1), g2 = ld(2 * J0), g3 = ld(2 * J0 + 1), g4 = ld(2 * J0 + 2);
+    for (int64_t J = J0; J < J1; ++J) {
+      const double *w = W + J * 5;
+      double f = w[0] * g0;
+      f = fma(w[1], g1, f);
+      f = fma(w[2], g2, f);
+      f = fma(w[3], g3, f);
+      f = fma(w[4], g4, f);
+      F[J * ncs + x] = f;
+      g0 = g2;
+      g1 = g3;
+      g2 = g4;
+      g3 = ld(2 * J + 3);
+      g4 = ld(2 * J + 4);
+    }
+  }
+}
+
+// Neighbours of level position i along one space dim for the interpolant:
+// the coarse positions on either side and the weight of the right one
+// (both the node itself, weight 0, where i is coarse or the dim not
+// coarsened).  Level-grid positions (LVL) or coarse-grid indices.
+template <bool LVL>
+__device__ __forceinline__ void nb_dim(int64_t i, int64_t m, int64_t c, bool co, const double *r, int64_t &lo,
+                                       int64_t &hi, double &w) {
+  if (!co) {
+    lo = hi = i;
+    w = 0.0;
+  } else if (i % 2 == 0 || i == m - 1) {
+    lo = hi = LVL ? i : (i == m - 1 ? c - 1 : i / 2);
+    w = 0.0;
+  } else {
+    lo = LVL ? i - 1 : (i - 1) / 2;
+    hi = LVL ? i + 1 : (i + 1 == m - 1 ? c - 1 : (i + 1) / 2);
+    w = r[i];
+  }
+}
+
+template <typename T>
+struct TfineArgs {
+  const T *src;          // decompose: compact level grid; recompose: stored coefficients (finest layout)
+  T *dst;                // decompose: output (finest layout); recompose: compact level grid
+  const T *crs;          // coarse values: the level grid (decompose) or the compact coarse grid (recompose)
+  Map3 fmap;             // space map of the finest-layout side
+  const int64_t *tnod;   // finest time index of each level time position
+  const double *rt;      // time interpolation weights of the level
+  int64_t S0;            // nodes of a finest time slice
+  int64_t tm, m0, m1, m2, c0, c1, c2;
+  int co0, co1, co2;
+  const double *r0, *r1, *r2;
+};
+
+// The time-fine slices of a 4-D level: every node of slice t = 2q + 1 holds a
+// coefficient, and its interpolant is the space-multilinear interpolant of the
+// time lerp (weight rt[t] of the later slice) of the coarse values of slices
+// t - 1 and t + 1.  Decompose: coefficient = value - interpolant; recompose:
+// value = coefficient + interpolant.  Grid: x over the slice's nodes, y over q.
+template <typename T, bool DEC>
+__global__ void __launch_bounds__(256) k_tfine(TfineArgs<T> a) {
+  const int64_t sm = a.m0 * a.m1 * a.m2;
+  const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (x >= sm) return;
+  const uint32_t ux = (uint32_t)x, um2 = (uint32_t)a.m2, um1 = (uint32_t)a.m1;
+  const int64_t k = ux % um2, row = ux / um2, j = row % um1, i = row / um1;
+  int64_t l0, h0, l1, h1, l2, h2;
+  double w0, w1, w2;
+  nb_dim<DEC>(i, a.m0, a.c0, a.co0, a.r0, l0, h0, w0);
+  nb_dim<DEC>(j, a.m1, a.c1, a.co1, a.r1, l1, h1, w1);
+  nb_dim<DEC>(k, a.m2, a.c2, a.co2, a.r2, l2, h2, w2);
+  // strides of the array holding the coarse values
+  const int64_t s1 = DEC ? a.m2 : a.c2, s0 = s1 * (DEC ? a.m1 : a.c1), ss = s0 * (DEC ? a.m0 : a.c0);
+  const int64_t nf = (a.tm - 1) / 2;  // odd positions below the last
+  for (int64_t q = blockIdx.y; q < nf; q += gridDim.y) {
+    const int64_t t = 2 * q + 1;
+    auto tri = [&](const T *c) -> double {
+      auto row2 = [&](int64_t o) {
+        return lerp(lerp((double)c[o + l1 * s1 + l2], (double)c[o + l1 * s1 + h2], w2),
+                    lerp((double)c[o + h1 * s1 + l2], (double)c[o + h1 * s1 + h2], w2), w1);
+      };
+      return lerp(row2(l0 * s0), row2(h0 * s0), w0);
+    };
+    // earlier and later coarse slices: level positions t -/+ 1, or coarse indices q, q + 1
+    const T *cl = a.crs + (DEC ? t - 1 : q) * ss, *cr = a.crs + (DEC ? t + 1 : q + 1) * ss;
+    const double pi = lerp(tri(cl), tri(cr), a.rt[t]);
+    const int64_t fo = a.tnod[t] * a.S0 + moff(a.fmap, i, j, k);
+    const int64_t lo = t * sm + x;
+    if (DEC)
+      a.dst[fo] = (T)((double)a.src[lo] - pi);
+    else
+      a.dst[lo] = (T)((double)a.src[fo] + pi);
+  }
+}
+
+// The coarsest grid of a 4-D field between its nodal positions and a compact
+// grid (TO_NODAL: compact -> nodal).
+template <typename T, bool TO_NODAL>
+__global__ void __launch_bounds__(256) k_nodal4(const T *src, T *dst, Map3 nmap, const int64_t *tnod, int64_t S0,
+                                                int64_t tm, int64_t m0, int64_t m1, int64_t m2) {
+  const int64_t n = tm * m0 * m1 * m2;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t k = e % m2, r1 = e / m2, j = r1 % m1, r0 = r1 / m1, i = r0 % m0, t = r0 / m0;
+    const int64_t o = tnod[t] * S0 + moff(nmap, i, j, k);
+    if (TO_NODAL)
+      dst[o] = src[e];
+    else
+      dst[e] = src[o];
+  }
+}
+
 // Class-contiguous layout of a nodal representation: the coarsest grid's
 // values, then each level's coefficient class (its nodes that are not in the
 // next coarser grid) from the coarsest level to the finest, each in C order
@@ -1412,7 +1552,9 @@ void launch_loadvec_t(LoadArgs<T> a, Ctx &cx) {
     const double nl = (double)a.m0 * a.m1 * a.m2, nc = (double)a.c0 * a.c1 * a.c2;
     // recompose: read the coefficients, write f
     // decompose: read the level grid, write the coefficients and f
-    bytes = DEC ? (2.0 * nl - nc) * sizeof(T) + 8.0 * nc : (nl - nc) * sizeof(T) + 8.0 * nc;
+    if (DEC && a.out == nullptr) bytes = nl * sizeof(T) + 8.0 * nc;
+    else if (!DEC && a.keep_coarse) bytes = nl * sizeof(T) + 8.0 * nc;
+    else bytes = DEC ? (2.0 * nl - nc) * sizeof(T) + 8.0 * nc : (nl - nc) * sizeof(T) + 8.0 * nc;
   }
   TimedLaunch tl(cx.stream,
                  std::string("k_loadvec<") + tname<T>() + ", " + bname(DEC) + ", " + bname(NODAL) + ", " +
@@ -1799,6 +1941,202 @@ bool recompose_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t stre
   return cx.ok;
 }
 
+// ------------------------------------------------------------ 4-D fields
+
+struct Workspace4 {
+  void *buf[2];
+  double *F, *G;
+};
+
+Workspace4 carve4(const Plan &pl, void *ws, size_t elem) {
+  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+  const int64_t cs = pl.lev[0].c[0] * pl.lev[0].c[1] * pl.lev[0].c[2];
+  const int64_t c4 = pl.time->lev[0].c[2] * cs;
+  const size_t nb = al((size_t)c4 * elem), nf = al((size_t)c4 * sizeof(double));
+  char *p = (char *)ws;
+  return Workspace4{{p, p + nb}, (double *)(p + 2 * nb), (double *)(p + 2 * nb + nf)};
+}
+
+inline bool tcoarse(int64_t t, int64_t m) { return m < 3 || t % 2 == 0 || t == m - 1; }
+inline int64_t tcoarse_idx(int64_t t, int64_t m, int64_t c) { return m < 3 ? t : (t == m - 1 ? c - 1 : t / 2); }
+
+// Correction solves of a 4-D level on its compact coarse grid (ct slices of
+// the space coarse grid), each run by the 3-D solvers on a rank-3 view of the
+// grid: space dim 0 as dim 1 of (ct, c0, c1 c2), space dims 1 and 2 as dims 1
+// and 2 of (ct c0, c1, c2), time as dim 0 of (ct, 1, c0 c1 c2).  The last
+// solve applies `last`.
+template <typename T>
+void solve_all4(double *F, const Level &L, const Level &Lt, const Epi<T> &last, Ctx &cx) {
+  const int64_t ct = Lt.c[2], c0 = L.c[0], c1 = L.c[1], c2 = L.c[2];
+  struct View {
+    Level v;
+    int axis;
+  };
+  std::vector<View> views;
+  for (int k = 0; k < kDims; ++k) {
+    if (!L.co[k]) continue;
+    View w{};
+    if (k == 0) {
+      w.v.c[0] = ct; w.v.c[1] = c0; w.v.c[2] = c1 * c2; w.axis = 1;
+    } else {
+      w.v.c[0] = ct * c0; w.v.c[1] = c1; w.v.c[2] = c2; w.axis = k;
+    }
+    w.v.d[w.axis] = L.d[k];
+    views.push_back(w);
+  }
+  if (Lt.co[2]) {
+    View w{};
+    w.v.c[0] = ct; w.v.c[1] = 1; w.v.c[2] = c0 * c1 * c2; w.axis = 0;
+    w.v.d[0] = Lt.d[2];
+    views.push_back(w);
+  }
+  for (size_t q = 0; q < views.size() && cx.ok; ++q) {
+    const Epi<T> ep = (q + 1 == views.size()) ? last : Epi<T>{EPI_Z, nullptr, Map3{}};
+    launch_solve<T>(F, views[q].v, views[q].axis, ep, cx);
+  }
+}
+
+void launch_tload(const double *G, const Level &Lt, double *F, int64_t ncs, Ctx &cx) {
+  const int64_t tm = Lt.m[2], ct = Lt.c[2];
+  const int64_t nrun = (ct + TL_JC - 1) / TL_JC;
+  const dim3 grid((unsigned)((ncs + 255) / 256), (unsigned)std::min<int64_t>(nrun, 65535));
+  TimedLaunch tl(cx.stream, "k_tload", timing_enabled() ? 8.0 * (double)(tm + ct) * (double)ncs : 0.0);
+  hipLaunchKernelGGL(k_tload, grid, dim3(256), 0, cx.stream, G, tm, Lt.d[2].W, F, ct, ncs);
+  cx.check("k_tload launch");
+}
+
+template <typename T, bool DEC>
+void launch_tfine(const Plan &pl, const Level &L, const Level &Lt, const T *src, T *dst, const T *crs,
+                  Map3 fmap, Ctx &cx) {
+  const int64_t tm = Lt.m[2], nf = (tm - 1) / 2;
+  if (nf <= 0) return;
+  TfineArgs<T> a{};
+  a.src = src; a.dst = dst; a.crs = crs; a.fmap = fmap;
+  a.tnod = Lt.d[2].nodal; a.rt = Lt.d[2].r;
+  a.S0 = pl.n[0] * pl.n[1] * pl.n[2];
+  a.tm = tm;
+  a.m0 = L.m[0]; a.m1 = L.m[1]; a.m2 = L.m[2];
+  a.c0 = L.c[0]; a.c1 = L.c[1]; a.c2 = L.c[2];
+  a.co0 = L.co[0]; a.co1 = L.co[1]; a.co2 = L.co[2];
+  a.r0 = L.d[0].r; a.r1 = L.d[1].r; a.r2 = L.d[2].r;
+  const int64_t sm = L.m[0] * L.m[1] * L.m[2];
+  const dim3 grid((unsigned)((sm + 255) / 256), (unsigned)std::min<int64_t>(nf, 65535));
+  TimedLaunch tl(cx.stream, std::string("k_tfine<") + tname<T>() + ", " + bname(DEC) + ">",
+                 timing_enabled() ? 2.0 * (double)nf * (double)sm * sizeof(T) : 0.0);
+  hipLaunchKernelGGL((k_tfine<T, DEC>), grid, dim3(256), 0, cx.stream, a);
+  cx.check("k_tfine launch");
+}
+
+template <typename T, bool TO_NODAL>
+void launch_nodal4(const Plan &pl, const T *src, T *dst, Ctx &cx) {
+  const Level &L = pl.lev[pl.nlev];
+  const Level &Lt = pl.time->lev[pl.nlev];
+  const int64_t n = Lt.m[2] * L.m[0] * L.m[1] * L.m[2];
+  TimedLaunch tl(cx.stream, std::string("k_nodal4<") + tname<T>() + ", " + bname(TO_NODAL) + ">",
+                 timing_enabled() ? 2.0 * (double)n * sizeof(T) : 0.0);
+  hipLaunchKernelGGL((k_nodal4<T, TO_NODAL>), dim3((unsigned)grid_1d(n, 256)), dim3(256), 0, cx.stream, src, dst,
+                     nodal_map(L), Lt.d[2].nodal, pl.n[0] * pl.n[1] * pl.n[2], Lt.m[2], L.m[0], L.m[1], L.m[2]);
+  cx.check("k_nodal4 launch");
+}
+
+// One level of a 4-D decomposition: the space load vector of every time
+// slice (with the coefficients of the time-coarse slices, which only space
+// interpolation reaches), the load vector along time, the four solves (their
+// solution is the next level's grid), then the coefficients of the time-fine
+// slices.
+template <typename T>
+bool decompose4_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t stream, std::string &err) {
+  Ctx cx{stream, &err};
+  const int64_t S0 = pl.n[0] * pl.n[1] * pl.n[2];
+  if (pl.nlev == 0) {
+    if (hipMemcpyAsync(out, in, pl.nt * S0 * sizeof(T), hipMemcpyDeviceToDevice, stream) != hipSuccess) {
+      err = "hipMemcpyAsync failed";
+      return false;
+    }
+    return true;
+  }
+  const Plan &tp = *pl.time;
+  Workspace4 w = carve4(pl, ws, sizeof(T));
+  const T *src = in;
+  for (int s = 0; s < pl.nlev && cx.ok; ++s) {
+    const Level &L = pl.lev[s];
+    const Level &Lt = tp.lev[s];
+    const int64_t tm = Lt.m[2];
+    const bool cot = Lt.co[2];
+    const int64_t sm = L.m[0] * L.m[1] * L.m[2], cs = L.c[0] * L.c[1] * L.c[2];
+    T *next = (T *)w.buf[s % 2];
+    double *G = cot ? w.G : w.F;
+    const Map3 lmap = compact_map(L.m[1], L.m[2]);
+    const Map3 omap = (s == 0) ? lmap : nodal_map(L);
+    for (int64_t t = 0; t < tm && cx.ok; ++t) {
+      const bool tc = tcoarse(t, tm) || !cot;
+      LoadArgs<T> a{};
+      a.src = src + t * sm;
+      a.smap = lmap;
+      a.out = tc ? out + pl.tpos[s][t] * S0 : nullptr;
+      a.omap = tc ? omap : lmap;
+      a.F = G + t * cs;
+      launch_loadvec<T, true>(L, a, cx);
+    }
+    if (cot && cx.ok) launch_tload(w.G, Lt, w.F, cs, cx);
+    solve_all4<T>(w.F, L, Lt, Epi<T>{EPI_STORE_COMPACT, next, Map3{}}, cx);
+    if (cot && cx.ok) launch_tfine<T, true>(pl, L, Lt, src, out, src, omap, cx);
+    src = next;
+  }
+  if (cx.ok) launch_nodal4<T, true>(pl, src, out, cx);
+  return cx.ok;
+}
+
+// One level of a 4-D recomposition: the load vector of the stored
+// coefficients (zero at the coarse nodes: those of the time-coarse slices
+// that are coarse in space), the solves, whose solution z is subtracted from
+// the stored coarse values, then the level grid: time-coarse slices by the
+// space reconstruct from their coarse slice, time-fine slices by k_tfine.
+template <typename T>
+bool recompose4_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t stream, std::string &err) {
+  Ctx cx{stream, &err};
+  const int64_t S0 = pl.n[0] * pl.n[1] * pl.n[2];
+  if (pl.nlev == 0) {
+    if (hipMemcpyAsync(out, in, pl.nt * S0 * sizeof(T), hipMemcpyDeviceToDevice, stream) != hipSuccess) {
+      err = "hipMemcpyAsync failed";
+      return false;
+    }
+    return true;
+  }
+  const Plan &tp = *pl.time;
+  Workspace4 w = carve4(pl, ws, sizeof(T));
+  T *V = (T *)w.buf[pl.nlev % 2];
+  launch_nodal4<T, false>(pl, in, V, cx);
+  for (int s = pl.nlev - 1; s >= 0 && cx.ok; --s) {
+    const Level &L = pl.lev[s];
+    const Level &Lt = tp.lev[s];
+    const int64_t tm = Lt.m[2], ct = Lt.c[2];
+    const bool cot = Lt.co[2];
+    const int64_t sm = L.m[0] * L.m[1] * L.m[2], cs = L.c[0] * L.c[1] * L.c[2];
+    T *dst = (s == 0) ? out : (T *)w.buf[s % 2];
+    double *G = cot ? w.G : w.F;
+    const Map3 cmap = (s == 0) ? compact_map(L.m[1], L.m[2]) : nodal_map(L);
+    for (int64_t t = 0; t < tm && cx.ok; ++t) {
+      LoadArgs<T> a{};
+      a.src = in + pl.tpos[s][t] * S0;
+      a.smap = cmap;
+      a.F = G + t * cs;
+      a.keep_coarse = (cot && !tcoarse(t, tm)) ? 1 : 0;
+      launch_loadvec<T, false>(L, a, cx);
+    }
+    if (cot && cx.ok) launch_tload(w.G, Lt, w.F, cs, cx);
+    solve_all4<T>(w.F, L, Lt, Epi<T>{EPI_SUB_COMPACT, V, Map3{}}, cx);
+    for (int64_t t = 0; t < tm && cx.ok; ++t) {
+      if (cot && !tcoarse(t, tm)) continue;
+      const int64_t J = cot ? tcoarse_idx(t, tm, ct) : t;
+      launch_reconstruct<T>(L, in + pl.tpos[s][t] * S0, cmap, V + J * cs, dst + t * sm, cx);
+    }
+    if (cot && cx.ok) launch_tfine<T, false>(pl, L, Lt, in, dst, V, cmap, cx);
+    V = dst;
+  }
+  return cx.ok;
+}
+
 // ------------------------------------------------------------ autotuner
 //
 // The paper tunes its kernels' launch shapes per problem size by ranking
@@ -2052,6 +2390,9 @@ bool enqueue_copy_probe(const void *src, void *dst, size_t bytes, void *stream, 
 bool enqueue_decompose(const Plan &pl, bool f64, const void *in, void *out, void *ws, void *stream,
                        std::string &err) {
   hipStream_t st = (hipStream_t)stream;
+  if (pl.time)
+    return f64 ? decompose4_t<double>(pl, (const double *)in, (double *)out, ws, st, err)
+               : decompose4_t<float>(pl, (const float *)in, (float *)out, ws, st, err);
   return f64 ? decompose_t<double>(pl, (const double *)in, (double *)out, ws, st, err)
              : decompose_t<float>(pl, (const float *)in, (float *)out, ws, st, err);
 }
@@ -2059,6 +2400,9 @@ bool enqueue_decompose(const Plan &pl, bool f64, const void *in, void *out, void
 bool enqueue_recompose(const Plan &pl, bool f64, const void *in, void *out, void *ws, void *stream,
                        std::string &err, int nkeep) {
   hipStream_t st = (hipStream_t)stream;
+  if (pl.time)
+    return f64 ? recompose4_t<double>(pl, (const double *)in, (double *)out, ws, st, err)
+               : recompose4_t<float>(pl, (const float *)in, (float *)out, ws, st, err);
   if (nkeep < 0) nkeep = pl.nlev;
   return f64 ? recompose_t<double>(pl, (const double *)in, (double *)out, ws, st, err, nkeep)
              : recompose_t<float>(pl, (const float *)in, (float *)out, ws, st, err, nkeep);

@@ -58,6 +58,21 @@ int max_levels3(const int64_t n[kDims]) {
   return best;
 }
 
+int max_levels4(int64_t nt, const int64_t n[kDims]) {
+  int steps = 0;
+  for (int64_t m = nt; m > 2; m = coarse_count(m)) ++steps;
+  return std::max(steps, max_levels3(n));
+}
+
+size_t workspace_bytes4(int64_t nt, const int64_t n[kDims], int nlev, size_t elem_size) {
+  if (nlev <= 0) return 0;
+  int64_t cs = 1;
+  for (int k = 0; k < kDims; ++k) cs *= coarse_count(n[k]);
+  const int64_t c4 = coarse_count(nt) * cs;
+  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+  return 2 * al((size_t)c4 * elem_size) + al((size_t)c4 * sizeof(double)) + al((size_t)(nt * cs) * sizeof(double));
+}
+
 size_t workspace_bytes(const int64_t n[kDims], int nlev, size_t elem_size) {
   if (nlev <= 0) return 0;
   int64_t c1 = 1;
@@ -210,7 +225,7 @@ SolveTabs solve_tables(const std::vector<double> &X) {
 
 std::unique_ptr<Plan> build_plan(int ndim, const int64_t n[kDims],
                                  const std::vector<std::vector<double>> &coords,
-                                 int nlev, std::string &err, int &status) {
+                                 int nlev, std::string &err, int &status, bool allow_tail) {
   auto plan = std::make_unique<Plan>();
   plan->ndim = ndim;
   for (int k = 0; k < kDims; ++k) plan->n[k] = n[k];
@@ -335,7 +350,7 @@ std::unique_ptr<Plan> build_plan(int ndim, const int64_t n[kDims],
     int64_t noff = 0, ndbl = 0;
     for (int k = 0; k < kDims; ++k) noff += plan->lev[nlev].m[k];
     plan->tail_start = nlev;
-    for (int s = nlev - 1; s >= 0 && nlev - s <= kTailMaxLevels; --s) {
+    for (int s = nlev - 1; allow_tail && s >= 0 && nlev - s <= kTailMaxLevels; --s) {
       const Level &L = plan->lev[s];
       if (L.m[0] * L.m[1] * L.m[2] > kTailNodes || L.m[0] > kTailMaxExtent || L.m[1] > kTailMaxExtent ||
           L.m[2] > kTailMaxExtent)
@@ -435,6 +450,33 @@ std::unique_ptr<Plan> build_plan(int ndim, const int64_t n[kDims],
     return nullptr;
   }
   status = 0;
+  return plan;
+}
+
+std::unique_ptr<Plan> build_plan4(int64_t nt, const int64_t n[kDims],
+                                  const std::vector<std::vector<double>> &coords, int nlev,
+                                  std::string &err, int &status) {
+  std::vector<std::vector<double>> cs(coords.begin() + 1, coords.end());
+  auto plan = build_plan(kDims, n, cs, nlev, err, status, false);
+  if (!plan) return nullptr;
+  const int64_t tn[kDims] = {1, 1, nt};
+  std::vector<std::vector<double>> ct = {{0.0}, {0.0}, coords[0]};
+  plan->time = build_plan(1, tn, ct, nlev, err, status, false);
+  if (!plan->time) return nullptr;
+  plan->ndim = 4;
+  plan->nt = nt;
+  plan->tpos.resize(nlev + 1);
+  std::vector<int64_t> idx(nt);
+  for (int64_t t = 0; t < nt; ++t) idx[t] = t;
+  for (int s = 0; s <= nlev; ++s) {
+    plan->tpos[s] = idx;
+    const int64_t m = (int64_t)idx.size();
+    if (s == nlev || m < 3) continue;
+    std::vector<int64_t> nx;
+    for (int64_t i = 0; i < m; ++i)
+      if (is_coarse(m, i)) nx.push_back(idx[i]);
+    idx = nx;
+  }
   return plan;
 }
 

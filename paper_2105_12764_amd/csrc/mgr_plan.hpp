@@ -100,6 +100,14 @@ struct Plan {
     std::lock_guard<std::mutex> lk(tune_mu);
     return tune;
   }
+  // Four-dimensional fields (Sec. III-F: time as one more tensor-product
+  // dimension).  Dim 0 of the caller's shape is taken as time: this plan then
+  // covers the three remaining dims (one time slice; no tail levels) and
+  // `time` covers dim 0 as a (1, 1, nt) plan.  tpos[s][t] is the finest time
+  // index of time position t of the level-s grid.
+  std::unique_ptr<Plan> time;
+  int64_t nt = 1;
+  std::vector<std::vector<int64_t>> tpos;
   ~Plan();
 };
 
@@ -107,13 +115,23 @@ struct Plan {
 inline int64_t coarse_count(int64_t m) { return m < 3 ? m : m / 2 + 1; }
 
 int max_levels3(const int64_t n[kDims]);
+// Levels of a 4-D grid (nt time positions, space extents n).
+int max_levels4(int64_t nt, const int64_t n[kDims]);
 
 // Builds tables on the host and uploads them to the current device.
-// Returns nullptr and sets `err` on failure.
+// Returns nullptr and sets `err` on failure.  `allow_tail` false keeps every
+// level on the general kernels.
 std::unique_ptr<Plan> build_plan(int ndim, const int64_t n[kDims],
                                  const std::vector<std::vector<double>> &coords,
-                                 int nlev, std::string &err, int &status);
+                                 int nlev, std::string &err, int &status, bool allow_tail = true);
+// A 4-D plan: coords holds the time coordinates, then the three space dims'.
+std::unique_ptr<Plan> build_plan4(int64_t nt, const int64_t n[kDims],
+                                  const std::vector<std::vector<double>> &coords, int nlev,
+                                  std::string &err, int &status);
 
 size_t workspace_bytes(const int64_t n[kDims], int nlev, size_t elem_size);
+// 4-D: two coarse grids in the field's type, the FP64 load/correction grid
+// and the FP64 per-slice load vectors (nt slices of the coarse space grid).
+size_t workspace_bytes4(int64_t nt, const int64_t n[kDims], int nlev, size_t elem_size);
 
 }  // namespace mgr

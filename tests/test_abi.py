@@ -36,7 +36,8 @@ def test_missing_library_fails_loudly(monkeypatch):
 
 
 @pytest.mark.parametrize("shape", [(513, 513, 513), (65, 65, 65), (400, 300, 250), (2, 2, 2),
-                                   (3,), (1000,), (129, 70), (5, 2, 9), (2, 1025)])
+                                   (3,), (1000,), (129, 70), (5, 2, 9), (2, 1025),
+                                   (16, 65, 65, 65), (65, 9, 9, 5), (2, 2, 2, 2), (3, 2, 2, 2)])
 def test_max_levels_matches_oracle(shape):
     assert mgr.max_levels(shape) == oracle.max_levels(shape)
 
@@ -49,6 +50,14 @@ def test_workspace_size():
     assert mgr.workspace_size((513, 513, 513), np.float32, 9) == 2 * al(4 * n1) + al(8 * n1)
     with pytest.raises(mgr.MgrError):
         mgr.workspace_size((513, 513, 513), np.float64, 10)
+    # 4-D: two coarse 4-D grids in the field's type, the FP64 coarse grid and
+    # the FP64 load vectors of every time slice
+    cs, ct = 201 ** 3, 9
+    assert mgr.workspace_size((16, 401, 401, 401), np.float32, 8) == \
+        2 * al(4 * ct * cs) + al(8 * ct * cs) + al(8 * 16 * cs)
+    assert mgr.workspace_size((16, 401, 401, 401), np.float32, 0) == 0
+    with pytest.raises(mgr.MgrError):
+        mgr.workspace_size((16, 401, 401, 401), np.float32, 10)
 
 
 def _call(shape=(5, 5, 5), coords=None, dtype=mgr.MGR_FLOAT64, nlev=2, inp=4096,
@@ -72,8 +81,13 @@ def _call(shape=(5, 5, 5), coords=None, dtype=mgr.MGR_FLOAT64, nlev=2, inp=4096,
 @pytest.mark.parametrize("fn", ["mgr_decompose", "mgr_recompose"])
 def test_invalid_arguments_are_rejected_before_any_device_call(fn):
     E = mgr.MGR_ERR_INVALID_ARG
-    assert _call(shape=(5, 5, 5, 5), fn=fn) == E
+    assert _call(shape=(5, 5, 5, 5, 5), fn=fn) == E
     assert _call(shape=(5, 1, 5), fn=fn) == E
+    # 4-D (time, then space): rejected shapes and level counts, all before any device call
+    assert _call(shape=(1, 5, 5, 5), fn=fn) == E
+    assert _call(shape=(5, 5, 1, 5), fn=fn) == E
+    assert _call(shape=(5, 5, 5, 5), nlev=3, fn=fn) == E
+    assert _call(shape=(5, 5, 5, 5), nlev=2, ws=0, fn=fn) == mgr.MGR_ERR_WORKSPACE
     assert _call(nlev=3, fn=fn) == E
     assert _call(nlev=-1, fn=fn) == E
     assert _call(dtype=7, fn=fn) == E

@@ -1,0 +1,92 @@
+"""GPU: 4-D fields (time as a fourth tensor-product dimension, Sec. III-F).
+
+The decomposition must match the oracle's 4-D decomposition to 1e-12 relative
+(FP64) or 1e-5 relative L2 (FP32); the recomposition must rebuild the field
+from the oracle's coefficients and from the GPU's own.  Cases cover time
+coarsened and not, time the longest dim, a size-2 space dim, partial depth,
+odd and even extents, and non-uniform coordinates.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2105_12764_amd import mgr
+from paper_2105_12764_amd.synth import make_input
+
+pytestmark = pytest.mark.gpu
+
+# (shape (time first), nlevels or None for all, non-uniform coordinates, dtype)
+CASES = [
+    ((5, 9, 9, 9), None, False, np.float64),
+    ((16, 33, 17, 20), None, True, np.float64),
+    ((7, 2, 17, 10), None, True, np.float64),
+    ((65, 9, 9, 5), None, True, np.float64),      # time the longest dim
+    ((2, 17, 17, 17), None, False, np.float64),   # time never coarsened
+    ((6, 7, 10, 12), 2, True, np.float64),        # even extents, partial depth
+    ((3, 5, 5, 5), 1, False, np.float64),
+    ((9, 33, 33, 33), None, True, np.float32),
+    ((16, 20, 30, 41), 3, False, np.float32),
+]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    mgr.lib()
+
+
+def _err(got, ref, dtype):
+    got = got.astype(np.float64)
+    if dtype == np.float64:
+        return float(np.max(np.abs(got - ref)) / max(np.max(np.abs(ref)), 1e-300))
+    return float(np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-300))
+
+
+@pytest.mark.parametrize("shape,nlev,nonuni,dtype", CASES)
+def test_4d_matches_oracle(shape, nlev, nonuni, dtype):
+    print(f"\n[case] 4-D {shape} nlev={nlev} nonuniform={nonuni} {np.dtype(dtype).name}", flush=True)
+    u, coords = make_input(shape, 700 + sum(shape), nonuniform=nonuni, dtype=dtype)
+    if nlev is None:
+        nlev = oracle.max_levels(shape)
+    assert mgr.max_levels(shape) == oracle.max_levels(shape)
+    tol = 1e-12 if dtype == np.float64 else 1e-5
+    ref = oracle.decompose(u.astype(np.float64), coords, nlev)
+    x = torch.from_numpy(u).cuda()
+    d = mgr.decompose(x, coords, nlev)
+    r = mgr.recompose(d, coords, nlev)
+    # recomposition of the oracle's coefficients (rounded to the field's type)
+    r2 = mgr.recompose(torch.from_numpy(ref.astype(dtype)).cuda(), coords, nlev)
+    torch.cuda.synchronize()
+    e_dec = _err(d.cpu().numpy(), ref, dtype)
+    e_rt = _err(r.cpu().numpy(), u.astype(np.float64), dtype)
+    e_rec = _err(r2.cpu().numpy(), oracle.recompose(ref.astype(dtype).astype(np.float64), coords, nlev), dtype)
+    print(f"  dec {e_dec:.2e}  round trip {e_rt:.2e}  recompose(oracle coefficients) {e_rec:.2e}", flush=True)
+    assert e_dec <= tol
+    assert e_rt <= tol
+    assert e_rec <= tol
+
+
+def test_4d_zero_levels_is_a_copy():
+    u, coords = make_input((4, 5, 6, 7), 3, nonuniform=True)
+    x = torch.from_numpy(u).cuda()
+    d = mgr.decompose(x, coords, 0)
+    torch.cuda.synchronize()
+    assert torch.equal(d, x)
+
+
+def test_4d_large_round_trip():
+    """16 time steps of 129^3 FP64, all levels: round trip to 1e-12."""
+    shape = (16, 129, 129, 129)
+    print(f"\n[case] 4-D round trip {shape}", flush=True)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(4242)
+    x = torch.randn(shape, dtype=torch.float64, device="cuda", generator=g)
+    nlev = mgr.max_levels(shape)
+    d = mgr.decompose(x, None, nlev)
+    r = mgr.recompose(d, None, nlev)
+    torch.cuda.synchronize()
+    err = float((r - x).abs().max() / x.abs().max())
+    print(f"  round trip {err:.2e}", flush=True)
+    assert err <= 1e-12
