@@ -58,6 +58,14 @@ __device__ __forceinline__ int64_t moff(const Map3 &m, int64_t i, int64_t j, int
 // Linear interpolation between a (left) and b (right) with the weight r of
 // the right node, in the paper's FMA form (Sec. III-E, Table III).
 __device__ __forceinline__ double lerp(double a, double b, double r) { return fma(r, b, fma(-r, a, a)); }
+__device__ __forceinline__ float lerp(float a, float b, float r) { return fmaf(r, b, fmaf(-r, a, a)); }
+
+// Arithmetic type of the interpolation and load-vector stencils: the field's
+// own type.  The FP32 mode keeps FP64 for the load vector it hands to the
+// solves (each stencil result is widened once, where it is stored) and for
+// the correction solves themselves.
+template <typename T>
+using Acc = T;
 
 template <bool CO>
 __device__ __forceinline__ bool coarse_pos(int64_t g, int64_t m) {
@@ -122,6 +130,7 @@ __device__ __forceinline__ int xcd_tile(int bid, int nb) {
 // and forms f = (P^T M)^{(x)3} C the same way.
 template <typename T, bool DEC, bool NODAL, bool CO0, bool CO1, bool CO2>
 __global__ void __launch_bounds__(NTHR, LV_WAVES) k_loadvec(LoadArgs<T> a) {
+  using A = Acc<T>;
   constexpr int SJ = CO1 ? 2 : 1, HJ = CO1 ? 2 : 0;
   constexpr int SK = CO2 ? 2 : 1, HK = CO2 ? 2 : 0;
   constexpr int NJ = SJ * (TJ - 1) + 1 + 2 * HJ;
@@ -129,15 +138,15 @@ __global__ void __launch_bounds__(NTHR, LV_WAVES) k_loadvec(LoadArgs<T> a) {
   constexpr int NE = NJ * NK;
   constexpr int EPT = (NE + NTHR - 1) / NTHR;  // tile elements per thread
   constexpr int NG = NJ * TK;                  // dim-2 reduced rows of one plane
-  __shared__ double sA[NE];      // plane b (coarse along dim 0)
-  __shared__ double sB[NE];      // plane a (fine along dim 0)
-  __shared__ double sG[2 * NG];  // dim-2 reduced rows of b, then of a
-  __shared__ double sR1[DEC ? NJ : 1], sR2[DEC ? NK : 1];  // interpolation weights of rows / columns
+  __shared__ A sA[NE];      // plane b (coarse along dim 0)
+  __shared__ A sB[NE];      // plane a (fine along dim 0)
+  __shared__ A sG[2 * NG];  // dim-2 reduced rows of b, then of a
+  __shared__ A sR1[DEC ? NJ : 1], sR2[DEC ? NK : 1];  // interpolation weights of rows / columns
   // Tables read inside the plane loop are staged in LDS (or loaded one step
   // ahead with the prefetch): a vector-memory read of a table there would
   // make the compiler wait for the in-flight prefetch loads.
   __shared__ int64_t sPO[NODAL ? LV_MAXP : 1];  // nodal plane offsets of the window
-  __shared__ double sStep[2][6];                // per-step dim-0 taps and weight
+  __shared__ A sStep[2][6];                // per-step dim-0 taps and weight
 
   const int tid = threadIdx.x;
   const int tile = xcd_tile(blockIdx.x, a.gx * a.gy * a.gz);
@@ -184,11 +193,11 @@ __global__ void __launch_bounds__(NTHR, LV_WAVES) k_loadvec(LoadArgs<T> a) {
   if (DEC) {
     for (int j = tid; j < NJ; j += NTHR) {
       const int64_t gj = fj0 + j;
-      sR1[j] = (CO1 && gj >= 0 && gj < a.m1 && !coarse_pos<CO1>(gj, a.m1)) ? a.r1[gj] : 0.0;
+      sR1[j] = (CO1 && gj >= 0 && gj < a.m1 && !coarse_pos<CO1>(gj, a.m1)) ? a.r1[gj] : A(0);
     }
     for (int k = tid; k < NK; k += NTHR) {
       const int64_t gk = fk0 + k;
-      sR2[k] = (CO2 && gk >= 0 && gk < a.m2 && !coarse_pos<CO2>(gk, a.m2)) ? a.r2[gk] : 0.0;
+      sR2[k] = (CO2 && gk >= 0 && gk < a.m2 && !coarse_pos<CO2>(gk, a.m2)) ? a.r2[gk] : A(0);
     }
   }
 
@@ -205,30 +214,30 @@ __global__ void __launch_bounds__(NTHR, LV_WAVES) k_loadvec(LoadArgs<T> a) {
   // loads of one plane into registers.  Branch-free, so that all of them
   // are in flight together: elements outside the grid read the plane's first
   // node (colS = 0) and are masked when staged.
-  auto fetch = [&](double (&v)[EPT], int64_t p) {
+  auto fetch = [&](A (&v)[EPT], int64_t p) {
     const T *base = a.src + src_plane(p);
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) v[i] = (double)base[colS[i]];
+    for (int i = 0; i < EPT; ++i) v[i] = (A)base[colS[i]];
   };
   // stage a plane into LDS: zero outside the grid and, for recomposition of a
   // plane coarse along dim 0, at the stored coarse values (not coefficients)
-  auto stage = [&](double *s, const double (&v)[EPT], bool zero_coarse) {
+  auto stage = [&](A *s, const A (&v)[EPT], bool zero_coarse) {
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
       const int e = tid + i * NTHR;
       const unsigned f = flag_of(i);
       const bool keep = (f & F_IN) && !(zero_coarse && (f & F_C1) && (f & F_C2));
-      if (e < NE) s[e] = keep ? v[i] : 0.0;
+      if (e < NE) s[e] = keep ? v[i] : A(0);
     }
   };
 
   // bilinear interpolant (dims 1, 2) at tile element e of the staged plane s,
   // branch-free: along a dimension where the node is coarse both neighbours
   // are the node itself and the weight is 0 (the weight tables hold 0 there)
-  auto interp2 = [&](const double *s, int e, unsigned f) -> double {
-    if (!(f & F_IN)) return 0.0;
+  auto interp2 = [&](const A *s, int e, unsigned f) -> A {
+    if (!(f & F_IN)) return A(0);
     const int dk = (f & F_C2) ? 0 : 1, dj = (f & F_C1) ? 0 : NK;
-    const double rk = sR2[e % NK], rj = sR1[e / NK];
+    const A rk = sR2[e % NK], rj = sR1[e / NK];
     return lerp(lerp(s[e - dj - dk], s[e - dj + dk], rk), lerp(s[e + dj - dk], s[e + dj + dk], rk), rj);
   };
 
@@ -241,43 +250,30 @@ __global__ void __launch_bounds__(NTHR, LV_WAVES) k_loadvec(LoadArgs<T> a) {
   const int rK = tid / RG, rj0 = tid % RG;
   const bool rOK = K0 + rK < a.c2;
   // taps of this thread's dim-2 column and dim-1 row: via LDS into registers
-  __shared__ double sW[(TJ + TK) * 5];
+  __shared__ A sW[(TJ + TK) * 5];
   for (int e = tid; e < TK * 5; e += NTHR)
-    sW[TJ * 5 + e] = (CO2 && K0 + e / 5 < a.c2) ? a.W2[K0 * 5 + e] : 0.0;
+    sW[TJ * 5 + e] = (CO2 && K0 + e / 5 < a.c2) ? a.W2[K0 * 5 + e] : A(0);
   for (int e = tid; e < TJ * 5; e += NTHR)
-    sW[e] = (CO1 && J0 + e / 5 < a.c1) ? a.W1[J0 * 5 + e] : 0.0;
+    sW[e] = (CO1 && J0 + e / 5 < a.c1) ? a.W1[J0 * 5 + e] : A(0);
   __syncthreads();
-  // Taps of this thread's dim-2 column and dim-1 row: kept in registers, or
-  // -- for the FP32 decomposition, which is issue-bound rather than
-  // memory-bound -- read from LDS where used, which brings it under 128
-  // VGPRs and two resident workgroups per CU (measured faster there, slower
-  // for the FP64 and recomposition kernels).
-  constexpr bool kTapsInLds = DEC && sizeof(T) == 4;
-  double w1r[kTapsInLds ? 1 : 5], w2r[kTapsInLds ? 1 : 5];
-  if constexpr (!kTapsInLds) {
+  // taps of this thread's dim-2 column and dim-1 row, kept in registers
+  A w2r[5], w1r[5];
 #pragma unroll
-    for (int o = 0; o < 5; ++o) {
-      w2r[o] = sW[TJ * 5 + rK * 5 + o];
-      w1r[o] = sW[hJ * 5 + o];
-    }
+  for (int o = 0; o < 5; ++o) {
+    w2r[o] = sW[TJ * 5 + rK * 5 + o];
+    w1r[o] = sW[hJ * 5 + o];
   }
-  auto w2 = [&](int o) -> double {
-    if constexpr (kTapsInLds) return sW[TJ * 5 + rK * 5 + o];
-    else return w2r[o];
-  };
-  auto w1 = [&](int o) -> double {
-    if constexpr (kTapsInLds) return sW[hJ * 5 + o];
-    else return w1r[o];
-  };
-  auto reduce2 = [&](const double *s, int off) {
+  auto w2 = [&](int o) -> A { return w2r[o]; };
+  auto w1 = [&](int o) -> A { return w1r[o]; };
+  auto reduce2 = [&](const A *s, int off) {
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
       const int j = rj0 + q * RG;
       if (j < NJ) {
-        double g = 0.0;
+        A g = A(0);
         if (rOK) {
           if (CO2) {
-            const double *row = s + j * NK + 2 * rK;
+            const A *row = s + j * NK + 2 * rK;
 #pragma unroll
             for (int o = 0; o < 5; ++o) g = fma(w2(o), row[o], g);
           } else {
@@ -289,10 +285,10 @@ __global__ void __launch_bounds__(NTHR, LV_WAVES) k_loadvec(LoadArgs<T> a) {
     }
   };
   // P^T M along dim 1 of the reduced rows at sG + off, for this thread's (J, K)
-  auto reduce1 = [&](int off) -> double {
-    double h = 0.0;
+  auto reduce1 = [&](int off) -> A {
+    A h = A(0);
     if (hOK) {
-      const double *col = sG + off + hK * NJ;
+      const A *col = sG + off + hK * NJ;
       if (CO1) {
 #pragma unroll
         for (int o = 0; o < 5; ++o) h = fma(w1(o), col[2 * hJ + o], h);
@@ -303,10 +299,10 @@ __global__ void __launch_bounds__(NTHR, LV_WAVES) k_loadvec(LoadArgs<T> a) {
     return h;
   };
 
-  double piPrev[EPT], piNext[EPT];
+  A piPrev[EPT], piNext[EPT];
 #pragma unroll
-  for (int i = 0; i < EPT; ++i) piPrev[i] = piNext[i] = 0.0;
-  double h0 = 0.0, h1 = 0.0, h2 = 0.0, h3 = 0.0, h4 = 0.0;
+  for (int i = 0; i < EPT; ++i) piPrev[i] = piNext[i] = A(0);
+  A h0 = A(0), h1 = A(0), h2 = A(0), h3 = A(0), h4 = A(0);
 
   // step schedule: with dim 0 coarsened, step I covers fine planes
   // (2I+1, 2I+2) for I in [I0-2, I1-1] and emits F[I] for I >= I0; without,
@@ -335,7 +331,7 @@ __global__ void __launch_bounds__(NTHR, LV_WAVES) k_loadvec(LoadArgs<T> a) {
     }
     kv = *kp;
   };
-  double va[EPT], vb[EPT];
+  A va[EPT], vb[EPT];
   {
     int64_t pa, pb;
     planes(sbeg, pa, pb);
@@ -349,7 +345,7 @@ __global__ void __launch_bounds__(NTHR, LV_WAVES) k_loadvec(LoadArgs<T> a) {
     const bool b_in_a_slot = CO0 && pb >= 0 && pb == 2 * I + 1;  // coarse plane in the fine slot
     if (pb >= 0) stage(sA, vb, !DEC && !a.keep_coarse);
     if (pa >= 0) stage(sB, va, false);
-    double *kst = sStep[I & 1];
+    A *kst = sStep[I & 1];
     if (tid < 6) kst[tid] = kv;
     // prefetch the next step while this one computes
     if (I + 1 < send) {
@@ -390,16 +386,16 @@ __global__ void __launch_bounds__(NTHR, LV_WAVES) k_loadvec(LoadArgs<T> a) {
       }
     }
     __syncthreads();
-    const double hb = pb >= 0 ? reduce1(0) : 0.0;
-    const double ha = pa >= 0 ? reduce1(NG) : 0.0;
+    const A hb = pb >= 0 ? reduce1(0) : A(0);
+    const A ha = pa >= 0 ? reduce1(NG) : A(0);
     if (CO0) {
       h0 = h2;
       h1 = h3;
       h2 = h4;
       h3 = b_in_a_slot ? hb : ha;
-      h4 = b_in_a_slot ? 0.0 : hb;
+      h4 = b_in_a_slot ? A(0) : hb;
       if (I >= I0 && hOK) {
-        double f = kst[0] * h0;
+        A f = kst[0] * h0;
         f = fma(kst[1], h1, f);
         f = fma(kst[2], h2, f);
         f = fma(kst[3], h3, f);
@@ -811,19 +807,20 @@ struct ReconArgs {
 
 template <typename T, bool NODALC, bool CO0, bool CO1, bool CO2>
 __global__ void __launch_bounds__(RC_THR) k_reconstruct(ReconArgs<T> a) {
+  using A = Acc<T>;
   constexpr int SJ = CO1 ? 2 : 1, SK = CO2 ? 2 : 1;
   const int FJ = SJ * a.TJ, FK = SK * a.TK;  // owned fine tile (host: FJ * FK <= RC_NE)
   const int NE = FJ * FK;
   const int CK = a.TK + (CO2 ? 1 : 0);       // coarse tile with halo (host: CJ * CK <= RC_NC)
   const int NC = (a.TJ + (CO1 ? 1 : 0)) * CK;
-  __shared__ double sU[2][RC_NC];  // coarse values of the current / previous coarse plane
+  __shared__ A sU[2][RC_NC];  // coarse values of the current / previous coarse plane
   // interpolation weights of the tile's rows, then of its columns (FJ + FK <= RC_NE + 1)
-  __shared__ double sR[RC_NE + 1];
-  double *sR1 = sR, *sR2 = sR + FJ;
+  __shared__ A sR[RC_NE + 1];
+  A *sR1 = sR, *sR2 = sR + FJ;
   // tables read inside the plane loop come from LDS or are loaded one step
   // ahead with the prefetch (see k_loadvec)
   __shared__ int64_t sPO[NODALC ? LV_MAXP : 1];  // nodal plane offsets of the coefficients
-  __shared__ double sR0[2];                      // dim-0 weight of the step's fine plane
+  __shared__ A sR0[2];                      // dim-0 weight of the step's fine plane
 
   const int tid = threadIdx.x;
   const int tile = xcd_tile(blockIdx.x, a.gx * a.gy * a.gz);
@@ -865,11 +862,11 @@ __global__ void __launch_bounds__(RC_THR) k_reconstruct(ReconArgs<T> a) {
   auto flag_of = [&](int i) -> unsigned { return (flags >> (3 * i)) & 7u; };
   for (int j = tid; j < FJ; j += RC_THR) {
     const int64_t gj = fj0 + j;
-    sR1[j] = (CO1 && gj < a.m1 && !coarse_pos<CO1>(gj, a.m1)) ? a.r1[gj] : 0.0;
+    sR1[j] = (CO1 && gj < a.m1 && !coarse_pos<CO1>(gj, a.m1)) ? a.r1[gj] : A(0);
   }
   for (int k = tid; k < FK; k += RC_THR) {
     const int64_t gk = fk0 + k;
-    sR2[k] = (CO2 && gk < a.m2 && !coarse_pos<CO2>(gk, a.m2)) ? a.r2[gk] : 0.0;
+    sR2[k] = (CO2 && gk < a.m2 && !coarse_pos<CO2>(gk, a.m2)) ? a.r2[gk] : A(0);
   }
 
   // coarse-tile elements this thread stages
@@ -887,31 +884,31 @@ __global__ void __launch_bounds__(RC_THR) k_reconstruct(ReconArgs<T> a) {
 
   // branch-free loads (invalid elements read a valid node and are never used);
   // a level whose coefficients are dropped (partial recomposition) reads none
-  auto fetchC = [&](double (&v)[RC_EPT], int64_t p) {
+  auto fetchC = [&](A (&v)[RC_EPT], int64_t p) {
     if (!a.coef) {
 #pragma unroll
-      for (int i = 0; i < RC_EPT; ++i) v[i] = 0.0;
+      for (int i = 0; i < RC_EPT; ++i) v[i] = A(0);
       return;
     }
     const T *base = a.coef + (NODALC ? sPO[p - pw0] : p * a.m1 * a.m2);
 #pragma unroll
-    for (int i = 0; i < RC_EPT; ++i) v[i] = (double)base[colC[i]];
+    for (int i = 0; i < RC_EPT; ++i) v[i] = (A)base[colC[i]];
   };
-  auto fetchU = [&](double (&v)[RC_EPC], int64_t cp) {
+  auto fetchU = [&](A (&v)[RC_EPC], int64_t cp) {
     const T *base = a.uc + cp * a.c1 * a.c2;
 #pragma unroll
-    for (int i = 0; i < RC_EPC; ++i) v[i] = (double)base[ucol[i] >= 0 ? ucol[i] : 0];
+    for (int i = 0; i < RC_EPC; ++i) v[i] = (A)base[ucol[i] >= 0 ? ucol[i] : 0];
   };
   double kv = 0.0;  // dim-0 weight of the fine plane of a step (thread 0), loaded a step ahead
-  auto fetch_r0 = [&](int64_t pa) { kv = a.r0 ? a.r0[pa >= 0 ? pa : 0] : 0.0; };
+  auto fetch_r0 = [&](int64_t pa) { kv = a.r0 ? a.r0[pa >= 0 ? pa : 0] : A(0); };
   // interpolant (dims 1, 2) of owned element i from the staged coarse tile s
-  auto interp2 = [&](const double *s, int i) -> double {
+  auto interp2 = [&](const A *s, int i) -> A {
     const unsigned f = flag_of(i);
-    if (!(f & F_IN)) return 0.0;
+    if (!(f & F_IN)) return A(0);
     const int l = lo[i];
     const bool c1 = f & F_C1, c2 = f & F_C2;
     if (c1 && c2) return s[l];
-    const double rk = sR2[jk[i] & 0xffff], rj = sR1[jk[i] >> 16];
+    const A rk = sR2[jk[i] & 0xffff], rj = sR1[jk[i] >> 16];
     if (c1) return lerp(s[l], s[l + 1], rk);
     if (c2) return lerp(s[l], s[l + CK], rj);
     return lerp(lerp(s[l], s[l + 1], rk), lerp(s[l + CK], s[l + CK + 1], rk), rj);
@@ -930,10 +927,10 @@ __global__ void __launch_bounds__(RC_THR) k_reconstruct(ReconArgs<T> a) {
     if (pa >= 0 && pb < 0) { pb = pa; pa = -1; }  // last plane of an even extent is coarse
   };
 
-  double ca[RC_EPT], cb[RC_EPT], uv[RC_EPC];
-  double piPrev[RC_EPT], piNext[RC_EPT];
+  A ca[RC_EPT], cb[RC_EPT], uv[RC_EPC];
+  A piPrev[RC_EPT], piNext[RC_EPT];
 #pragma unroll
-  for (int i = 0; i < RC_EPT; ++i) piPrev[i] = piNext[i] = 0.0;
+  for (int i = 0; i < RC_EPT; ++i) piPrev[i] = piNext[i] = A(0);
   {
     int64_t pa, pb;
     planes(sbeg, pa, pb);
@@ -945,16 +942,16 @@ __global__ void __launch_bounds__(RC_THR) k_reconstruct(ReconArgs<T> a) {
   for (int64_t I = sbeg; I < send; ++I) {
     int64_t pa, pb;
     planes(I, pa, pb);
-    double *s = sU[buf];
+    A *s = sU[buf];
     if (pb >= 0) {
 #pragma unroll
       for (int i = 0; i < RC_EPC; ++i) {
         const int e = tid + i * RC_THR;
-        if (e < NC) s[e] = ucol[i] >= 0 ? uv[i] : 0.0;
+        if (e < NC) s[e] = ucol[i] >= 0 ? uv[i] : A(0);
       }
     }
     if (tid == 0) sR0[buf] = kv;
-    double xb[RC_EPT], xa[RC_EPT];
+    A xb[RC_EPT], xa[RC_EPT];
 #pragma unroll
     for (int i = 0; i < RC_EPT; ++i) {
       xb[i] = cb[i];
