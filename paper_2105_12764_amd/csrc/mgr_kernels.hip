@@ -1083,40 +1083,74 @@ struct TfineArgs {
 // coefficient, and its interpolant is the space-multilinear interpolant of the
 // time lerp (weight rt[t] of the later slice) of the coarse values of slices
 // t - 1 and t + 1.  Decompose: coefficient = value - interpolant; recompose:
-// value = coefficient + interpolant.  Grid: x over the slice's nodes, y over q.
+// value = coefficient + interpolant.  A workgroup takes TF_ROWS fine rows of
+// one plane i of one such slice at a time: it stages in LDS, for the coarse
+// rows and columns they need, the lerp in time and along dim 0 (four loads
+// per coarse node), then each fine node interpolates along dims 1 and 2 from
+// LDS.
+constexpr int TF_THR = 256;
+constexpr int TF_ROWS = 8;   // fine rows (dim 1) per workgroup
+constexpr int TF_CH = 512;   // fine columns (dim 2) per pass
+constexpr int TF_PITCH = TF_CH + 2;
 template <typename T, bool DEC>
-__global__ void __launch_bounds__(256) k_tfine(TfineArgs<T> a) {
+__global__ void __launch_bounds__(TF_THR) k_tfine(TfineArgs<T> a) {
+  __shared__ double sR[TF_ROWS * TF_PITCH];
+  const int tid = threadIdx.x;
   const int64_t sm = a.m0 * a.m1 * a.m2;
-  const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (x >= sm) return;
-  const uint32_t ux = (uint32_t)x, um2 = (uint32_t)a.m2, um1 = (uint32_t)a.m1;
-  const int64_t k = ux % um2, row = ux / um2, j = row % um1, i = row / um1;
-  int64_t l0, h0, l1, h1, l2, h2;
-  double w0, w1, w2;
-  nb_dim<DEC>(i, a.m0, a.c0, a.co0, a.r0, l0, h0, w0);
-  nb_dim<DEC>(j, a.m1, a.c1, a.co1, a.r1, l1, h1, w1);
-  nb_dim<DEC>(k, a.m2, a.c2, a.co2, a.r2, l2, h2, w2);
-  // strides of the array holding the coarse values
-  const int64_t s1 = DEC ? a.m2 : a.c2, s0 = s1 * (DEC ? a.m1 : a.c1), ss = s0 * (DEC ? a.m0 : a.c0);
   const int64_t nf = (a.tm - 1) / 2;  // odd positions below the last
-  for (int64_t q = blockIdx.y; q < nf; q += gridDim.y) {
+  const int64_t ngr = (a.m1 + TF_ROWS - 1) / TF_ROWS;
+  // strides of the array holding the coarse values (DEC: the level grid)
+  const int64_t s1 = DEC ? a.m2 : a.c2, s0 = s1 * (DEC ? a.m1 : a.c1), ss = s0 * (DEC ? a.m0 : a.c0);
+  // array position of coarse index X along a dim (DEC: its level position)
+  auto cpos = [](int64_t X, int64_t m, int64_t c, int co) -> int64_t {
+    return (DEC && co) ? (X == c - 1 ? m - 1 : 2 * X) : X;
+  };
+  for (int64_t job = blockIdx.x; job < nf * a.m0 * ngr; job += gridDim.x) {
+    const int64_t q = job / (a.m0 * ngr), rem = job - q * (a.m0 * ngr);
+    const int64_t i = rem / ngr, j0 = (rem - i * ngr) * TF_ROWS, j1 = min(j0 + TF_ROWS, a.m1);
     const int64_t t = 2 * q + 1;
-    auto tri = [&](const T *c) -> double {
-      auto row2 = [&](int64_t o) {
-        return lerp(lerp((double)c[o + l1 * s1 + l2], (double)c[o + l1 * s1 + h2], w2),
-                    lerp((double)c[o + h1 * s1 + l2], (double)c[o + h1 * s1 + h2], w2), w1);
-      };
-      return lerp(row2(l0 * s0), row2(h0 * s0), w0);
-    };
-    // earlier and later coarse slices: level positions t -/+ 1, or coarse indices q, q + 1
-    const T *cl = a.crs + (DEC ? t - 1 : q) * ss, *cr = a.crs + (DEC ? t + 1 : q + 1) * ss;
-    const double pi = lerp(tri(cl), tri(cr), a.rt[t]);
-    const int64_t fo = a.tnod[t] * a.S0 + moff(a.fmap, i, j, k);
-    const int64_t lo = t * sm + x;
-    if (DEC)
-      a.dst[fo] = (T)((double)a.src[lo] - pi);
-    else
-      a.dst[lo] = (T)((double)a.src[fo] + pi);
+    int64_t l0, h0, J0, J1, lo, hi;
+    double w0, w;
+    nb_dim<DEC>(i, a.m0, a.c0, a.co0, a.r0, l0, h0, w0);
+    nb_dim<false>(j0, a.m1, a.c1, a.co1, a.r1, J0, hi, w);
+    nb_dim<false>(j1 - 1, a.m1, a.c1, a.co1, a.r1, lo, J1, w);
+    const double rt = a.rt[t];
+    // the earlier and later coarse slices (level positions t -/+ 1, or coarse indices q, q + 1)
+    const T *cl = a.crs + (DEC ? t - 1 : q) * ss + l0 * s0, *cr = a.crs + (DEC ? t + 1 : q + 1) * ss + l0 * s0;
+    const int64_t dh = (h0 - l0) * s0;
+    const int64_t frow = a.tnod[t] * a.S0;  // this slice in the finest layout
+    for (int64_t k0 = 0; k0 < a.m2; k0 += TF_CH) {
+      const int64_t k1 = min(k0 + TF_CH, a.m2);
+      int64_t K0, K1;
+      nb_dim<false>(k0, a.m2, a.c2, a.co2, a.r2, K0, hi, w);
+      nb_dim<false>(k1 - 1, a.m2, a.c2, a.co2, a.r2, lo, K1, w);
+      const int64_t nK = K1 - K0 + 1, nst = (J1 - J0 + 1) * nK;
+      for (int64_t e = tid; e < nst; e += TF_THR) {
+        const int64_t Jr = e / nK, Kr = e - Jr * nK;
+        const int64_t o = cpos(J0 + Jr, a.m1, a.c1, a.co1) * s1 + cpos(K0 + Kr, a.m2, a.c2, a.co2);
+        const double vl = lerp((double)cl[o], (double)cl[o + dh], w0);
+        const double vr = lerp((double)cr[o], (double)cr[o + dh], w0);
+        sR[Jr * TF_PITCH + Kr] = lerp(vl, vr, rt);
+      }
+      __syncthreads();
+      const int64_t nk = k1 - k0, nfine = (j1 - j0) * nk;
+      for (int64_t e = tid; e < nfine; e += TF_THR) {
+        const int64_t jr = e / nk, j = j0 + jr, k = k0 + (e - jr * nk);
+        int64_t jl, jh, kl, kh;
+        double wj, wk;
+        nb_dim<false>(j, a.m1, a.c1, a.co1, a.r1, jl, jh, wj);
+        nb_dim<false>(k, a.m2, a.c2, a.co2, a.r2, kl, kh, wk);
+        const double *rl = sR + (jl - J0) * TF_PITCH - K0, *rh = sR + (jh - J0) * TF_PITCH - K0;
+        const double pi = lerp(lerp(rl[kl], rl[kh], wk), lerp(rh[kl], rh[kh], wk), wj);
+        const int64_t fo = frow + moff(a.fmap, i, j, k);
+        const int64_t lv = t * sm + (i * a.m1 + j) * a.m2 + k;
+        if (DEC)
+          a.dst[fo] = (T)((double)a.src[lv] - pi);
+        else
+          a.dst[lv] = (T)((double)a.src[fo] + pi);
+      }
+      __syncthreads();
+    }
   }
 }
 
@@ -2017,10 +2051,11 @@ void launch_tfine(const Plan &pl, const Level &L, const Level &Lt, const T *src,
   a.co0 = L.co[0]; a.co1 = L.co[1]; a.co2 = L.co[2];
   a.r0 = L.d[0].r; a.r1 = L.d[1].r; a.r2 = L.d[2].r;
   const int64_t sm = L.m[0] * L.m[1] * L.m[2];
-  const dim3 grid((unsigned)((sm + 255) / 256), (unsigned)std::min<int64_t>(nf, 65535));
+  const int64_t jobs = nf * L.m[0] * ((L.m[1] + TF_ROWS - 1) / TF_ROWS);  // row groups of the time-fine slices
+  const dim3 grid((unsigned)std::min<int64_t>(jobs, (int64_t)1 << 20));
   TimedLaunch tl(cx.stream, std::string("k_tfine<") + tname<T>() + ", " + bname(DEC) + ">",
                  timing_enabled() ? 2.0 * (double)nf * (double)sm * sizeof(T) : 0.0);
-  hipLaunchKernelGGL((k_tfine<T, DEC>), grid, dim3(256), 0, cx.stream, a);
+  hipLaunchKernelGGL((k_tfine<T, DEC>), grid, dim3(TF_THR), 0, cx.stream, a);
   cx.check("k_tfine launch");
 }
 
