@@ -255,7 +255,8 @@ typedef struct mgr_service mgr_service;
 mgr_status mgr_service_create(size_t budget_bytes, int nstreams, mgr_service **svc);
 
 /* Submit one request (recompose != 0: recomposition).  Arguments as for
- * mgr_decompose minus the workspace and stream; coordinates are copied.
+ * mgr_decompose minus the workspace and stream (1..4 dims); coordinates are
+ * copied.
  * `in` must stay unchanged and `out` unused by the caller until the request
  * is done.  Returns at once with a ticket (1, 2, ...); the request waits if
  * it does not fit yet.  MGR_ERR_UNSUPPORTED for a request whose footprint

@@ -38,7 +38,7 @@ struct Request {
   uint64_t ticket = 0;
   bool recompose = false;
   int ndim = 0;
-  int64_t shape[3] = {0, 0, 0};
+  int64_t shape[4] = {0, 0, 0, 0};
   std::vector<std::vector<double>> coords;  // host copies (empty: uniform)
   mgr_dtype dtype = MGR_FLOAT64;
   int nlevels = 0;
@@ -221,7 +221,7 @@ mgr_status mgr_service_submit(mgr_service *svc, int recompose, int ndim, const i
                               const double *const *coords, mgr_dtype dtype, int nlevels, const void *in,
                               void *out, uint64_t *ticket) {
   if (!svc || !ticket) return sfail(MGR_ERR_INVALID_ARG, "svc and ticket must be non-NULL");
-  if (ndim < 1 || ndim > 3 || !shape) return sfail(MGR_ERR_INVALID_ARG, "ndim must be 1..3 with a shape");
+  if (ndim < 1 || ndim > 4 || !shape) return sfail(MGR_ERR_INVALID_ARG, "ndim must be 1..4 with a shape");
   size_t ws = 0;
   mgr_status s = mgr_workspace_size(ndim, shape, dtype, nlevels, &ws);
   if (s != MGR_OK) return sfail(s, mgr_last_error());

@@ -72,3 +72,47 @@ def test_service_rejects_oversized_requests():
     with pytest.raises(mgr.MgrError):
         svc.submit(False, x, y)
     svc.close()
+
+
+def test_service_reports_a_failing_request_and_serves_the_rest():
+    """A request that the library rejects when it is enqueued (in and out
+    overlap) is retired with its error status; the others complete."""
+    print("\n[case] service with one invalid request", flush=True)
+    u, coords = make_input((33, 33, 33), 5, nonuniform=True)
+    x = torch.from_numpy(u).cuda()
+    ref = mgr.decompose(x, coords)
+    torch.cuda.synchronize()
+    svc = mgr.Service(1 << 30, nstreams=2)
+    y0, y1 = torch.empty_like(x), torch.empty_like(x)
+    t0 = svc.submit(False, x, y0, coords)
+    tbad = svc.submit(False, x, x, coords)  # out overlaps in
+    t1 = svc.submit(False, x, y1, coords)
+    svc.wait_all()
+    d0, s0, _, _ = svc.result(t0)
+    dbad, sbad, _, _ = svc.result(tbad)
+    d1, s1, _, _ = svc.result(t1)
+    svc.close()
+    assert d0 and d1 and dbad
+    assert s0 == mgr.MGR_OK and s1 == mgr.MGR_OK
+    assert sbad == mgr.MGR_ERR_INVALID_ARG
+    torch.cuda.synchronize()
+    assert torch.equal(y0, ref) and torch.equal(y1, ref)
+
+
+def test_service_serves_4d_requests():
+    print("\n[case] service with 4-D requests", flush=True)
+    shapes = [(5, 17, 9, 12), (9, 9, 9, 9), (16, 5, 6, 7)]
+    svc = mgr.Service(1 << 30, nstreams=3)
+    jobs = []
+    for i, sh in enumerate(shapes):
+        u, coords = make_input(sh, 60 + i, nonuniform=True)
+        x = torch.from_numpy(u).cuda()
+        y = torch.empty_like(x)
+        jobs.append((x, y, coords, svc.submit(False, x, y, coords)))
+    svc.wait_all()
+    for x, y, coords, t in jobs:
+        done, st, _, _ = svc.result(t)
+        assert done and st == mgr.MGR_OK
+    svc.close()
+    for x, y, coords, _ in jobs:
+        assert torch.equal(y, mgr.decompose(x, coords))
