@@ -672,13 +672,14 @@ __global__ void __launch_bounds__(ROWS_THR) k_solve_rows(double *F, int64_t nrow
         for (int u = 0; u < 8; ++u)
           if (e + u * nt < n) ep.dst[gbase + e + u * nt] = (T)((double)d[u] - tile[e + u * nt]);
       }
-    } else {
+    } else if (ep.mode == EPI_STORE_NODAL) {
       for (int e = t; e < n; e += nt) {
-        const unsigned rr = (unsigned)e / (unsigned)c, cc = (unsigned)e - rr * (unsigned)c;
-        const unsigned row = (unsigned)row0 + rr;
-        const unsigned i = row / (unsigned)c1, j = row - i * (unsigned)c1;
+        const int rr = e / c, cc = e - rr * c;
+        const int64_t row = row0 + rr, i = row / c1, j = row - i * c1;
         epi_store(ep, F, gbase + e, i, j, cc, tile[e]);
       }
+    } else {
+      for (int e = t; e < n; e += nt) epi_store(ep, F, gbase + e, 0, 0, 0, tile[e]);
     }
   }
 }
@@ -699,8 +700,10 @@ __global__ void __launch_bounds__(64 * LONG_WAVES) k_solve_long(double *F, int64
   extern __shared__ double xs[];  // yF, yL, Fs, t: [P][64] each
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t k = (int64_t)blockIdx.x * 64 + lane;
-  const int64_t outer = blockIdx.y;
+  // blocks of 64 lines in (outer, k-block) order on a one-dimensional grid
+  const int64_t nkb = (nk + 63) / 64;
+  const int64_t k = ((int64_t)blockIdx.x % nkb) * 64 + lane;
+  const int64_t outer = (int64_t)blockIdx.x / nkb;
   const bool active = k < nk;
   const int64_t base = outer * so + (active ? k : 0) * sk;
   double *yF = xs, *yL = xs + P * 64, *Fs = xs + 2 * P * 64, *tt = xs + 3 * P * 64;
@@ -1696,7 +1699,7 @@ void launch_long(double *F, const Level &L, int axis, const Epi<T> &ep, Ctx &cx)
   if (axis == 0) { sp_ = c1 * c2; so = c2; sk = 1; nk = c2; nouter = c1; }
   else if (axis == 1) { sp_ = c2; so = c1 * c2; sk = 1; nk = c2; nouter = c0; }
   else { sp_ = 1; so = 0; sk = c2; nk = c0 * c1; nouter = 1; }
-  dim3 grid((unsigned)((nk + 63) / 64), (unsigned)nouter);
+  dim3 grid((unsigned)(((nk + 63) / 64) * nouter));
   const size_t lds = (size_t)4 * d.P * 64 * sizeof(double);
   // the interior solutions are written and re-read once more
   TimedLaunch tl(cx.stream, std::string("k_solve_long<") + tname<T>() + ">" + epi_tag(ep.mode),

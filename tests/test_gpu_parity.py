@@ -161,3 +161,54 @@ def test_parity_benchmark_workloads(name):
     """The benchmark's workloads at full size, in the launch configuration it times."""
     shape, seed, nonuni, dtype, nlev = WORKLOADS[name]
     _case(shape, nlev, nonuni, dtype, seed=seed)
+
+
+def _drop_level(n, nlev):
+    """Level at which each finest position of a dim of n nodes leaves the
+    hierarchy (nlev for positions on the coarsest grid)."""
+    from dense_l2 import coarse_positions
+    out = np.full(n, nlev)
+    pos = np.arange(n)
+    for s in range(nlev):
+        keep = pos[coarse_positions(len(pos))]
+        out[np.setdiff1d(pos, keep)] = s
+        pos = keep
+    return out
+
+
+def test_beyond_2pow31_elements_against_the_oracle():
+    """Maximum sizes: 1300^3 FP64 (2.2e9 nodes, offsets past 2^31), all 11
+    levels.  The field repeats a 2-D pattern g along dim 0, so by the tensor
+    structure its decomposition is the oracle's 2-D decomposition of g at
+    every node that leaves the hierarchy no earlier along dim 0 than in
+    (dims 1, 2), and zero elsewhere; sampled planes, including planes past the
+    2^31-element offset, are checked against that, and the round trip
+    everywhere."""
+    n = 1300
+    shape = (n, n, n)
+    nlev = mgr.max_levels(shape)
+    print(f"\n[case] {shape} float64 nlev={nlev}: u = 1 (x) g", flush=True)
+    g, cyz = make_input((n, n), 31, nonuniform=True)
+    cx = np.cumsum(np.random.default_rng(32).uniform(0.5, 1.5, n))
+    coords = [cx, cyz[0], cyz[1]]
+    ref2 = oracle.decompose(g, cyz, nlev)
+    gd = torch.from_numpy(g).cuda()
+    u = gd.unsqueeze(0).expand(n, n, n).contiguous()
+    d = mgr.decompose(u, coords, nlev)
+    torch.cuda.synchronize()
+    s_i = _drop_level(n, nlev)
+    s_jk = np.minimum.outer(_drop_level(n, nlev), _drop_level(n, nlev))
+    scale = np.max(np.abs(ref2))
+    planes = sorted({0, 1, 2, 3, 4, 8, 640, 1024, 1270, 1271, 1272, 1280, 1296, 1298, n - 1})
+    assert (n - 1) * n * n > 2 ** 31 and 1272 * n * n > 2 ** 31
+    for i in planes:
+        want = np.where(s_jk <= s_i[i], ref2, 0.0)
+        err = float(np.max(np.abs(d[i].cpu().numpy() - want))) / scale
+        assert err <= TOL64, (i, err)
+    r = mgr.recompose(d, coords, nlev)
+    torch.cuda.synchronize()
+    e_rt = float((r - u).abs().max() / u.abs().max())
+    print(f"[case] sampled planes ok, round trip {e_rt:.2e}", flush=True)
+    assert e_rt <= TOL64
+    del u, d, r
+    torch.cuda.empty_cache()
