@@ -276,7 +276,10 @@ mgr_status mgr_service_wait_all(mgr_service *svc);
 mgr_status mgr_service_result(mgr_service *svc, uint64_t ticket, int *done, mgr_status *status,
                               double *queue_ms, double *latency_ms);
 
-/* Wait for every request, stop the threads and free the arena and streams. */
+/* Wait for every request, stop the threads and free the arena and streams.
+ * (Each request's record -- status and times, about a hundred bytes of host
+ * memory -- is kept until then, so that mgr_service_result answers for every
+ * ticket.) */
 mgr_status mgr_service_destroy(mgr_service *svc);
 
 /* Detail of the calling thread's last service failure ("" if none). */

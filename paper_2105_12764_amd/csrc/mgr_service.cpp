@@ -10,6 +10,8 @@
 // per stream retires its requests in order, releases their budget and
 // workspace, and admits what waits.  Times are host steady-clock
 // milliseconds: submit, start (enqueued) and done (the waiter saw the event).
+// A request's coordinates are freed once it is enqueued; its record (about
+// a hundred bytes: status and times) stays until the service is destroyed.
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
@@ -130,6 +132,8 @@ struct mgr_service {
                        : mgr_decompose(r->ndim, r->shape, carg, r->dtype, r->nlevels, r->in, r->out, ws,
                                        r->ws_bytes, streams[best]);
       r->status = s;
+      // the library keeps its own tables: the request needs its coordinates no more
+      std::vector<std::vector<double>>().swap(r->coords);
       if (s == MGR_OK && hipEventRecord(r->ev, streams[best]) != hipSuccess) {
         (void)hipGetLastError();
         r->status = MGR_ERR_DEVICE;
