@@ -62,8 +62,12 @@ typedef enum { MGR_FLOAT32 = 0, MGR_FLOAT64 = 1 } mgr_dtype;
 int mgr_max_levels(int ndim, const int64_t *shape);
 
 /* Bytes of device workspace that mgr_decompose / mgr_recompose need for this
- * request (0 when nlevels == 0).  Host only, no GPU needed.  Returns
- * MGR_ERR_INVALID_ARG for a bad shape, dtype or level count. */
+ * request (0 when nlevels == 0): two grids of the level-1 shape in the field's
+ * type, one FP64 level-1 grid and, with two or more levels, one FP64 grid of
+ * the level-2 shape (4-D: two coarse 4-D grids in the field's type, the FP64
+ * coarse grid and an FP64 coarse space grid per time step).  Host only, no
+ * GPU needed.
+ * Returns MGR_ERR_INVALID_ARG for a bad shape, dtype or level count. */
 mgr_status mgr_workspace_size(int ndim, const int64_t *shape, mgr_dtype dtype,
                               int nlevels, size_t *bytes);
 
@@ -102,7 +106,13 @@ mgr_status mgr_decompose(int ndim, const int64_t *shape,
 /* Recompose the field from its nodal multilevel representation: the inverse
  * of mgr_decompose with the same shape, coords and nlevels.  Arguments,
  * ownership and errors as for mgr_decompose (here `in` is the
- * representation and `out` the field). */
+ * representation and `out` the field).  With two or more levels, the finest
+ * level's load vector and first solves (which read only `in`) run on a
+ * library-owned stream forked from `stream` after the work already on it and
+ * joined back before the finest level's last kernels, so the call stays
+ * ordered on `stream` and capturable in a HIP graph; the helper stream of a
+ * (device, stream) pair is created by its first call, so make one call
+ * before capturing. */
 mgr_status mgr_recompose(int ndim, const int64_t *shape,
                          const double *const *coords, mgr_dtype dtype,
                          int nlevels, const void *in, void *out,

@@ -201,6 +201,53 @@ mgr_status get_plan(const int64_t n[mgr::kDims], int ndim, int nlevels,
   return MGR_OK;
 }
 
+// A helper stream per (device, caller stream) for the work a recomposition
+// runs beside the caller's stream, with its fork and join events; created on
+// first use and kept until the process ends (a stream may still hold work).
+// `mu` keeps one forked enqueue at a time per caller stream, so that the
+// shared events pair up.
+struct Helper {
+  int device = -1;
+  hipStream_t caller = nullptr;
+  hipStream_t s = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+  std::mutex mu;
+};
+std::mutex g_hmu;
+std::list<Helper> g_helpers;  // stable addresses
+
+// The helper of `caller` on the current device, or nullptr (then the call
+// runs serially) when it cannot be created.
+Helper *helper_for(hipStream_t caller) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(g_hmu);
+  for (auto &h : g_helpers)
+    if (h.device == dev && h.caller == caller) return &h;
+  hipStream_t s = nullptr;
+  hipEvent_t f = nullptr, j = nullptr;
+  bool ok = hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess;
+  ok = ok && hipEventCreateWithFlags(&f, hipEventDisableTiming) == hipSuccess;
+  ok = ok && hipEventCreateWithFlags(&j, hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    if (j) (void)hipEventDestroy(j);
+    if (f) (void)hipEventDestroy(f);
+    if (s) (void)hipStreamDestroy(s);
+    return nullptr;
+  }
+  Helper &h = g_helpers.emplace_back();
+  h.device = dev;
+  h.caller = caller;
+  h.s = s;
+  h.fork = f;
+  h.join = j;
+  return &h;
+}
+
 mgr_status run(bool dec, int ndim, const int64_t *shape, const double *const *coords, int dtype,
                int nlevels, const void *in, void *out, void *ws, size_t ws_bytes, void *stream,
                int nkeep = -1) {
@@ -219,8 +266,16 @@ mgr_status run(bool dec, int ndim, const int64_t *shape, const double *const *co
     if (s != MGR_OK) return s;
     std::string err;
     const bool f64 = dtype == MGR_FLOAT64;
-    const bool ok = dec ? mgr::enqueue_decompose(*plan, f64, in, out, ws, stream, err)
-                        : mgr::enqueue_recompose(*plan, f64, in, out, ws, stream, err, nkeep);
+    bool ok = false;
+    if (dec) {
+      ok = mgr::enqueue_decompose(*plan, f64, in, out, ws, stream, err);
+    } else if (Helper *h = (plan->nlev >= 2 && !plan->time) ? helper_for((hipStream_t)stream) : nullptr) {
+      std::lock_guard<std::mutex> lk(h->mu);
+      const mgr::StreamFork fk{h->s, h->fork, h->join};
+      ok = mgr::enqueue_recompose(*plan, f64, in, out, ws, stream, err, nkeep, &fk);
+    } else {
+      ok = mgr::enqueue_recompose(*plan, f64, in, out, ws, stream, err, nkeep);
+    }
     if (!ok) return fail(MGR_ERR_DEVICE, err);
     return MGR_OK;
   } catch (const std::bad_alloc &) {

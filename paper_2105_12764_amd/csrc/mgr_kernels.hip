@@ -1737,14 +1737,21 @@ void launch_solve(double *F, const Level &L, int axis, const Epi<T> &ep, Ctx &cx
   cx.check("correction solve launch");
 }
 
-// Solves along every coarsened dim in order 0, 1, 2; the last one applies `last`.
-template <typename T>
-void solve_all(double *F, const Level &L, const Epi<T> &last, Ctx &cx) {
+// The last coarsened dim of a level (-1: none).
+int last_dim(const Level &L) {
   int lastk = -1;
   for (int k = 0; k < kDims; ++k)
     if (L.co[k]) lastk = k;
+  return lastk;
+}
+
+// Solves along the coarsened dims in order 0, 1, 2; the last one applies
+// `last`.  `part`: 0 all of them, 1 all but the last, 2 only the last.
+template <typename T>
+void solve_all(double *F, const Level &L, const Epi<T> &last, Ctx &cx, int part = 0) {
+  const int lastk = last_dim(L);
   for (int k = 0; k < kDims; ++k) {
-    if (!L.co[k]) continue;
+    if (!L.co[k] || (part == 1 && k == lastk) || (part == 2 && k != lastk)) continue;
     Epi<T> ep = (k == lastk) ? last : Epi<T>{EPI_Z, nullptr, Map3{}};
     launch_solve<T>(F, L, k, ep, cx);
   }
@@ -1856,13 +1863,14 @@ void launch_tail(const Plan &pl, const T *src, T *dst, Ctx &cx, int t_drop = 0) 
 struct Workspace {
   void *buf[2];
   double *F;
+  double *F2;  // coarser levels' load vector while level 0's runs beside them (nlev >= 2)
 };
 
 Workspace carve(const Plan &pl, void *ws, size_t elem) {
   auto al = [](size_t b) { return (b + 255) / 256 * 256; };
-  const size_t nb = al((size_t)pl.max_coarse * elem);
+  const size_t nb = al((size_t)pl.max_coarse * elem), nf = al((size_t)pl.max_coarse * sizeof(double));
   char *p = (char *)ws;
-  return Workspace{{p, p + nb}, (double *)(p + 2 * nb)};
+  return Workspace{{p, p + nb}, (double *)(p + 2 * nb), pl.nlev >= 2 ? (double *)(p + 2 * nb + nf) : nullptr};
 }
 
 template <typename T>
@@ -1913,9 +1921,16 @@ bool decompose_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t stre
 // nkeep: coefficient classes used, coarsest first (nlev: all of them); the
 // finer levels' coefficients are taken as zero, so those levels need no load
 // vector and no solve (z = 0) and only interpolate.
+//
+// With a fork, level 0's load vector and its solves but the last -- which
+// read only the stored coefficients -- run on the helper stream while the
+// coarser levels recompose on `stream` (their load vectors in a second FP64
+// grid); the stream then waits for them, and level 0's last solve subtracts
+// z from the level-1 grid as before.  Every kernel and its arithmetic are
+// those of the serial order.
 template <typename T>
 bool recompose_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t stream, std::string &err,
-                 int nkeep) {
+                 int nkeep, const StreamFork *fk = nullptr) {
   Ctx cx{stream, &err};
   const int64_t total = pl.n[0] * pl.n[1] * pl.n[2];
   if (pl.nlev == 0) {
@@ -1928,6 +1943,34 @@ bool recompose_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t stre
   Workspace w = carve(pl, ws, sizeof(T));
   const int st = std::min(pl.tail_start, pl.nlev);
   const int drop = pl.nlev - std::max(0, std::min(nkeep, pl.nlev));  // levels below take zero coefficients
+  const std::vector<LevelTune> tune0 = pl.tune_snapshot();
+  const bool split = fk != nullptr && w.F2 != nullptr && st >= 1 && drop == 0;
+  double *Fc = split ? w.F2 : w.F;  // load vector of the levels on `stream`
+  if (split) {
+    hipStream_t hs = (hipStream_t)fk->helper;
+    if (hipEventRecord((hipEvent_t)fk->fork, stream) != hipSuccess ||
+        hipStreamWaitEvent(hs, (hipEvent_t)fk->fork, 0) != hipSuccess) {
+      (void)hipGetLastError();
+      err = "forking the helper stream failed";
+      return false;
+    }
+    Ctx hx{hs, &err};
+    const Level &L = pl.lev[0];
+    LoadArgs<T> a{};
+    a.src = in;
+    a.smap = compact_map(pl.n[1], pl.n[2]);
+    a.F = w.F;
+    hx.ti_req = tune0.empty() ? 0 : tune0[0].lv_ti[1];
+    launch_loadvec<T, false>(L, a, hx);
+    hx.ti_req = 0;
+    if (hx.ok) solve_all<T>(w.F, L, Epi<T>{EPI_Z, nullptr, Map3{}}, hx, 1);
+    if (hipEventRecord((hipEvent_t)fk->join, hs) != hipSuccess) {
+      (void)hipGetLastError();
+      if (hx.ok) err = "joining the helper stream failed";
+      hx.ok = false;
+    }
+    if (!hx.ok) return false;
+  }
   T *V = nullptr;
   if (st < pl.nlev) {
     // the coarsest levels in one workgroup, up to the level grid of level st
@@ -1943,7 +1986,7 @@ bool recompose_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t stre
                        nodal_map(Lc), V, Lc.m[0], Lc.m[1], Lc.m[2]);
     cx.check("k_gather launch");
   }
-  const std::vector<LevelTune> tune = pl.tune_snapshot();
+  const std::vector<LevelTune> &tune = tune0;
   for (int s = st - 1; s >= 0 && cx.ok; --s) {
     const Level &L = pl.lev[s];
     const LevelTune lt = s < (int)tune.size() ? tune[s] : LevelTune{};
@@ -1956,17 +1999,27 @@ bool recompose_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t stre
       V = dst;
       continue;
     }
-    LoadArgs<T> a{};
-    a.src = in;
-    a.smap = cmap;
-    a.F = w.F;
-    cx.ti_req = lt.lv_ti[1];
-    launch_loadvec<T, false>(L, a, cx);
-    cx.ti_req = 0;
     Epi<T> ep{};
     ep.mode = EPI_SUB_COMPACT;
     ep.dst = V;
-    solve_all<T>(w.F, L, ep, cx);
+    if (split && s == 0) {
+      // level 0's load vector and first solves ran on the helper stream
+      if (hipStreamWaitEvent(stream, (hipEvent_t)fk->join, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        err = "waiting for the helper stream failed";
+        return false;
+      }
+      solve_all<T>(w.F, L, ep, cx, 2);
+    } else {
+      LoadArgs<T> a{};
+      a.src = in;
+      a.smap = cmap;
+      a.F = Fc;
+      cx.ti_req = lt.lv_ti[1];
+      launch_loadvec<T, false>(L, a, cx);
+      cx.ti_req = 0;
+      solve_all<T>(Fc, L, ep, cx);
+    }
     cx.ti_req = lt.rc_ti;
     launch_reconstruct<T>(L, in, cmap, V, dst, cx, lt.rc_tj, lt.rc_tk);
     cx.ti_req = 0;
@@ -2433,14 +2486,14 @@ bool enqueue_decompose(const Plan &pl, bool f64, const void *in, void *out, void
 }
 
 bool enqueue_recompose(const Plan &pl, bool f64, const void *in, void *out, void *ws, void *stream,
-                       std::string &err, int nkeep) {
+                       std::string &err, int nkeep, const StreamFork *fk) {
   hipStream_t st = (hipStream_t)stream;
   if (pl.time)
     return f64 ? recompose4_t<double>(pl, (const double *)in, (double *)out, ws, st, err)
                : recompose4_t<float>(pl, (const float *)in, (float *)out, ws, st, err);
   if (nkeep < 0) nkeep = pl.nlev;
-  return f64 ? recompose_t<double>(pl, (const double *)in, (double *)out, ws, st, err, nkeep)
-             : recompose_t<float>(pl, (const float *)in, (float *)out, ws, st, err, nkeep);
+  return f64 ? recompose_t<double>(pl, (const double *)in, (double *)out, ws, st, err, nkeep, fk)
+             : recompose_t<float>(pl, (const float *)in, (float *)out, ws, st, err, nkeep, fk);
 }
 
 }  // namespace mgr

@@ -13,9 +13,20 @@ namespace mgr {
 bool enqueue_decompose(const Plan &pl, bool f64, const void *in, void *out, void *ws, void *stream,
                        std::string &err);
 bool enqueue_copy_probe(const void *src, void *dst, size_t bytes, void *stream, std::string &err);
-// nkeep: coefficient classes used, coarsest first (< 0: all).
+// A helper stream and two events for work that a call may run beside its
+// own stream (forked after everything already on the stream, joined back
+// before the work that needs it).
+struct StreamFork {
+  void *helper;  // hipStream_t
+  void *fork;    // hipEvent_t
+  void *join;    // hipEvent_t
+};
+
+// nkeep: coefficient classes used, coarsest first (< 0: all).  With `fk`, the
+// finest level's load vector and all but its last solve run on the helper
+// stream while the coarser levels recompose (same arithmetic, same results).
 bool enqueue_recompose(const Plan &pl, bool f64, const void *in, void *out, void *ws, void *stream,
-                       std::string &err, int nkeep = -1);
+                       std::string &err, int nkeep = -1, const StreamFork *fk = nullptr);
 
 // Reorder a nodal representation into class-contiguous order (export) or
 // back (import); src and dst hold prod(shape) elements each.

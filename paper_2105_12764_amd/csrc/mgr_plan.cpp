@@ -75,11 +75,19 @@ size_t workspace_bytes4(int64_t nt, const int64_t n[kDims], int nlev, size_t ele
 
 size_t workspace_bytes(const int64_t n[kDims], int nlev, size_t elem_size) {
   if (nlev <= 0) return 0;
-  int64_t c1 = 1;
-  for (int k = 0; k < kDims; ++k) c1 *= coarse_count(n[k]);
+  int64_t c1 = 1, c2 = 1;
+  for (int k = 0; k < kDims; ++k) {
+    c1 *= coarse_count(n[k]);
+    c2 *= coarse_count(coarse_count(n[k]));
+  }
   auto al = [](size_t b) { return (b + 255) / 256 * 256; };
-  // two coarse grids in the field's type (ping-pong) + one FP64 load/correction grid
-  return 2 * al((size_t)c1 * elem_size) + al((size_t)c1 * sizeof(double));
+  // two coarse grids in the field's type (ping-pong) + one FP64 load/correction
+  // grid, and with two or more levels one more FP64 grid of the next level's
+  // size for the coarser levels while the finest level's recompose load vector
+  // and solves run beside them
+  size_t b = 2 * al((size_t)c1 * elem_size) + al((size_t)c1 * sizeof(double));
+  if (nlev >= 2) b += al((size_t)c2 * sizeof(double));
+  return b;
 }
 
 namespace {
