@@ -44,21 +44,34 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_2105_12764_amd", "csrc", "mgr_kernels.
 PROFILES = os.path.join(ROOT, "profiles")
 
 
+def code_sha256(path: str) -> str:
+    """sha256 of a C++/HIP source with its // comments, trailing blanks and
+    blank lines removed: it changes when the code changes, not its comments."""
+    import hashlib
+    import re
+
+    lines = []
+    for line in open(path, encoding="utf-8"):
+        line = re.sub(r"//.*$", "", line.rstrip("\n")).rstrip()
+        if line.strip():
+            lines.append(line)
+    return hashlib.sha256("\n".join(lines).encode()).hexdigest()
+
+
 def measured_traffic(kernel: str):
     """HBM bytes per launch of `kernel` from a committed rocprofv3 PMC summary
     (profiles/*.md, a line '<!-- traffic: {json} -->'), or None when there is
-    none or the kernel source changed since the counters were taken."""
+    none or the kernel code changed since the counters were taken."""
     import glob
-    import hashlib
     import json as _json
 
-    sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    sha = code_sha256(KERNEL_SOURCE)
     for path in sorted(glob.glob(os.path.join(PROFILES, "*.md"))):
         for line in open(path):
             line = line.strip()
             if line.startswith("<!-- traffic:") and line.endswith("-->"):
                 rec = _json.loads(line[len("<!-- traffic:"):-3])
-                if rec.get("kernel") == kernel and rec.get("source_sha256") == sha:
+                if rec.get("kernel") == kernel and rec.get("code_sha256") == sha:
                     return rec["bytes_per_launch"]
     return None
 METRIC = "decompose+recompose GB/s at 513^3 FP64/FP32 (% HBM peak); batched p50/p99 ms"
@@ -424,7 +437,7 @@ def run_service(nreq: int = 300, rates=(50, 100, 200, 500, 1000, 2000), budget_g
 
 
 def run_spatiotemporal(side: int = 400, steps=(1, 2, 4, 8, 16), reps: int = 3):
-    """4-D refactoring (time as a fourth dimension, Sec. III-F, V-F): T time
+    """4-D refactoring (time as a fourth dimension, Sec. III-D, IV-F): T time
     steps of a side^3 FP64 field (512 MB per step at side 400) refactored
     together as one (T, side, side, side) field, all levels; T = 1 is the
     3-D path on one step.  GB/s = 2 x bytes / (t_dec + t_rec), best of reps;

@@ -74,7 +74,7 @@ mgr_status mgr_workspace_size(int ndim, const int64_t *shape, mgr_dtype dtype,
 /* Decompose `in` into its nodal multilevel representation `out`.
  *   ndim, shape : 1..4 dimensions, each >= 2 nodes, C order.  A 4-D shape
  *                 is (time, then three space dims): the decomposition in
- *                 four tensor-product dims of Sec. III-F, time coarsening
+ *                 four tensor-product dims of Sec. III-D, time coarsening
  *                 like space; the product of the three space dims must be
  *                 below 2^31.  4-D fields are taken by mgr_decompose,
  *                 mgr_recompose, mgr_workspace_size and mgr_max_levels;
@@ -252,7 +252,7 @@ mgr_status mgr_recompose_batch(int nfields, const mgr_field *fields, void *works
  * Workspace comes from an arena allocated at creation (half the budget plus
  * 1 MiB, at most the budget), so requests allocate nothing.  The operations
  * are those of mgr_decompose / mgr_recompose; the service is the stream of
- * many independent fields refactored inside a workflow (Sec. III-F, IV)
+ * many independent fields refactored inside workflows (Sec. V)
  * with admission by memory footprint.  Admitted requests run on
  * `nstreams` internal streams (default priority), least-loaded first; one
  * host thread per stream retires them in order.  All calls on one service

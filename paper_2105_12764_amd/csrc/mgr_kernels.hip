@@ -1009,7 +1009,7 @@ __global__ void __launch_bounds__(256) k_gather(const T *src, Map3 smap, T *dst,
 // ------------------------------------------------------------ 4-D levels
 //
 // A 4-D field is refactored as one more tensor-product dimension (Sec.
-// III-F): dim 0 (time) coarsens with the same nesting rule, interpolation is
+// III-D): dim 0 (time) coarsens with the same nesting rule, interpolation is
 // multilinear in all four dims, and the load vector and the correction solves
 // act along time as along space.  Space is processed per time slice by the
 // 3-D kernels (time over launches), time by the kernels below with the three

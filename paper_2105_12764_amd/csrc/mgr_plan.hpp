@@ -100,7 +100,7 @@ struct Plan {
     std::lock_guard<std::mutex> lk(tune_mu);
     return tune;
   }
-  // Four-dimensional fields (Sec. III-F: time as one more tensor-product
+  // Four-dimensional fields (Sec. III-D: time as one more tensor-product
   // dimension).  Dim 0 of the caller's shape is taken as time: this plan then
   // covers the three remaining dims (one time slice; no tail levels) and
   // `time` covers dim 0 as a (1, 1, nt) plan.  tpos[s][t] is the finest time

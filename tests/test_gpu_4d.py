@@ -1,4 +1,4 @@
-"""GPU: 4-D fields (time as a fourth tensor-product dimension, Sec. III-F).
+"""GPU: 4-D fields (time as a fourth tensor-product dimension, Sec. III-D).
 
 The decomposition must match the oracle's 4-D decomposition to 1e-12 relative
 (FP64) or 1e-5 relative L2 (FP32); the recomposition must rebuild the field
