@@ -186,6 +186,22 @@ def _coords_arg(shape, coords):
     return arr, keep
 
 
+def _check_pair(x, out):
+    """The library takes raw pointers: make sure `out` can hold what it writes."""
+    if not (x.is_cuda and x.is_contiguous()):
+        raise ValueError("input must be a contiguous (C order) HIP device tensor")
+    if not (out.is_cuda and out.is_contiguous()):
+        raise ValueError("out must be a contiguous (C order) HIP device tensor")
+    if out.shape != x.shape or out.dtype != x.dtype or out.device != x.device:
+        raise ValueError("out must match the input in shape, dtype and device")
+
+
+def _workspace_bytes(ws, device) -> int:
+    if not (ws.is_cuda and ws.is_contiguous() and ws.device == device):
+        raise ValueError("workspace must be a contiguous HIP tensor on the input's device")
+    return ws.numel() * ws.element_size()
+
+
 def alloc_workspace(shape, dtype, nlevels, device=None):
     import torch
     nb = workspace_size(shape, dtype, nlevels)
@@ -194,24 +210,24 @@ def alloc_workspace(shape, dtype, nlevels, device=None):
 
 def _call(fn, x, coords, nlevels, out, workspace, stream):
     import torch
-    if not x.is_cuda:
-        raise ValueError("input must be a HIP device tensor")
-    if not x.is_contiguous():
-        raise ValueError("input must be contiguous (C order)")
+    if not (x.is_cuda and x.is_contiguous()):
+        raise ValueError("input must be a contiguous (C order) HIP device tensor")
     shape = tuple(x.shape)
     if nlevels is None:
         nlevels = max_levels(shape)
     if out is None:
         out = torch.empty_like(x)
+    _check_pair(x, out)
     if workspace is None:
         workspace = alloc_workspace(shape, x.dtype, nlevels, device=x.device)
+    wsb = _workspace_bytes(workspace, x.device)
     if stream is None:
         stream = torch.cuda.current_stream(x.device)
     carr, keep = _coords_arg(shape, coords)
     with torch.cuda.device(x.device):
         s = fn(len(shape), _shape(shape), carr, _dtype_code(x.dtype), int(nlevels),
                ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
-               ctypes.c_void_p(workspace.data_ptr()), ctypes.c_size_t(workspace.numel()),
+               ctypes.c_void_p(workspace.data_ptr()), ctypes.c_size_t(wsb),
                ctypes.c_void_p(stream.cuda_stream))
     del keep
     if s != MGR_OK:
@@ -245,8 +261,8 @@ class Batch:
         for i, (x, y, coords, nlevels) in enumerate(items):
             if not (x.is_cuda and y.is_cuda and x.is_contiguous() and y.is_contiguous()):
                 raise ValueError(f"field {i}: in and out must be contiguous HIP tensors")
-            if x.shape != y.shape or x.dtype != y.dtype:
-                raise ValueError(f"field {i}: in and out must match in shape and dtype")
+            if x.shape != y.shape or x.dtype != y.dtype or x.device != y.device:
+                raise ValueError(f"field {i}: in and out must match in shape, dtype and device")
             shape = tuple(x.shape)
             f = self.fields[i]
             f.ndim = len(shape)
@@ -293,11 +309,12 @@ def _call_batch(fn, batch: Batch, workspace, stream):
     dev = batch.tensors[0][0].device
     if workspace is None:
         workspace = batch.alloc_workspace(dev)
+    wsb = _workspace_bytes(workspace, dev)
     if stream is None:
         stream = torch.cuda.current_stream(dev)
     with torch.cuda.device(dev):
         s = fn(len(batch.fields), batch.fields, ctypes.c_void_p(workspace.data_ptr()),
-               ctypes.c_size_t(workspace.numel()), ctypes.c_void_p(stream.cuda_stream))
+               ctypes.c_size_t(wsb), ctypes.c_void_p(stream.cuda_stream))
     if s != MGR_OK:
         raise MgrError(s, last_error())
 
@@ -335,6 +352,7 @@ def _classes(fn, x, nlevels, out, stream):
         nlevels = max_levels(shape)
     if out is None:
         out = torch.empty_like(x)
+    _check_pair(x, out)
     if stream is None:
         stream = torch.cuda.current_stream(x.device)
     with torch.cuda.device(x.device):
@@ -386,6 +404,9 @@ class Service:
         self._keep = {}
 
     def submit(self, recompose: bool, x, out, coords=None, nlevels: Optional[int] = None) -> int:
+        """Queue one request; ``x`` and ``out`` must stay alive and untouched
+        until it is done (:meth:`result` or :meth:`wait_all`)."""
+        _check_pair(x, out)
         shape = tuple(x.shape)
         if nlevels is None:
             nlevels = max_levels(shape)

@@ -219,3 +219,16 @@ def test_service_rejects_bad_arguments_without_a_device():
                                 ctypes.c_void_p(1), ctypes.c_void_p(2), ctypes.byref(t)) == E
     assert L.mgr_service_wait_all(None) == E
     assert L.mgr_service_destroy(None) == mgr.MGR_OK
+
+
+def test_binding_rejects_mismatched_outputs_before_the_library():
+    """The C ABI takes raw pointers, so the binding checks that `out` can hold
+    what the library writes (no device needed: CPU tensors are rejected
+    first, and a mismatched `out` is rejected before any pointer is passed)."""
+    import torch
+
+    x = torch.zeros((5, 5, 5), dtype=torch.float64)
+    with pytest.raises(ValueError):
+        mgr.decompose(x)
+    with pytest.raises(ValueError):
+        mgr._check_pair(x, torch.zeros((5, 5, 5), dtype=torch.float64))

@@ -212,3 +212,23 @@ def test_beyond_2pow31_elements_against_the_oracle():
     assert e_rt <= TOL64
     del u, d, r
     torch.cuda.empty_cache()
+
+
+def test_binding_checks_out_and_workspace():
+    """The C ABI takes raw pointers: the binding refuses an `out` that cannot
+    hold the result and counts the workspace in bytes whatever its dtype."""
+    print("\n[case] binding checks of out and workspace", flush=True)
+    u, coords = make_input((33, 20, 17), 3, nonuniform=True)
+    x = torch.from_numpy(u).cuda()
+    for bad in (torch.empty((33, 20, 17), dtype=torch.float32, device="cuda"),
+                torch.empty((33, 20, 16), dtype=torch.float64, device="cuda"),
+                torch.empty((33, 20, 17), dtype=torch.float64)):
+        with pytest.raises(ValueError):
+            mgr.decompose(x, coords, out=bad)
+    nlev = mgr.max_levels(tuple(x.shape))
+    nb = mgr.workspace_size(tuple(x.shape), x.dtype, nlev)
+    ws64 = torch.empty((nb + 7) // 8, dtype=torch.float64, device="cuda")  # the same bytes as uint8
+    d = mgr.decompose(x, coords, nlev, workspace=ws64)
+    ref = mgr.decompose(x, coords, nlev)
+    torch.cuda.synchronize()
+    assert torch.equal(d, ref)
