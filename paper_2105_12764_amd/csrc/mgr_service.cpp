@@ -18,7 +18,6 @@
 #include <chrono>
 #include <condition_variable>
 #include <deque>
-#include <map>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -26,6 +25,7 @@
 #include <vector>
 
 #include "../../include/mgr.h"
+#include "mgr_arena.hpp"
 
 namespace {
 
@@ -61,7 +61,7 @@ struct mgr_service {
   size_t budget = 0, in_flight = 0;
   char *arena = nullptr;
   size_t arena_bytes = 0;
-  std::map<size_t, size_t> free_blocks;  // offset -> bytes
+  mgr::ArenaFit fit;  // workspace ranges of the arena
   std::mutex mu;
   std::condition_variable cv;
   std::deque<Request *> pending;
@@ -71,41 +71,6 @@ struct mgr_service {
   std::vector<std::unique_ptr<Request>> all;  // index = ticket - 1
   bool stop = false;
 
-  // first fit in the arena, 256-byte granules
-  bool alloc(size_t bytes, size_t &off) {
-    bytes = (bytes + 255) / 256 * 256;
-    if (bytes == 0) {
-      off = 0;
-      return true;
-    }
-    for (auto it = free_blocks.begin(); it != free_blocks.end(); ++it) {
-      if (it->second < bytes) continue;
-      off = it->first;
-      const size_t rest = it->second - bytes;
-      free_blocks.erase(it);
-      if (rest) free_blocks[off + bytes] = rest;
-      return true;
-    }
-    return false;
-  }
-  void release(size_t off, size_t bytes) {
-    bytes = (bytes + 255) / 256 * 256;
-    if (bytes == 0) return;
-    auto it = free_blocks.emplace(off, bytes).first;
-    auto next = std::next(it);
-    if (next != free_blocks.end() && it->first + it->second == next->first) {
-      it->second += next->second;
-      free_blocks.erase(next);
-    }
-    if (it != free_blocks.begin()) {
-      auto prev = std::prev(it);
-      if (prev->first + prev->second == it->first) {
-        prev->second += it->second;
-        free_blocks.erase(it);
-      }
-    }
-  }
-
   // Enqueue waiting requests in order while budget and workspace allow
   // (caller holds mu).
   void admit() {
@@ -113,7 +78,7 @@ struct mgr_service {
       Request *r = pending.front();
       if (in_flight + r->footprint > budget) return;
       size_t off = 0;
-      if (!alloc(r->ws_bytes, off)) return;
+      if (!fit.alloc(r->ws_bytes, off)) return;
       pending.pop_front();
       r->ws_off = off;
       in_flight += r->footprint;
@@ -160,7 +125,7 @@ struct mgr_service {
       r->t_done = t;
       r->done = true;
       in_flight -= r->footprint;
-      release(r->ws_off, r->ws_bytes);
+      fit.release(r->ws_off, r->ws_bytes);
       (void)hipEventDestroy(r->ev);
       r->ev = nullptr;
       admit();
@@ -197,12 +162,12 @@ mgr_status mgr_service_create(size_t budget_bytes, int nstreams, mgr_service **s
     // rounding, so half the budget plus 1 MiB holds any admissible request;
     // a larger in-flight set that does not fit waits for a release.
     s->arena_bytes = std::min(budget_bytes, budget_bytes / 2 + ((size_t)1 << 20));
-    s->arena_bytes = (s->arena_bytes + 255) / 256 * 256;
+    s->arena_bytes = mgr::ArenaFit::round_up(s->arena_bytes);
     if (hipMalloc((void **)&s->arena, s->arena_bytes) != hipSuccess) {
       (void)hipGetLastError();
       return sfail(MGR_ERR_OUT_OF_MEMORY, "workspace arena allocation failed");
     }
-    s->free_blocks[0] = s->arena_bytes;
+    s->fit.reset(s->arena_bytes);
     s->running.resize(nstreams);
     s->streams.assign(nstreams, nullptr);
     for (int k = 0; k < nstreams; ++k)
@@ -256,7 +221,7 @@ mgr_status mgr_service_submit(mgr_service *svc, int recompose, int ndim, const i
     r->ws_bytes = ws;
     r->footprint = 2 * n * (dtype == MGR_FLOAT64 ? 8 : 4) + ws;
     if (r->footprint > svc->budget) return sfail(MGR_ERR_UNSUPPORTED, "request larger than the service budget");
-    if ((ws + 255) / 256 * 256 > svc->arena_bytes)
+    if (mgr::ArenaFit::round_up(ws) > svc->arena_bytes)
       return sfail(MGR_ERR_UNSUPPORTED, "request workspace larger than the service arena");
     if (hipEventCreateWithFlags(&r->ev, hipEventDisableTiming) != hipSuccess) {
       (void)hipGetLastError();
