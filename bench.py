@@ -12,7 +12,10 @@ Prints one JSON line:
                the timed region, against the 8 TB/s HBM peak;
   cpu_baseline the FP64 CPU oracle on the same workload (one step), GB/s in
                the same unit, with the number of threads it used.
-Extra keys: the algorithmic-byte rate of the whole step, per-kernel totals,
+Extra keys: the algorithmic-byte rate of the whole step, `hbm_measured` (the
+rocprofv3 HBM bytes of every kernel of one step, from the committed PMC
+summary of the same kernel code, over the step time, and their ratio to the
+algorithmic bytes), per-kernel totals,
 the FP32 mode on the same grid, the round-trip error of the timed data,
 `progressive`: the time and relative L2 error of recomposing from the k
 coarsest coefficient classes, k = 0..nlevels, and
@@ -58,10 +61,11 @@ def code_sha256(path: str) -> str:
     return hashlib.sha256("\n".join(lines).encode()).hexdigest()
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from a committed rocprofv3 PMC summary
-    (profiles/*.md, a line '<!-- traffic: {json} -->'), or None when there is
-    none or the kernel code changed since the counters were taken."""
+def traffic_record(kernel: str):
+    """The committed rocprofv3 PMC record (profiles/*.md, a line
+    '<!-- traffic: {json} -->') whose dominant kernel is `kernel`: HBM bytes
+    per launch of that kernel and of the whole profiled step.  None when
+    there is none or the kernel code changed since the counters were taken."""
     import glob
     import json as _json
 
@@ -72,7 +76,7 @@ def measured_traffic(kernel: str):
             if line.startswith("<!-- traffic:") and line.endswith("-->"):
                 rec = _json.loads(line[len("<!-- traffic:"):-3])
                 if rec.get("kernel") == kernel and rec.get("code_sha256") == sha:
-                    return rec["bytes_per_launch"]
+                    return rec
     return None
 METRIC = "decompose+recompose GB/s at 513^3 FP64/FP32 (% HBM peak); batched p50/p99 ms"
 
@@ -206,16 +210,28 @@ def run_gpu(name: str, steps: int, warmup: int, graph_steps: int = 0, tune: bool
                for k, v in sorted(totals.items(), key=lambda kv: -kv[1][1])}
     dom_name, (dom_n, dom_ms, dom_b) = max(totals.items(), key=lambda kv: kv[1][1])
     achieved = dom_b / (dom_ms * 1e-3) / 1e9
+    rec = traffic_record(dom_name)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom_name),
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": rec["bytes_per_launch"] if rec else None,
                 "kernel": dom_name,
                 "alg_bytes_per_launch": dom_b / dom_n, "mean_launch_us": dom_ms * 1e3 / dom_n}
+    # measured HBM bytes of the whole step (rocprofv3 FETCH_SIZE + WRITE_SIZE over
+    # every dispatch of one decompose + recompose) over the step's event time
+    hbm_measured = None
+    if rec and rec.get("step_bytes"):
+        sb = float(rec["step_bytes"])
+        gbps = sb / ((t_dec + t_rec) * 1e-3) / 1e9
+        hbm_measured = {"bytes_per_step": int(sb), "GBps": round(gbps, 1),
+                        "pct_hbm_peak": round(100.0 * gbps / HBM_PEAK_GBS, 2),
+                        "amplification_over_alg": round(sb / alg_bytes_step, 3)}
     res = {
         "workload": name, "shape": list(shape), "dtype": np.dtype(dtype).name, "nlevels": nlev,
         "t_dec_ms": t_dec, "t_rec_ms": t_rec, "ms_per_step": ms_step, "value": value,
         "alg_GB_per_step": alg_bytes_step / 1e9,
         "alg_GBps": alg_bytes_step / ((t_dec + t_rec) * 1e-3) / 1e9,
         "roundtrip_max_rel_err": rt_err, "kernels": kernels, "roofline": roofline,
+        "hbm_measured": hbm_measured,
         "graph": graph,
         "progressive": progressive,
         "autotune": None if not tune else {
@@ -611,6 +627,7 @@ def main():
         "pct_of_copy_probe": round(100.0 * res["alg_GBps"] / probe["GBps"], 2),
         "roundtrip_max_rel_err": res["roundtrip_max_rel_err"],
         "roofline": res["roofline"],
+        "hbm_measured": res["hbm_measured"],
         "cpu_baseline": cpu,
         "kernels": res["kernels"],
         "fp32": fp32,
