@@ -60,10 +60,10 @@ __device__ __forceinline__ int64_t moff(const Map3 &m, int64_t i, int64_t j, int
 __device__ __forceinline__ double lerp(double a, double b, double r) { return fma(r, b, fma(-r, a, a)); }
 __device__ __forceinline__ float lerp(float a, float b, float r) { return fmaf(r, b, fmaf(-r, a, a)); }
 
-// Arithmetic type of the interpolation and load-vector stencils: the field's
-// own type.  The FP32 mode keeps FP64 for the load vector it hands to the
-// solves (each stencil result is widened once, where it is stored) and for
-// the correction solves themselves.
+// Arithmetic type of the recomposition's stencils: the field's own type (a
+// recomposition adds a coefficient to an interpolant, with no cancellation).
+// The decomposition always computes in FP64 (see k_loadvec), the correction
+// solves too, and the load vector handed to them is FP64.
 template <typename T>
 using Acc = T;
 
@@ -84,9 +84,9 @@ constexpr int NTHR = TJ * TK;
 #define LV_WAVES (DEC ? 1 : 5)
 #define LV_MAXP 128
 
-template <typename T>
+template <typename T, typename TS = T>
 struct LoadArgs {
-  const T *src;   // level grid: field values (decompose) or stored coefficients (recompose)
+  const TS *src;  // level grid: field values (decompose) or stored coefficients (recompose)
   Map3 smap;
   T *out;         // decompose: coefficient destination (nodal positions)
   Map3 omap;
@@ -128,9 +128,11 @@ __device__ __forceinline__ int xcd_tile(int bid, int nb) {
 //     lerp of the interpolants of the coarse planes on either side.
 // Recomposition stages the stored coefficients (zero at the coarse nodes)
 // and forms f = (P^T M)^{(x)3} C the same way.
-template <typename T, bool DEC, bool NODAL, bool CO0, bool CO1, bool CO2>
-__global__ void __launch_bounds__(NTHR, LV_WAVES) k_loadvec(LoadArgs<T> a) {
-  using A = Acc<T>;
+template <typename T, typename TS, bool DEC, bool NODAL, bool CO0, bool CO1, bool CO2>
+__global__ void __launch_bounds__(NTHR, LV_WAVES) k_loadvec(LoadArgs<T, TS> a) {
+  // a decomposition forms its coefficients as differences of nearly equal
+  // values, so it computes in FP64 whatever the storage type
+  using A = std::conditional_t<DEC, double, Acc<T>>;
   constexpr int SJ = CO1 ? 2 : 1, HJ = CO1 ? 2 : 0;
   constexpr int SK = CO2 ? 2 : 1, HK = CO2 ? 2 : 0;
   constexpr int NJ = SJ * (TJ - 1) + 1 + 2 * HJ;
@@ -215,7 +217,7 @@ __global__ void __launch_bounds__(NTHR, LV_WAVES) k_loadvec(LoadArgs<T> a) {
   // are in flight together: elements outside the grid read the plane's first
   // node (colS = 0) and are masked when staged.
   auto fetch = [&](A (&v)[EPT], int64_t p) {
-    const T *base = a.src + src_plane(p);
+    const TS *base = a.src + src_plane(p);
 #pragma unroll
     for (int i = 0; i < EPT; ++i) v[i] = (A)base[colS[i]];
   };
@@ -256,15 +258,29 @@ __global__ void __launch_bounds__(NTHR, LV_WAVES) k_loadvec(LoadArgs<T> a) {
   for (int e = tid; e < TJ * 5; e += NTHR)
     sW[e] = (CO1 && J0 + e / 5 < a.c1) ? a.W1[J0 * 5 + e] : A(0);
   __syncthreads();
-  // taps of this thread's dim-2 column and dim-1 row, kept in registers
-  A w2r[5], w1r[5];
+  // Taps of this thread's dim-2 column and dim-1 row: kept in registers, or
+  // -- for the FP32 decomposition, which moves half the bytes of FP64 per
+  // step with the same FP64 arithmetic and is latency- rather than
+  // memory-bound -- read from LDS where used, which brings it under 128 VGPRs
+  // and two resident workgroups per CU (measured faster there, slower for the
+  // FP64 and recomposition kernels).
+  constexpr bool kTapsInLds = DEC && sizeof(T) == 4;
+  A w1r[kTapsInLds ? 1 : 5], w2r[kTapsInLds ? 1 : 5];
+  if constexpr (!kTapsInLds) {
 #pragma unroll
-  for (int o = 0; o < 5; ++o) {
-    w2r[o] = sW[TJ * 5 + rK * 5 + o];
-    w1r[o] = sW[hJ * 5 + o];
+    for (int o = 0; o < 5; ++o) {
+      w2r[o] = sW[TJ * 5 + rK * 5 + o];
+      w1r[o] = sW[hJ * 5 + o];
+    }
   }
-  auto w2 = [&](int o) -> A { return w2r[o]; };
-  auto w1 = [&](int o) -> A { return w1r[o]; };
+  auto w2 = [&](int o) -> A {
+    if constexpr (kTapsInLds) return sW[TJ * 5 + rK * 5 + o];
+    else return w2r[o];
+  };
+  auto w1 = [&](int o) -> A {
+    if constexpr (kTapsInLds) return sW[hJ * 5 + o];
+    else return w1r[o];
+  };
   auto reduce2 = [&](const A *s, int off) {
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
@@ -1387,8 +1403,8 @@ __device__ __forceinline__ int64_t tail_off(const TailLevel &L, const int64_t *s
 
 // Decomposition of levels tail_start .. nlev-1.  src: level grid of the first
 // tail level, compact; out: the caller's output array (nodal positions).
-template <typename T>
-__global__ void __launch_bounds__(TAIL_THR) k_tail_dec(const T *__restrict__ src, T *__restrict__ out,
+template <typename T, typename TS>
+__global__ void __launch_bounds__(TAIL_THR) k_tail_dec(const TS *__restrict__ src, T *__restrict__ out,
                                                        TailArgs a) {
   __shared__ TailSmem sm;
   auto buf = [&](int b) { return sm.g + b * kTailNodes; };
@@ -1568,9 +1584,9 @@ int64_t pick_chunk(int64_t c0, int64_t tiles, int64_t slots, int halo, int64_t m
   return best;
 }
 
-template <typename T, bool DEC, bool NODAL, bool C0, bool C1, bool C2>
-void launch_loadvec_t(LoadArgs<T> a, Ctx &cx) {
-  static const int slots = resident_slots((const void *)k_loadvec<T, DEC, NODAL, C0, C1, C2>, NTHR);
+template <typename T, typename TS, bool DEC, bool NODAL, bool C0, bool C1, bool C2>
+void launch_loadvec_t(LoadArgs<T, TS> a, Ctx &cx) {
+  static const int slots = resident_slots((const void *)k_loadvec<T, TS, DEC, NODAL, C0, C1, C2>, NTHR);
   const int64_t tiles = (int64_t)a.gx * a.gy;
   // chunks short enough for the kernel's LDS plane window (2 TI + 3 planes)
   const int64_t maxti = (LV_MAXP - 3) / 2;
@@ -1586,15 +1602,16 @@ void launch_loadvec_t(LoadArgs<T> a, Ctx &cx) {
     const double nl = (double)a.m0 * a.m1 * a.m2, nc = (double)a.c0 * a.c1 * a.c2;
     // recompose: read the coefficients, write f
     // decompose: read the level grid, write the coefficients and f
-    if (DEC && a.out == nullptr) bytes = nl * sizeof(T) + 8.0 * nc;
-    else if (!DEC && a.keep_coarse) bytes = nl * sizeof(T) + 8.0 * nc;
-    else bytes = DEC ? (2.0 * nl - nc) * sizeof(T) + 8.0 * nc : (nl - nc) * sizeof(T) + 8.0 * nc;
+    if (DEC && a.out == nullptr) bytes = nl * sizeof(TS) + 8.0 * nc;
+    else if (!DEC && a.keep_coarse) bytes = nl * sizeof(TS) + 8.0 * nc;
+    else if (DEC) bytes = nl * sizeof(TS) + (nl - nc) * sizeof(T) + 8.0 * nc;
+    else bytes = (nl - nc) * sizeof(TS) + 8.0 * nc;
   }
   TimedLaunch tl(cx.stream,
-                 std::string("k_loadvec<") + tname<T>() + ", " + bname(DEC) + ", " + bname(NODAL) + ", " +
-                     bname(C0) + ", " + bname(C1) + ", " + bname(C2) + ">",
+                 std::string("k_loadvec<") + tname<T>() + ", " + tname<TS>() + ", " + bname(DEC) + ", " +
+                     bname(NODAL) + ", " + bname(C0) + ", " + bname(C1) + ", " + bname(C2) + ">",
                  bytes);
-  hipLaunchKernelGGL((k_loadvec<T, DEC, NODAL, C0, C1, C2>), grid, dim3(NTHR), 0, cx.stream, a);
+  hipLaunchKernelGGL((k_loadvec<T, TS, DEC, NODAL, C0, C1, C2>), grid, dim3(NTHR), 0, cx.stream, a);
 }
 
 // Suffix of a solve's timing label naming what its store does (the kernel
@@ -1616,8 +1633,8 @@ double solve_bytes(double nc, int mode) {
   return 8.0 * nc + sizeof(T) * nc;                             // read F, write grid
 }
 
-template <typename T, bool DEC>
-void launch_loadvec(const Level &L, LoadArgs<T> a, Ctx &cx) {
+template <typename T, typename TS, bool DEC>
+void launch_loadvec(const Level &L, LoadArgs<T, TS> a, Ctx &cx) {
   a.m0 = L.m[0]; a.m1 = L.m[1]; a.m2 = L.m[2];
   a.c0 = L.c[0]; a.c1 = L.c[1]; a.c2 = L.c[2];
   a.r0 = L.d[0].r; a.r1 = L.d[1].r; a.r2 = L.d[2].r;
@@ -1629,25 +1646,25 @@ void launch_loadvec(const Level &L, LoadArgs<T> a, Ctx &cx) {
   // goes through the nodal tables
   if (DEC ? a.omap.t0 != nullptr : a.smap.t0 != nullptr) {
     switch (key) {
-      case 0: launch_loadvec_t<T, DEC, true, false, false, false>(a, cx); break;
-      case 1: launch_loadvec_t<T, DEC, true, false, false, true>(a, cx); break;
-      case 2: launch_loadvec_t<T, DEC, true, false, true, false>(a, cx); break;
-      case 3: launch_loadvec_t<T, DEC, true, false, true, true>(a, cx); break;
-      case 4: launch_loadvec_t<T, DEC, true, true, false, false>(a, cx); break;
-      case 5: launch_loadvec_t<T, DEC, true, true, false, true>(a, cx); break;
-      case 6: launch_loadvec_t<T, DEC, true, true, true, false>(a, cx); break;
-      default: launch_loadvec_t<T, DEC, true, true, true, true>(a, cx); break;
+      case 0: launch_loadvec_t<T, TS, DEC, true, false, false, false>(a, cx); break;
+      case 1: launch_loadvec_t<T, TS, DEC, true, false, false, true>(a, cx); break;
+      case 2: launch_loadvec_t<T, TS, DEC, true, false, true, false>(a, cx); break;
+      case 3: launch_loadvec_t<T, TS, DEC, true, false, true, true>(a, cx); break;
+      case 4: launch_loadvec_t<T, TS, DEC, true, true, false, false>(a, cx); break;
+      case 5: launch_loadvec_t<T, TS, DEC, true, true, false, true>(a, cx); break;
+      case 6: launch_loadvec_t<T, TS, DEC, true, true, true, false>(a, cx); break;
+      default: launch_loadvec_t<T, TS, DEC, true, true, true, true>(a, cx); break;
     }
   } else {
     switch (key) {
-      case 0: launch_loadvec_t<T, DEC, false, false, false, false>(a, cx); break;
-      case 1: launch_loadvec_t<T, DEC, false, false, false, true>(a, cx); break;
-      case 2: launch_loadvec_t<T, DEC, false, false, true, false>(a, cx); break;
-      case 3: launch_loadvec_t<T, DEC, false, false, true, true>(a, cx); break;
-      case 4: launch_loadvec_t<T, DEC, false, true, false, false>(a, cx); break;
-      case 5: launch_loadvec_t<T, DEC, false, true, false, true>(a, cx); break;
-      case 6: launch_loadvec_t<T, DEC, false, true, true, false>(a, cx); break;
-      default: launch_loadvec_t<T, DEC, false, true, true, true>(a, cx); break;
+      case 0: launch_loadvec_t<T, TS, DEC, false, false, false, false>(a, cx); break;
+      case 1: launch_loadvec_t<T, TS, DEC, false, false, false, true>(a, cx); break;
+      case 2: launch_loadvec_t<T, TS, DEC, false, false, true, false>(a, cx); break;
+      case 3: launch_loadvec_t<T, TS, DEC, false, false, true, true>(a, cx); break;
+      case 4: launch_loadvec_t<T, TS, DEC, false, true, false, false>(a, cx); break;
+      case 5: launch_loadvec_t<T, TS, DEC, false, true, false, true>(a, cx); break;
+      case 6: launch_loadvec_t<T, TS, DEC, false, true, true, false>(a, cx); break;
+      default: launch_loadvec_t<T, TS, DEC, false, true, true, true>(a, cx); break;
     }
   }
   cx.check("k_loadvec launch");
@@ -1842,22 +1859,32 @@ void launch_reconstruct(const Level &L, const T *coef, Map3 cmap, const T *uc, T
 }
 
 // Levels tail_start .. nlev-1 in one workgroup.  Decompose: src is the
-// compact level grid of level tail_start, dst the caller's output.
-// Recompose: src is the caller's input, dst the compact level grid.
-template <typename T, bool DEC>
-void launch_tail(const Plan &pl, const T *src, T *dst, Ctx &cx, int t_drop = 0) {
-  const int nt = pl.nlev - pl.tail_start;
+// compact level grid of level tail_start (FP64 from level 1 on), dst the
+// caller's output.  Recompose: src is the caller's input, dst the compact
+// level grid.
+template <typename T, typename TS>
+void launch_tail_dec(const Plan &pl, const TS *src, T *dst, Ctx &cx) {
   const Level &L = pl.lev[pl.tail_start];
   const double n = (double)L.m[0] * L.m[1] * L.m[2];
-  // read the level grid (or the coefficients), write the coefficients (or the level grid)
-  TimedLaunch tl(cx.stream, std::string(DEC ? "k_tail_dec<" : "k_tail_rec<") + tname<T>() + ">",
-                 timing_enabled() ? 2.0 * n * sizeof(T) : 0.0);
-  const TailArgs ta{pl.dev_tail, pl.dev_tail_off, pl.dev_tail_dbl, pl.tail_noff, pl.tail_ndbl, nt, t_drop};
-  if (DEC)
-    hipLaunchKernelGGL((k_tail_dec<T>), dim3(1), dim3(TAIL_THR), 0, cx.stream, src, dst, ta);
-  else
-    hipLaunchKernelGGL((k_tail_rec<T>), dim3(1), dim3(TAIL_THR), 0, cx.stream, src, dst, ta);
-  cx.check(DEC ? "k_tail_dec launch" : "k_tail_rec launch");
+  // read the level grid, write the coefficients
+  TimedLaunch tl(cx.stream, std::string("k_tail_dec<") + tname<T>() + ">",
+                 timing_enabled() ? n * (sizeof(TS) + sizeof(T)) : 0.0);
+  const TailArgs ta{pl.dev_tail, pl.dev_tail_off, pl.dev_tail_dbl, pl.tail_noff, pl.tail_ndbl,
+                    pl.nlev - pl.tail_start, 0};
+  hipLaunchKernelGGL((k_tail_dec<T, TS>), dim3(1), dim3(TAIL_THR), 0, cx.stream, src, dst, ta);
+  cx.check("k_tail_dec launch");
+}
+
+template <typename T>
+void launch_tail_rec(const Plan &pl, const T *src, T *dst, Ctx &cx, int t_drop) {
+  const Level &L = pl.lev[pl.tail_start];
+  const double n = (double)L.m[0] * L.m[1] * L.m[2];
+  // read the coefficients, write the level grid
+  TimedLaunch tl(cx.stream, std::string("k_tail_rec<") + tname<T>() + ">", timing_enabled() ? 2.0 * n * sizeof(T) : 0.0);
+  const TailArgs ta{pl.dev_tail, pl.dev_tail_off, pl.dev_tail_dbl, pl.tail_noff, pl.tail_ndbl,
+                    pl.nlev - pl.tail_start, t_drop};
+  hipLaunchKernelGGL((k_tail_rec<T>), dim3(1), dim3(TAIL_THR), 0, cx.stream, src, dst, ta);
+  cx.check("k_tail_rec launch");
 }
 
 struct Workspace {
@@ -1866,13 +1893,19 @@ struct Workspace {
   double *F2;  // coarser levels' load vector while level 0's runs beside them (nlev >= 2)
 };
 
-Workspace carve(const Plan &pl, void *ws, size_t elem) {
+// The level-grid buffers hold FP64 (a decomposition keeps its coarser level
+// grids in FP64 whatever the storage type) or the field's type (recomposition).
+Workspace carve(const Plan &pl, void *ws) {
   auto al = [](size_t b) { return (b + 255) / 256 * 256; };
-  const size_t nb = al((size_t)pl.max_coarse * elem), nf = al((size_t)pl.max_coarse * sizeof(double));
+  const size_t nb = al((size_t)pl.max_coarse * sizeof(double)), nf = nb;
   char *p = (char *)ws;
   return Workspace{{p, p + nb}, (double *)(p + 2 * nb), pl.nlev >= 2 ? (double *)(p + 2 * nb + nf) : nullptr};
 }
 
+// Decomposition.  Level 0 reads the caller's input; every coarser level grid
+// is kept in FP64 in the workspace (written by the previous level's last
+// solve), so that an FP32 field's coefficients at every level are rounded to
+// FP32 once, when stored, and carry no rounding of the grids they came from.
 template <typename T>
 bool decompose_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t stream, std::string &err) {
   Ctx cx{stream, &err};
@@ -1884,37 +1917,42 @@ bool decompose_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t stre
     }
     return true;
   }
-  Workspace w = carve(pl, ws, sizeof(T));
-  const T *src = in;
-  Map3 smap = compact_map(pl.n[1], pl.n[2]);
+  Workspace w = carve(pl, ws);
+  const double *src = nullptr;  // level grid of levels >= 1 (FP64)
   const int st = std::min(pl.tail_start, pl.nlev);
   const std::vector<LevelTune> tune = pl.tune_snapshot();
   for (int s = 0; s < st && cx.ok; ++s) {
     const Level &L = pl.lev[s];
-    T *next = (T *)w.buf[s % 2];
-    LoadArgs<T> a{};
-    a.src = src;
-    a.smap = smap;
-    a.out = out;
-    a.omap = (s == 0) ? compact_map(pl.n[1], pl.n[2]) : nodal_map(L);
-    a.F = w.F;
+    double *next = (double *)w.buf[s % 2];
     cx.ti_req = s < (int)tune.size() ? tune[s].lv_ti[0] : 0;
-    launch_loadvec<T, true>(L, a, cx);
-    cx.ti_req = 0;
-    Epi<T> ep{};
-    if (s + 1 < pl.nlev) {
-      ep.mode = EPI_STORE_COMPACT;
-      ep.dst = next;
+    if (s == 0) {
+      LoadArgs<T> a{};
+      a.src = in;
+      a.smap = compact_map(pl.n[1], pl.n[2]);
+      a.out = out;
+      a.omap = compact_map(pl.n[1], pl.n[2]);
+      a.F = w.F;
+      launch_loadvec<T, T, true>(L, a, cx);
     } else {
-      ep.mode = EPI_STORE_NODAL;
-      ep.dst = out;
-      ep.nmap = nodal_map(pl.lev[s + 1]);
+      LoadArgs<T, double> a{};
+      a.src = src;
+      a.smap = compact_map(L.m[1], L.m[2]);
+      a.out = out;
+      a.omap = nodal_map(L);
+      a.F = w.F;
+      launch_loadvec<T, double, true>(L, a, cx);
     }
-    solve_all<T>(w.F, L, ep, cx);
+    cx.ti_req = 0;
+    if (s + 1 < pl.nlev)
+      solve_all<double>(w.F, L, Epi<double>{EPI_STORE_COMPACT, next, Map3{}}, cx);
+    else
+      solve_all<T>(w.F, L, Epi<T>{EPI_STORE_NODAL, out, nodal_map(pl.lev[s + 1])}, cx);
     src = next;
-    smap = compact_map(L.c[1], L.c[2]);
   }
-  if (st < pl.nlev && cx.ok) launch_tail<T, true>(pl, src, out, cx);
+  if (st < pl.nlev && cx.ok) {
+    if (st == 0) launch_tail_dec<T, T>(pl, in, out, cx);
+    else launch_tail_dec<T, double>(pl, src, out, cx);
+  }
   return cx.ok;
 }
 
@@ -1940,7 +1978,7 @@ bool recompose_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t stre
     }
     return true;
   }
-  Workspace w = carve(pl, ws, sizeof(T));
+  Workspace w = carve(pl, ws);
   const int st = std::min(pl.tail_start, pl.nlev);
   const int drop = pl.nlev - std::max(0, std::min(nkeep, pl.nlev));  // levels below take zero coefficients
   const std::vector<LevelTune> tune0 = pl.tune_snapshot();
@@ -1961,7 +1999,7 @@ bool recompose_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t stre
     a.smap = compact_map(pl.n[1], pl.n[2]);
     a.F = w.F;
     hx.ti_req = tune0.empty() ? 0 : tune0[0].lv_ti[1];
-    launch_loadvec<T, false>(L, a, hx);
+    launch_loadvec<T, T, false>(L, a, hx);
     hx.ti_req = 0;
     if (hx.ok) solve_all<T>(w.F, L, Epi<T>{EPI_Z, nullptr, Map3{}}, hx, 1);
     if (hipEventRecord((hipEvent_t)fk->join, hs) != hipSuccess) {
@@ -1975,7 +2013,7 @@ bool recompose_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t stre
   if (st < pl.nlev) {
     // the coarsest levels in one workgroup, up to the level grid of level st
     V = (st == 0) ? out : (T *)w.buf[st % 2];
-    launch_tail<T, false>(pl, in, V, cx, std::max(0, drop - st));
+    launch_tail_rec<T>(pl, in, V, cx, std::max(0, drop - st));
   } else {
     // coarsest grid values, gathered compactly
     const Level &Lc = pl.lev[pl.nlev];
@@ -2016,7 +2054,7 @@ bool recompose_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t stre
       a.smap = cmap;
       a.F = Fc;
       cx.ti_req = lt.lv_ti[1];
-      launch_loadvec<T, false>(L, a, cx);
+      launch_loadvec<T, T, false>(L, a, cx);
       cx.ti_req = 0;
       solve_all<T>(Fc, L, ep, cx);
     }
@@ -2164,7 +2202,7 @@ bool decompose4_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t str
       a.out = tc ? out + pl.tpos[s][t] * S0 : nullptr;
       a.omap = tc ? omap : lmap;
       a.F = G + t * cs;
-      launch_loadvec<T, true>(L, a, cx);
+      launch_loadvec<T, T, true>(L, a, cx);
     }
     if (cot && cx.ok) launch_tload(w.G, Lt, w.F, cs, cx);
     solve_all4<T>(w.F, L, Lt, Epi<T>{EPI_STORE_COMPACT, next, Map3{}}, cx);
@@ -2210,7 +2248,7 @@ bool recompose4_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t str
       a.smap = cmap;
       a.F = G + t * cs;
       a.keep_coarse = (cot && !tcoarse(t, tm)) ? 1 : 0;
-      launch_loadvec<T, false>(L, a, cx);
+      launch_loadvec<T, T, false>(L, a, cx);
     }
     if (cot && cx.ok) launch_tload(w.G, Lt, w.F, cs, cx);
     solve_all4<T>(w.F, L, Lt, Epi<T>{EPI_SUB_COMPACT, V, Map3{}}, cx);
@@ -2284,7 +2322,7 @@ bool autotune_t(Plan &pl, const T *in, T *out, void *ws, hipStream_t stream, std
                 std::string &report) {
   Ctx cx{stream, &err};
   if (pl.nlev == 0) return true;
-  Workspace w = carve(pl, ws, sizeof(T));
+  Workspace w = carve(pl, ws);
   const int nt = std::min(pl.tail_start, pl.nlev);
   std::vector<LevelTune> tune(pl.nlev);
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -2340,16 +2378,37 @@ bool autotune_t(Plan &pl, const T *in, T *out, void *ws, hipStream_t stream, std
     const int64_t tiles_lv = ((L.c[2] + TK - 1) / TK) * ((L.c[1] + TJ - 1) / TJ);
     const int halo_lv = L.co[0] ? 2 : 0;
     for (int dec = 1; dec >= 0 && cx.ok; --dec) {
-      LoadArgs<T> a{};
-      a.src = dec ? (s == 0 ? in : (const T *)w.buf[(s + 1) % 2]) : in;
-      a.smap = (dec || s == 0) ? compact_map(L.m[1], L.m[2]) : nodal_map(L);
-      a.out = out;
-      a.omap = s == 0 ? compact_map(L.m[1], L.m[2]) : nodal_map(L);
-      a.F = w.F;
+      // level s's load vector as the decomposition (FP64 level grid from
+      // level 1 on) or the recomposition launches it
+      auto lv = [&]() {
+        const Map3 cm = compact_map(L.m[1], L.m[2]);
+        if (!dec) {
+          LoadArgs<T> a{};
+          a.src = in;
+          a.smap = s == 0 ? cm : nodal_map(L);
+          a.F = w.F;
+          launch_loadvec<T, T, false>(L, a, cx);
+        } else if (s == 0) {
+          LoadArgs<T> a{};
+          a.src = in;
+          a.smap = cm;
+          a.out = out;
+          a.omap = cm;
+          a.F = w.F;
+          launch_loadvec<T, T, true>(L, a, cx);
+        } else {
+          LoadArgs<T, double> a{};
+          a.src = (const double *)w.buf[(s + 1) % 2];
+          a.smap = cm;
+          a.out = out;
+          a.omap = nodal_map(L);
+          a.F = w.F;
+          launch_loadvec<T, double, true>(L, a, cx);
+        }
+      };
       cx.dry = true;
       cx.ti_req = 0;
-      if (dec) launch_loadvec<T, true>(L, a, cx);
-      else launch_loadvec<T, false>(L, a, cx);
+      lv();
       cx.dry = false;
       const int slots = cx.slots_out, ti0 = cx.ti_out;
       const double per_plane = (dec ? 2.0 * nl * es : nl * es) / (double)L.c[0];
@@ -2364,8 +2423,7 @@ bool autotune_t(Plan &pl, const T *in, T *out, void *ws, hipStream_t stream, std
       }
       const int best = choose(cand, ti0, [&](int ti) {
         cx.ti_req = ti;
-        if (dec) launch_loadvec<T, true>(L, a, cx);
-        else launch_loadvec<T, false>(L, a, cx);
+        lv();
         cx.ti_req = 0;
       }, dec ? "decompose load vector planes per workgroup" : "recompose load vector planes per workgroup", s);
       tune[s].lv_ti[dec ? 0 : 1] = best > 0 ? best : 0;

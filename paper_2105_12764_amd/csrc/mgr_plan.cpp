@@ -81,11 +81,13 @@ size_t workspace_bytes(const int64_t n[kDims], int nlev, size_t elem_size) {
     c2 *= coarse_count(coarse_count(n[k]));
   }
   auto al = [](size_t b) { return (b + 255) / 256 * 256; };
-  // two coarse grids in the field's type (ping-pong) + one FP64 load/correction
-  // grid, and with two or more levels one more FP64 grid of the next level's
-  // size for the coarser levels while the finest level's recompose load vector
-  // and solves run beside them
-  size_t b = 2 * al((size_t)c1 * elem_size) + al((size_t)c1 * sizeof(double));
+  // two coarse level grids in FP64 (ping-pong; a decomposition keeps its
+  // coarser level grids in FP64 whatever the field's type) + one FP64
+  // load/correction grid, and with two or more levels one more FP64 grid of the
+  // next level's size for the coarser levels while the finest level's
+  // recompose load vector and solves run beside them
+  (void)elem_size;
+  size_t b = 3 * al((size_t)c1 * sizeof(double));
   if (nlev >= 2) b += al((size_t)c2 * sizeof(double));
   return b;
 }

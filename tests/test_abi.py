@@ -46,11 +46,11 @@ def test_workspace_size():
     assert mgr.workspace_size((513, 513, 513), np.float64, 0) == 0
     n1, n2 = 257 ** 3, 129 ** 3
     al = lambda b: (b + 255) // 256 * 256
-    # two level-1 grids in the field's type, an FP64 level-1 grid and (two or
-    # more levels) an FP64 level-2 grid
-    assert mgr.workspace_size((513, 513, 513), np.float64, 9) == 2 * al(8 * n1) + al(8 * n1) + al(8 * n2)
-    assert mgr.workspace_size((513, 513, 513), np.float32, 9) == 2 * al(4 * n1) + al(8 * n1) + al(8 * n2)
-    assert mgr.workspace_size((513, 513, 513), np.float32, 1) == 2 * al(4 * n1) + al(8 * n1)
+    # three FP64 level-1 grids (level grids and load vector; FP64 for FP32
+    # fields too) and (two or more levels) an FP64 level-2 grid
+    assert mgr.workspace_size((513, 513, 513), np.float64, 9) == 3 * al(8 * n1) + al(8 * n2)
+    assert mgr.workspace_size((513, 513, 513), np.float32, 9) == 3 * al(8 * n1) + al(8 * n2)
+    assert mgr.workspace_size((513, 513, 513), np.float32, 1) == 3 * al(8 * n1)
     with pytest.raises(mgr.MgrError):
         mgr.workspace_size((513, 513, 513), np.float64, 10)
     # 4-D: two coarse 4-D grids in the field's type, the FP64 coarse grid and

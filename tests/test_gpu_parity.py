@@ -232,3 +232,63 @@ def test_binding_checks_out_and_workspace():
     ref = mgr.decompose(x, coords, nlev)
     torch.cuda.synchronize()
     assert torch.equal(d, ref)
+
+
+@pytest.mark.parametrize("name", ["box400x300x250_f32", "cube513_f32"])
+def test_fp32_errors_per_coefficient_class(name):
+    """FP32 mode against the FP64 oracle, stated per result: max and L2 error
+    of the whole representation, and of every coefficient class (the nodes
+    that leave the hierarchy at one level; the last class is the coarsest
+    grid).  Overall: relative L2 <= 1e-5.  Per class: max error over the
+    field's scale (max |oracle|) <= 1e-5."""
+    shape, seed, nonuni, dtype, nlev = WORKLOADS[name]
+    print(f"\n[case] {name}: FP32 errors per class", flush=True)
+    u, coords = make_input(shape, seed, nonuniform=nonuni, dtype=dtype)
+    d = mgr.decompose(torch.from_numpy(u).cuda(), coords, nlev)
+    torch.cuda.synchronize()
+    got = d.cpu().numpy().astype(np.float64)
+    ref = oracle.decompose(u.astype(np.float64), coords, nlev)
+    scale = float(np.max(np.abs(ref)))
+    diff = got - ref
+    l2 = float(np.linalg.norm(diff) / np.linalg.norm(ref))
+    mx = float(np.max(np.abs(diff)) / scale)
+    print(f"  all: max {mx:.2e}  L2 {l2:.2e}", flush=True)
+    assert l2 <= TOL32
+    lv = [_drop_level(n, nlev) for n in shape]
+    cls = np.minimum.outer(np.minimum.outer(lv[0], lv[1]), lv[2])
+    for c in range(nlev + 1):
+        m = cls == c
+        e_max = float(np.max(np.abs(diff[m])))
+        e_l2 = float(np.linalg.norm(diff[m]) / max(np.linalg.norm(ref[m]), 1e-300))
+        print(f"  class {c} ({int(m.sum())} nodes): max {e_max / scale:.2e} of the field scale, "
+              f"L2 {e_l2:.2e} of the class", flush=True)
+        assert e_max <= TOL32 * scale, (c, e_max / scale)
+
+
+def test_fp32_smooth_field_within_tolerance():
+    """FP32 mode on a smooth field with no noise, where a coefficient is the
+    small difference of nearly equal values: relative L2 against the FP64
+    oracle within 1e-5, overall and in every coefficient class (so neither
+    the coefficient arithmetic nor the coarser level grids may round at the
+    field's scale)."""
+    n = 257
+    shape, nlev = (n, n, n), mgr.max_levels((n, n, n))
+    print(f"\n[case] smooth field {shape} float32, {nlev} levels", flush=True)
+    x = np.linspace(0.0, 1.0, n)
+    u = (np.sin(2 * np.pi * x)[:, None, None] * np.cos(2 * np.pi * x)[None, :, None]
+         * np.sin(np.pi * x)[None, None, :] + 2.0).astype(np.float32)
+    d = mgr.decompose(torch.from_numpy(u).cuda(), None, nlev)
+    torch.cuda.synchronize()
+    got = d.cpu().numpy().astype(np.float64)
+    ref = oracle.decompose(u.astype(np.float64), None, nlev)
+    diff = got - ref
+    l2 = float(np.linalg.norm(diff) / np.linalg.norm(ref))
+    print(f"  all: L2 {l2:.2e}", flush=True)
+    assert l2 <= TOL32
+    lv = _drop_level(n, nlev)
+    cls = np.minimum.outer(np.minimum.outer(lv, lv), lv)
+    for c in range(nlev + 1):
+        m = cls == c
+        e = float(np.linalg.norm(diff[m]) / np.linalg.norm(ref[m]))
+        print(f"  class {c}: L2 {e:.2e} of the class", flush=True)
+        assert e <= TOL32, (c, e)
