@@ -81,7 +81,7 @@ __device__ __forceinline__ int64_t coarse_idx(int64_t g, int64_t m, int64_t c) {
 constexpr int TJ = 16;       // coarse rows (dim 1) per tile
 constexpr int TK = 32;       // coarse columns (dim 2) per tile
 constexpr int NTHR = TJ * TK;
-#define LV_WAVES (DEC ? 1 : 5)
+#define LV_WAVES (DEC ? (sizeof(TS) == 4 ? 4 : 1) : 5)
 #define LV_MAXP 128
 
 template <typename T, typename TS = T>
@@ -133,6 +133,8 @@ __global__ void __launch_bounds__(NTHR, LV_WAVES) k_loadvec(LoadArgs<T, TS> a) {
   // a decomposition forms its coefficients as differences of nearly equal
   // values, so it computes in FP64 whatever the storage type
   using A = std::conditional_t<DEC, double, Acc<T>>;
+  // staged planes hold the loaded values, exact in the source type
+  using P = TS;
   constexpr int SJ = CO1 ? 2 : 1, HJ = CO1 ? 2 : 0;
   constexpr int SK = CO2 ? 2 : 1, HK = CO2 ? 2 : 0;
   constexpr int NJ = SJ * (TJ - 1) + 1 + 2 * HJ;
@@ -140,8 +142,8 @@ __global__ void __launch_bounds__(NTHR, LV_WAVES) k_loadvec(LoadArgs<T, TS> a) {
   constexpr int NE = NJ * NK;
   constexpr int EPT = (NE + NTHR - 1) / NTHR;  // tile elements per thread
   constexpr int NG = NJ * TK;                  // dim-2 reduced rows of one plane
-  __shared__ A sA[NE];      // plane b (coarse along dim 0)
-  __shared__ A sB[NE];      // plane a (fine along dim 0)
+  __shared__ P sA[NE];      // plane b (coarse along dim 0)
+  __shared__ P sB[NE];      // plane a (fine along dim 0)
   __shared__ A sG[2 * NG];  // dim-2 reduced rows of b, then of a
   __shared__ A sR1[DEC ? NJ : 1], sR2[DEC ? NK : 1];  // interpolation weights of rows / columns
   // Tables read inside the plane loop are staged in LDS (or loaded one step
@@ -216,31 +218,32 @@ __global__ void __launch_bounds__(NTHR, LV_WAVES) k_loadvec(LoadArgs<T, TS> a) {
   // loads of one plane into registers.  Branch-free, so that all of them
   // are in flight together: elements outside the grid read the plane's first
   // node (colS = 0) and are masked when staged.
-  auto fetch = [&](A (&v)[EPT], int64_t p) {
+  auto fetch = [&](P (&v)[EPT], int64_t p) {
     const TS *base = a.src + src_plane(p);
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) v[i] = (A)base[colS[i]];
+    for (int i = 0; i < EPT; ++i) v[i] = base[colS[i]];
   };
   // stage a plane into LDS: zero outside the grid and, for recomposition of a
   // plane coarse along dim 0, at the stored coarse values (not coefficients)
-  auto stage = [&](A *s, const A (&v)[EPT], bool zero_coarse) {
+  auto stage = [&](P *s, const P (&v)[EPT], bool zero_coarse) {
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
       const int e = tid + i * NTHR;
       const unsigned f = flag_of(i);
       const bool keep = (f & F_IN) && !(zero_coarse && (f & F_C1) && (f & F_C2));
-      if (e < NE) s[e] = keep ? v[i] : A(0);
+      if (e < NE) s[e] = keep ? v[i] : P(0);
     }
   };
 
   // bilinear interpolant (dims 1, 2) at tile element e of the staged plane s,
   // branch-free: along a dimension where the node is coarse both neighbours
   // are the node itself and the weight is 0 (the weight tables hold 0 there)
-  auto interp2 = [&](const A *s, int e, unsigned f) -> A {
+  auto interp2 = [&](const P *s, int e, unsigned f) -> A {
     if (!(f & F_IN)) return A(0);
     const int dk = (f & F_C2) ? 0 : 1, dj = (f & F_C1) ? 0 : NK;
     const A rk = sR2[e % NK], rj = sR1[e / NK];
-    return lerp(lerp(s[e - dj - dk], s[e - dj + dk], rk), lerp(s[e + dj - dk], s[e + dj + dk], rk), rj);
+    return lerp(lerp((A)s[e - dj - dk], (A)s[e - dj + dk], rk), lerp((A)s[e + dj - dk], (A)s[e + dj + dk], rk),
+                rj);
   };
 
   // P^T M along dim 2 of the staged plane s into sG + off, stored column-major
@@ -281,7 +284,7 @@ __global__ void __launch_bounds__(NTHR, LV_WAVES) k_loadvec(LoadArgs<T, TS> a) {
     if constexpr (kTapsInLds) return sW[hJ * 5 + o];
     else return w1r[o];
   };
-  auto reduce2 = [&](const A *s, int off) {
+  auto reduce2 = [&](const P *s, int off) {
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
       const int j = rj0 + q * RG;
@@ -289,11 +292,11 @@ __global__ void __launch_bounds__(NTHR, LV_WAVES) k_loadvec(LoadArgs<T, TS> a) {
         A g = A(0);
         if (rOK) {
           if (CO2) {
-            const A *row = s + j * NK + 2 * rK;
+            const P *row = s + j * NK + 2 * rK;
 #pragma unroll
-            for (int o = 0; o < 5; ++o) g = fma(w2(o), row[o], g);
+            for (int o = 0; o < 5; ++o) g = fma(w2(o), (A)row[o], g);
           } else {
-            g = s[j * NK + rK];
+            g = (A)s[j * NK + rK];
           }
         }
         sG[off + rK * NJ + j] = g;
@@ -347,7 +350,7 @@ __global__ void __launch_bounds__(NTHR, LV_WAVES) k_loadvec(LoadArgs<T, TS> a) {
     }
     kv = *kp;
   };
-  A va[EPT], vb[EPT];
+  P va[EPT], vb[EPT];
   {
     int64_t pa, pb;
     planes(sbeg, pa, pb);
@@ -387,7 +390,7 @@ __global__ void __launch_bounds__(NTHR, LV_WAVES) k_loadvec(LoadArgs<T, TS> a) {
         // written here too (their coefficient is exactly 0): that keeps every
         // written row whole, so no cache line of the output is stored in part.
         if (own_p && (f & F_OWN) && (!NODAL || !((f & F_C1) && (f & F_C2))))
-          a.out[oo + (NODAL ? colO[NODAL ? i : 0] : colS[i])] = (T)(sA[e] - piNext[i]);
+          a.out[oo + (NODAL ? colO[NODAL ? i : 0] : colS[i])] = (T)((A)sA[e] - piNext[i]);
       }
     }
     if (DEC && pa >= 0) {
@@ -398,7 +401,7 @@ __global__ void __launch_bounds__(NTHR, LV_WAVES) k_loadvec(LoadArgs<T, TS> a) {
         const int e = tid + i * NTHR;
         if (e < NE && own_p && (flag_of(i) & F_OWN))
           a.out[oo + (NODAL ? colO[NODAL ? i : 0] : colS[i])] =
-              (T)(sB[e] - lerp(piPrev[i], piNext[i], kst[5]));
+              (T)((A)sB[e] - lerp(piPrev[i], piNext[i], kst[5]));
       }
     }
     __syncthreads();
