@@ -64,10 +64,9 @@ int mgr_max_levels(int ndim, const int64_t *shape);
 /* Bytes of device workspace that mgr_decompose / mgr_recompose need for this
  * request (0 when nlevels == 0): three FP64 grids of the level-1 shape (the
  * decomposition keeps its coarser level grids in FP64 also for FP32 fields)
- * and, with two or more levels, one FP64 grid of the level-2 shape (4-D: two
- * coarse 4-D grids in the field's type, the FP64
- * coarse grid and an FP64 coarse space grid per time step).  Host only, no
- * GPU needed.
+ * and, with two or more levels, one FP64 grid of the level-2 shape (4-D:
+ * three FP64 coarse 4-D grids and an FP64 coarse space grid per time step).
+ * Host only, no GPU needed.
  * Returns MGR_ERR_INVALID_ARG for a bad shape, dtype or level count. */
 mgr_status mgr_workspace_size(int ndim, const int64_t *shape, mgr_dtype dtype,
                               int nlevels, size_t *bytes);

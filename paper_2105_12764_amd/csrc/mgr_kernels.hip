@@ -1087,11 +1087,11 @@ __device__ __forceinline__ void nb_dim(int64_t i, int64_t m, int64_t c, bool co,
   }
 }
 
-template <typename T>
+template <typename T, typename TS = T>
 struct TfineArgs {
-  const T *src;          // decompose: compact level grid; recompose: stored coefficients (finest layout)
+  const TS *src;         // decompose: compact level grid; recompose: stored coefficients (finest layout)
   T *dst;                // decompose: output (finest layout); recompose: compact level grid
-  const T *crs;          // coarse values: the level grid (decompose) or the compact coarse grid (recompose)
+  const TS *crs;         // coarse values: the level grid (decompose) or the compact coarse grid (recompose)
   Map3 fmap;             // space map of the finest-layout side
   const int64_t *tnod;   // finest time index of each level time position
   const double *rt;      // time interpolation weights of the level
@@ -1114,8 +1114,8 @@ constexpr int TF_THR = 256;
 constexpr int TF_ROWS = 8;   // fine rows (dim 1) per workgroup
 constexpr int TF_CH = 512;   // fine columns (dim 2) per pass
 constexpr int TF_PITCH = TF_CH + 2;
-template <typename T, bool DEC>
-__global__ void __launch_bounds__(TF_THR) k_tfine(TfineArgs<T> a) {
+template <typename T, typename TS, bool DEC>
+__global__ void __launch_bounds__(TF_THR) k_tfine(TfineArgs<T, TS> a) {
   __shared__ double sR[TF_ROWS * TF_PITCH];
   const int tid = threadIdx.x;
   const int64_t sm = a.m0 * a.m1 * a.m2;
@@ -1138,7 +1138,7 @@ __global__ void __launch_bounds__(TF_THR) k_tfine(TfineArgs<T> a) {
     nb_dim<false>(j1 - 1, a.m1, a.c1, a.co1, a.r1, lo, J1, w);
     const double rt = a.rt[t];
     // the earlier and later coarse slices (level positions t -/+ 1, or coarse indices q, q + 1)
-    const T *cl = a.crs + (DEC ? t - 1 : q) * ss + l0 * s0, *cr = a.crs + (DEC ? t + 1 : q + 1) * ss + l0 * s0;
+    const TS *cl = a.crs + (DEC ? t - 1 : q) * ss + l0 * s0, *cr = a.crs + (DEC ? t + 1 : q + 1) * ss + l0 * s0;
     const int64_t dh = (h0 - l0) * s0;
     const int64_t frow = a.tnod[t] * a.S0;  // this slice in the finest layout
     for (int64_t k0 = 0; k0 < a.m2; k0 += TF_CH) {
@@ -1177,9 +1177,9 @@ __global__ void __launch_bounds__(TF_THR) k_tfine(TfineArgs<T> a) {
 }
 
 // The coarsest grid of a 4-D field between its nodal positions and a compact
-// grid (TO_NODAL: compact -> nodal).
-template <typename T, bool TO_NODAL>
-__global__ void __launch_bounds__(256) k_nodal4(const T *src, T *dst, Map3 nmap, const int64_t *tnod, int64_t S0,
+// grid (TO_NODAL: compact -> nodal), converted to the destination's type.
+template <typename TS, typename TD, bool TO_NODAL>
+__global__ void __launch_bounds__(256) k_nodal4(const TS *src, TD *dst, Map3 nmap, const int64_t *tnod, int64_t S0,
                                                 int64_t tm, int64_t m0, int64_t m1, int64_t m2) {
   const int64_t n = tm * m0 * m1 * m2;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
@@ -1187,9 +1187,9 @@ __global__ void __launch_bounds__(256) k_nodal4(const T *src, T *dst, Map3 nmap,
     const int64_t k = e % m2, r1 = e / m2, j = r1 % m1, r0 = r1 / m1, i = r0 % m0, t = r0 / m0;
     const int64_t o = tnod[t] * S0 + moff(nmap, i, j, k);
     if (TO_NODAL)
-      dst[o] = src[e];
+      dst[o] = (TD)src[e];
     else
-      dst[e] = src[o];
+      dst[e] = (TD)src[o];
   }
 }
 
@@ -2076,11 +2076,13 @@ struct Workspace4 {
   double *F, *G;
 };
 
-Workspace4 carve4(const Plan &pl, void *ws, size_t elem) {
+// Level-grid buffers in FP64, as in 3-D (the decomposition keeps its coarser
+// level grids in FP64; the recomposition uses them in the field's type).
+Workspace4 carve4(const Plan &pl, void *ws) {
   auto al = [](size_t b) { return (b + 255) / 256 * 256; };
   const int64_t cs = pl.lev[0].c[0] * pl.lev[0].c[1] * pl.lev[0].c[2];
   const int64_t c4 = pl.time->lev[0].c[2] * cs;
-  const size_t nb = al((size_t)c4 * elem), nf = al((size_t)c4 * sizeof(double));
+  const size_t nb = al((size_t)c4 * sizeof(double)), nf = nb;
   char *p = (char *)ws;
   return Workspace4{{p, p + nb}, (double *)(p + 2 * nb), (double *)(p + 2 * nb + nf)};
 }
@@ -2133,12 +2135,12 @@ void launch_tload(const double *G, const Level &Lt, double *F, int64_t ncs, Ctx 
   cx.check("k_tload launch");
 }
 
-template <typename T, bool DEC>
-void launch_tfine(const Plan &pl, const Level &L, const Level &Lt, const T *src, T *dst, const T *crs,
+template <typename T, typename TS, bool DEC>
+void launch_tfine(const Plan &pl, const Level &L, const Level &Lt, const TS *src, T *dst, const TS *crs,
                   Map3 fmap, Ctx &cx) {
   const int64_t tm = Lt.m[2], nf = (tm - 1) / 2;
   if (nf <= 0) return;
-  TfineArgs<T> a{};
+  TfineArgs<T, TS> a{};
   a.src = src; a.dst = dst; a.crs = crs; a.fmap = fmap;
   a.tnod = Lt.d[2].nodal; a.rt = Lt.d[2].r;
   a.S0 = pl.n[0] * pl.n[1] * pl.n[2];
@@ -2151,19 +2153,19 @@ void launch_tfine(const Plan &pl, const Level &L, const Level &Lt, const T *src,
   const int64_t jobs = nf * L.m[0] * ((L.m[1] + TF_ROWS - 1) / TF_ROWS);  // row groups of the time-fine slices
   const dim3 grid((unsigned)std::min<int64_t>(jobs, (int64_t)1 << 20));
   TimedLaunch tl(cx.stream, std::string("k_tfine<") + tname<T>() + ", " + bname(DEC) + ">",
-                 timing_enabled() ? 2.0 * (double)nf * (double)sm * sizeof(T) : 0.0);
-  hipLaunchKernelGGL((k_tfine<T, DEC>), grid, dim3(TF_THR), 0, cx.stream, a);
+                 timing_enabled() ? (double)nf * (double)sm * (sizeof(T) + sizeof(TS)) : 0.0);
+  hipLaunchKernelGGL((k_tfine<T, TS, DEC>), grid, dim3(TF_THR), 0, cx.stream, a);
   cx.check("k_tfine launch");
 }
 
-template <typename T, bool TO_NODAL>
-void launch_nodal4(const Plan &pl, const T *src, T *dst, Ctx &cx) {
+template <typename TS, typename TD, bool TO_NODAL>
+void launch_nodal4(const Plan &pl, const TS *src, TD *dst, Ctx &cx) {
   const Level &L = pl.lev[pl.nlev];
   const Level &Lt = pl.time->lev[pl.nlev];
   const int64_t n = Lt.m[2] * L.m[0] * L.m[1] * L.m[2];
-  TimedLaunch tl(cx.stream, std::string("k_nodal4<") + tname<T>() + ", " + bname(TO_NODAL) + ">",
-                 timing_enabled() ? 2.0 * (double)n * sizeof(T) : 0.0);
-  hipLaunchKernelGGL((k_nodal4<T, TO_NODAL>), dim3((unsigned)grid_1d(n, 256)), dim3(256), 0, cx.stream, src, dst,
+  TimedLaunch tl(cx.stream, std::string("k_nodal4<") + tname<TD>() + ", " + bname(TO_NODAL) + ">",
+                 timing_enabled() ? (double)n * (sizeof(TS) + sizeof(TD)) : 0.0);
+  hipLaunchKernelGGL((k_nodal4<TS, TD, TO_NODAL>), dim3((unsigned)grid_1d(n, 256)), dim3(256), 0, cx.stream, src, dst,
                      nodal_map(L), Lt.d[2].nodal, pl.n[0] * pl.n[1] * pl.n[2], Lt.m[2], L.m[0], L.m[1], L.m[2]);
   cx.check("k_nodal4 launch");
 }
@@ -2172,7 +2174,34 @@ void launch_nodal4(const Plan &pl, const T *src, T *dst, Ctx &cx) {
 // slice (with the coefficients of the time-coarse slices, which only space
 // interpolation reaches), the load vector along time, the four solves (their
 // solution is the next level's grid), then the coefficients of the time-fine
-// slices.
+// slices.  The level grid `src` is the field at level 0 and FP64 from level 1
+// on; the solves store the next level's grid in FP64 into `next`.
+template <typename T, typename TS>
+void decompose4_level(const Plan &pl, int s, const TS *src, T *out, double *next, const Workspace4 &w, Ctx &cx) {
+  const Level &L = pl.lev[s];
+  const Level &Lt = pl.time->lev[s];
+  const int64_t S0 = pl.n[0] * pl.n[1] * pl.n[2];
+  const int64_t tm = Lt.m[2];
+  const bool cot = Lt.co[2];
+  const int64_t sm = L.m[0] * L.m[1] * L.m[2], cs = L.c[0] * L.c[1] * L.c[2];
+  double *G = cot ? w.G : w.F;
+  const Map3 lmap = compact_map(L.m[1], L.m[2]);
+  const Map3 omap = (s == 0) ? lmap : nodal_map(L);
+  for (int64_t t = 0; t < tm && cx.ok; ++t) {
+    const bool tc = tcoarse(t, tm) || !cot;
+    LoadArgs<T, TS> a{};
+    a.src = src + t * sm;
+    a.smap = lmap;
+    a.out = tc ? out + pl.tpos[s][t] * S0 : nullptr;
+    a.omap = tc ? omap : lmap;
+    a.F = G + t * cs;
+    launch_loadvec<T, TS, true>(L, a, cx);
+  }
+  if (cot && cx.ok) launch_tload(w.G, Lt, w.F, cs, cx);
+  solve_all4<double>(w.F, L, Lt, Epi<double>{EPI_STORE_COMPACT, next, Map3{}}, cx);
+  if (cot && cx.ok) launch_tfine<T, TS, true>(pl, L, Lt, src, out, src, omap, cx);
+}
+
 template <typename T>
 bool decompose4_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t stream, std::string &err) {
   Ctx cx{stream, &err};
@@ -2184,35 +2213,15 @@ bool decompose4_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t str
     }
     return true;
   }
-  const Plan &tp = *pl.time;
-  Workspace4 w = carve4(pl, ws, sizeof(T));
-  const T *src = in;
+  Workspace4 w = carve4(pl, ws);
+  const double *src = nullptr;
   for (int s = 0; s < pl.nlev && cx.ok; ++s) {
-    const Level &L = pl.lev[s];
-    const Level &Lt = tp.lev[s];
-    const int64_t tm = Lt.m[2];
-    const bool cot = Lt.co[2];
-    const int64_t sm = L.m[0] * L.m[1] * L.m[2], cs = L.c[0] * L.c[1] * L.c[2];
-    T *next = (T *)w.buf[s % 2];
-    double *G = cot ? w.G : w.F;
-    const Map3 lmap = compact_map(L.m[1], L.m[2]);
-    const Map3 omap = (s == 0) ? lmap : nodal_map(L);
-    for (int64_t t = 0; t < tm && cx.ok; ++t) {
-      const bool tc = tcoarse(t, tm) || !cot;
-      LoadArgs<T> a{};
-      a.src = src + t * sm;
-      a.smap = lmap;
-      a.out = tc ? out + pl.tpos[s][t] * S0 : nullptr;
-      a.omap = tc ? omap : lmap;
-      a.F = G + t * cs;
-      launch_loadvec<T, T, true>(L, a, cx);
-    }
-    if (cot && cx.ok) launch_tload(w.G, Lt, w.F, cs, cx);
-    solve_all4<T>(w.F, L, Lt, Epi<T>{EPI_STORE_COMPACT, next, Map3{}}, cx);
-    if (cot && cx.ok) launch_tfine<T, true>(pl, L, Lt, src, out, src, omap, cx);
+    double *next = (double *)w.buf[s % 2];
+    if (s == 0) decompose4_level<T, T>(pl, s, in, out, next, w, cx);
+    else decompose4_level<T, double>(pl, s, src, out, next, w, cx);
     src = next;
   }
-  if (cx.ok) launch_nodal4<T, true>(pl, src, out, cx);
+  if (cx.ok) launch_nodal4<double, T, true>(pl, src, out, cx);
   return cx.ok;
 }
 
@@ -2233,9 +2242,9 @@ bool recompose4_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t str
     return true;
   }
   const Plan &tp = *pl.time;
-  Workspace4 w = carve4(pl, ws, sizeof(T));
+  Workspace4 w = carve4(pl, ws);
   T *V = (T *)w.buf[pl.nlev % 2];
-  launch_nodal4<T, false>(pl, in, V, cx);
+  launch_nodal4<T, T, false>(pl, in, V, cx);
   for (int s = pl.nlev - 1; s >= 0 && cx.ok; --s) {
     const Level &L = pl.lev[s];
     const Level &Lt = tp.lev[s];
@@ -2260,7 +2269,7 @@ bool recompose4_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t str
       const int64_t J = cot ? tcoarse_idx(t, tm, ct) : t;
       launch_reconstruct<T>(L, in + pl.tpos[s][t] * S0, cmap, V + J * cs, dst + t * sm, cx);
     }
-    if (cot && cx.ok) launch_tfine<T, false>(pl, L, Lt, in, dst, V, cmap, cx);
+    if (cot && cx.ok) launch_tfine<T, T, false>(pl, L, Lt, in, dst, V, cmap, cx);
     V = dst;
   }
   return cx.ok;

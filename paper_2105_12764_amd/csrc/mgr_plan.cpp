@@ -70,7 +70,8 @@ size_t workspace_bytes4(int64_t nt, const int64_t n[kDims], int nlev, size_t ele
   for (int k = 0; k < kDims; ++k) cs *= coarse_count(n[k]);
   const int64_t c4 = coarse_count(nt) * cs;
   auto al = [](size_t b) { return (b + 255) / 256 * 256; };
-  return 2 * al((size_t)c4 * elem_size) + al((size_t)c4 * sizeof(double)) + al((size_t)(nt * cs) * sizeof(double));
+  (void)elem_size;  // level grids in FP64, as in 3-D
+  return 3 * al((size_t)c4 * sizeof(double)) + al((size_t)(nt * cs) * sizeof(double));
 }
 
 size_t workspace_bytes(const int64_t n[kDims], int nlev, size_t elem_size) {

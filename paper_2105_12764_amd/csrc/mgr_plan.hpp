@@ -132,8 +132,8 @@ std::unique_ptr<Plan> build_plan4(int64_t nt, const int64_t n[kDims],
 // Three FP64 grids of level 1's size (two level grids, the load vector) and
 // (nlev >= 2) one FP64 grid of level 2's size; the same for FP32 fields.
 size_t workspace_bytes(const int64_t n[kDims], int nlev, size_t elem_size);
-// 4-D: two coarse grids in the field's type, the FP64 load/correction grid
-// and the FP64 per-slice load vectors (nt slices of the coarse space grid).
+// 4-D: two FP64 coarse level grids, the FP64 load/correction grid and the FP64
+// per-slice load vectors (nt slices of the coarse space grid).
 size_t workspace_bytes4(int64_t nt, const int64_t n[kDims], int nlev, size_t elem_size);
 
 }  // namespace mgr

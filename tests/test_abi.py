@@ -53,11 +53,11 @@ def test_workspace_size():
     assert mgr.workspace_size((513, 513, 513), np.float32, 1) == 3 * al(8 * n1)
     with pytest.raises(mgr.MgrError):
         mgr.workspace_size((513, 513, 513), np.float64, 10)
-    # 4-D: two coarse 4-D grids in the field's type, the FP64 coarse grid and
-    # the FP64 load vectors of every time slice
+    # 4-D: two FP64 coarse 4-D level grids, the FP64 coarse grid and the FP64
+    # load vectors of every time slice
     cs, ct = 201 ** 3, 9
     assert mgr.workspace_size((16, 401, 401, 401), np.float32, 8) == \
-        2 * al(4 * ct * cs) + al(8 * ct * cs) + al(8 * 16 * cs)
+        3 * al(8 * ct * cs) + al(8 * 16 * cs)
     assert mgr.workspace_size((16, 401, 401, 401), np.float32, 0) == 0
     with pytest.raises(mgr.MgrError):
         mgr.workspace_size((16, 401, 401, 401), np.float32, 10)

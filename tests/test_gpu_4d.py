@@ -90,3 +90,35 @@ def test_4d_large_round_trip():
     err = float((r - x).abs().max() / x.abs().max())
     print(f"  round trip {err:.2e}", flush=True)
     assert err <= 1e-12
+
+
+def test_4d_fp32_smooth_field_within_tolerance():
+    """FP32 4-D field, smooth and noise-free (a coefficient is the small
+    difference of nearly equal values): relative L2 against the FP64 oracle
+    within 1e-5 overall and in every coefficient class, so neither the
+    coefficient arithmetic nor the coarser level grids may round at the
+    field's scale."""
+    from test_gpu_parity import _drop_level
+
+    n = 33
+    shape = (n, n, n, n)
+    nlev = mgr.max_levels(shape)
+    print(f"\n[case] 4-D smooth field {shape} float32, {nlev} levels", flush=True)
+    x = np.linspace(0.0, 1.0, n)
+    u = (np.cos(np.pi * x)[:, None, None, None] * np.sin(2 * np.pi * x)[None, :, None, None]
+         * np.cos(2 * np.pi * x)[None, None, :, None] * np.sin(np.pi * x)[None, None, None, :]
+         + 2.0).astype(np.float32)
+    d = mgr.decompose(torch.from_numpy(u).cuda(), None, nlev)
+    torch.cuda.synchronize()
+    ref = oracle.decompose(u.astype(np.float64), None, nlev)
+    diff = d.cpu().numpy().astype(np.float64) - ref
+    l2 = float(np.linalg.norm(diff) / np.linalg.norm(ref))
+    print(f"  all: L2 {l2:.2e}", flush=True)
+    assert l2 <= 1e-5
+    lv = _drop_level(n, nlev)
+    cls = np.minimum.outer(np.minimum.outer(np.minimum.outer(lv, lv), lv), lv)
+    for c in range(nlev + 1):
+        m = cls == c
+        e = float(np.linalg.norm(diff[m]) / np.linalg.norm(ref[m]))
+        print(f"  class {c}: L2 {e:.2e} of the class", flush=True)
+        assert e <= 1e-5, (c, e)
