@@ -307,7 +307,8 @@ const char *mgr_service_last_error(void);
  * byte and no arithmetic -- the "achievable single-pass" bandwidth probe the
  * paper divides by to place its throughput (Sec. IV-D), and a kernel of known
  * traffic for calibrating hardware byte counters.  Buffers must not
- * overlap; MGR_ERR_INVALID_ARG otherwise.  Enqueued on `stream`. */
+ * overlap; MGR_ERR_INVALID_ARG otherwise.  At most 64 GiB (one launch);
+ * MGR_ERR_DEVICE beyond.  Enqueued on `stream`. */
 mgr_status mgr_probe_copy(const void *src, void *dst, size_t bytes, void *stream);
 
 /* Turn event recording on (on != 0) or off.  Always MGR_OK. */
