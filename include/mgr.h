@@ -112,7 +112,9 @@ mgr_status mgr_decompose(int ndim, const int64_t *shape,
  * joined back before the finest level's last kernels, so the call stays
  * ordered on `stream` and capturable in a HIP graph; the helper stream of a
  * (device, stream) pair is created by its first call, so make one call
- * before capturing. */
+ * before capturing.  Helper streams are kept for at most 64 such pairs per
+ * process; calls from further pairs, and 4-D fields, run serially on
+ * `stream`. */
 mgr_status mgr_recompose(int ndim, const int64_t *shape,
                          const double *const *coords, mgr_dtype dtype,
                          int nlevels, const void *in, void *out,

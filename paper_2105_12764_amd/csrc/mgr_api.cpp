@@ -215,9 +215,12 @@ struct Helper {
 };
 std::mutex g_hmu;
 std::list<Helper> g_helpers;  // stable addresses
+// Helpers kept at most: a caller that passes ever new streams gets serial
+// recompositions beyond this rather than one more stream per call.
+constexpr size_t kHelpersMax = 64;
 
 // The helper of `caller` on the current device, or nullptr (then the call
-// runs serially) when it cannot be created.
+// runs serially) when it cannot be created or the registry is full.
 Helper *helper_for(hipStream_t caller) {
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess) {
@@ -227,6 +230,7 @@ Helper *helper_for(hipStream_t caller) {
   std::lock_guard<std::mutex> lk(g_hmu);
   for (auto &h : g_helpers)
     if (h.device == dev && h.caller == caller) return &h;
+  if (g_helpers.size() >= kHelpersMax) return nullptr;
   hipStream_t s = nullptr;
   hipEvent_t f = nullptr, j = nullptr;
   bool ok = hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess;

@@ -4,8 +4,9 @@ A recomposition with two or more levels runs its finest level's load vector
 and first solves on a library-owned helper stream forked from the caller's
 stream.  It must stay ordered on the caller's stream (it sees the writes
 before it, the work after it sees its result), give the same bits as the
-serial order (the batched path runs it serially), and replay correctly from a
-HIP graph.
+serial order (the batched path runs it serially), replay correctly from a
+HIP graph, and fall back to the serial order once the library holds helper
+streams for 64 caller streams.
 """
 import numpy as np
 import pytest
@@ -94,3 +95,43 @@ def test_recompose_replays_from_a_graph():
         assert torch.equal(out, ref), f"replay {rep}"
     e = float((out - x).abs().max() / x.abs().max())
     assert e <= 1e-12
+
+
+class _RawStream:
+    """A caller stream created through the HIP runtime (not torch's pool)."""
+
+    def __init__(self, handle):
+        self.cuda_stream = handle
+
+
+def test_recompose_from_more_caller_streams_than_helpers():
+    """The library keeps helper streams for at most 64 (device, caller stream)
+    pairs; recompositions from further caller streams run serially on the
+    caller's stream and give the same bits as the forked ones."""
+    import ctypes
+
+    hip = ctypes.CDLL("libamdhip64.so.7")  # the runtime the library is linked against
+    shape, nlev = (65, 65, 65), 5
+    print(f"\n[case] recompose {shape} from 72 caller streams", flush=True)
+    u, coords = make_input(shape, 94, nonuniform=True)
+    x = torch.from_numpy(u).cuda()
+    d = mgr.decompose(x, coords, nlev)
+    ws = mgr.alloc_workspace(shape, x.dtype, nlev)
+    ref = mgr.recompose(d, coords, nlev, workspace=ws)
+    out = torch.empty_like(x)
+    torch.cuda.synchronize()
+    streams = []
+    try:
+        for i in range(72):
+            h = ctypes.c_void_p()
+            assert hip.hipStreamCreateWithFlags(ctypes.byref(h), ctypes.c_uint(1)) == 0
+            streams.append(h)
+            out.fill_(-1.0)
+            torch.cuda.synchronize()
+            mgr.recompose(d, coords, nlev, out=out, workspace=ws, stream=_RawStream(h.value))
+            assert hip.hipStreamSynchronize(h) == 0
+            assert torch.equal(out, ref), f"caller stream {i}"
+    finally:
+        torch.cuda.synchronize()
+        for h in streams:
+            hip.hipStreamDestroy(h)
