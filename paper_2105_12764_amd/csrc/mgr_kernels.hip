@@ -78,9 +78,15 @@ __device__ __forceinline__ int64_t coarse_idx(int64_t g, int64_t m, int64_t c) {
 
 // ------------------------------------------------------- load-vector kernel
 
-constexpr int TJ = 16;       // coarse rows (dim 1) per tile
-constexpr int TK = 32;       // coarse columns (dim 2) per tile
-constexpr int NTHR = TJ * TK;
+// Coarse rows (dim 1) per tile, by the field's type: 16 for FP64 fields;
+// 8 for FP32 fields, whose kernels wait on latency more than on bandwidth
+// and gain more from a third resident workgroup per CU (256 threads each)
+// than the taller tile saves in halo rows (measured both ways at 513^3).
+template <typename T>
+constexpr int kTJ = sizeof(T) == 4 ? 8 : 16;
+constexpr int TK = 32;  // coarse columns (dim 2) per tile
+template <typename T>
+constexpr int kNTHR = kTJ<T> * TK;
 #define LV_WAVES (DEC ? (sizeof(TS) == 4 ? 4 : 1) : 5)
 #define LV_MAXP 128
 
@@ -129,12 +135,13 @@ __device__ __forceinline__ int xcd_tile(int bid, int nb) {
 // Recomposition stages the stored coefficients (zero at the coarse nodes)
 // and forms f = (P^T M)^{(x)3} C the same way.
 template <typename T, typename TS, bool DEC, bool NODAL, bool CO0, bool CO1, bool CO2>
-__global__ void __launch_bounds__(NTHR, LV_WAVES) k_loadvec(LoadArgs<T, TS> a) {
+__global__ void __launch_bounds__(kNTHR<T>, LV_WAVES) k_loadvec(LoadArgs<T, TS> a) {
   // a decomposition forms its coefficients as differences of nearly equal
   // values, so it computes in FP64 whatever the storage type
   using A = std::conditional_t<DEC, double, Acc<T>>;
   // staged planes hold the loaded values, exact in the source type
   using P = TS;
+  constexpr int TJ = kTJ<T>, NTHR = kNTHR<T>;
   constexpr int SJ = CO1 ? 2 : 1, HJ = CO1 ? 2 : 0;
   constexpr int SK = CO2 ? 2 : 1, HK = CO2 ? 2 : 0;
   constexpr int NJ = SJ * (TJ - 1) + 1 + 2 * HJ;
@@ -1585,7 +1592,7 @@ int64_t pick_chunk(int64_t c0, int64_t tiles, int64_t slots, int halo, int64_t m
 
 template <typename T, typename TS, bool DEC, bool NODAL, bool C0, bool C1, bool C2>
 void launch_loadvec_t(LoadArgs<T, TS> a, Ctx &cx) {
-  static const int slots = resident_slots((const void *)k_loadvec<T, TS, DEC, NODAL, C0, C1, C2>, NTHR);
+  static const int slots = resident_slots((const void *)k_loadvec<T, TS, DEC, NODAL, C0, C1, C2>, kNTHR<T>);
   const int64_t tiles = (int64_t)a.gx * a.gy;
   // chunks short enough for the kernel's LDS plane window (2 TI + 3 planes)
   const int64_t maxti = (LV_MAXP - 3) / 2;
@@ -1610,7 +1617,7 @@ void launch_loadvec_t(LoadArgs<T, TS> a, Ctx &cx) {
                  std::string("k_loadvec<") + tname<T>() + ", " + tname<TS>() + ", " + bname(DEC) + ", " +
                      bname(NODAL) + ", " + bname(C0) + ", " + bname(C1) + ", " + bname(C2) + ">",
                  bytes);
-  hipLaunchKernelGGL((k_loadvec<T, TS, DEC, NODAL, C0, C1, C2>), grid, dim3(NTHR), 0, cx.stream, a);
+  hipLaunchKernelGGL((k_loadvec<T, TS, DEC, NODAL, C0, C1, C2>), grid, dim3(kNTHR<T>), 0, cx.stream, a);
 }
 
 // Suffix of a solve's timing label naming what its store does (the kernel
@@ -1639,7 +1646,7 @@ void launch_loadvec(const Level &L, LoadArgs<T, TS> a, Ctx &cx) {
   a.r0 = L.d[0].r; a.r1 = L.d[1].r; a.r2 = L.d[2].r;
   a.W0 = L.d[0].W; a.W1 = L.d[1].W; a.W2 = L.d[2].W;
   a.gx = (int)((a.c2 + TK - 1) / TK);
-  a.gy = (int)((a.c1 + TJ - 1) / TJ);
+  a.gy = (int)((a.c1 + kTJ<T> - 1) / kTJ<T>);
   const int key = (L.co[0] ? 4 : 0) | (L.co[1] ? 2 : 0) | (L.co[2] ? 1 : 0);
   // on coarser levels the field-side array (decompose: out; recompose: src)
   // goes through the nodal tables
@@ -2383,7 +2390,7 @@ bool autotune_t(Plan &pl, const T *in, T *out, void *ws, hipStream_t stream, std
   for (int s = 0; s < nt && cx.ok; ++s) {
     const Level &L = pl.lev[s];
     const double nl = (double)L.m[0] * L.m[1] * L.m[2];
-    const int64_t tiles_lv = ((L.c[2] + TK - 1) / TK) * ((L.c[1] + TJ - 1) / TJ);
+    const int64_t tiles_lv = ((L.c[2] + TK - 1) / TK) * ((L.c[1] + kTJ<T> - 1) / kTJ<T>);
     const int halo_lv = L.co[0] ? 2 : 0;
     for (int dec = 1; dec >= 0 && cx.ok; --dec) {
       // level s's load vector as the decomposition (FP64 level grid from
