@@ -78,15 +78,24 @@ __device__ __forceinline__ int64_t coarse_idx(int64_t g, int64_t m, int64_t c) {
 
 // ------------------------------------------------------- load-vector kernel
 
-// Coarse rows (dim 1) per tile, by the field's type: 16 for FP64 fields;
-// 8 for FP32 fields, whose kernels wait on latency more than on bandwidth
-// and gain more from a third resident workgroup per CU (256 threads each)
-// than the taller tile saves in halo rows (measured both ways at 513^3).
-template <typename T>
-constexpr int kTJ = sizeof(T) == 4 ? 8 : 16;
+// Coarse rows (dim 1) per tile (each measured at 513^3).  FP32 fields: 8;
+// their kernels wait on latency more than on bandwidth and gain more from a
+// third resident workgroup per CU (256 threads each) than a taller tile
+// saves in halo rows.  FP64 fields: 24 for the finest level's decomposition
+// (768 threads, three waves per SIMD at its register count, fewer halo rows),
+// 16 elsewhere (the taller tile is slower in the recomposition kernels and
+// on the nodal levels).
+template <typename T, bool DEC, bool NODAL>
+constexpr int kTJ = sizeof(T) == 4 ? 8 : (DEC && !NODAL ? 24 : 16);
 constexpr int TK = 32;  // coarse columns (dim 2) per tile
+template <typename T, bool DEC, bool NODAL>
+constexpr int kNTHR = kTJ<T, DEC, NODAL> * TK;
+// kTJ for a choice made at run time
 template <typename T>
-constexpr int kNTHR = kTJ<T> * TK;
+int tile_rows(bool dec, bool nodal) {
+  return dec ? (nodal ? kTJ<T, true, true> : kTJ<T, true, false>)
+             : (nodal ? kTJ<T, false, true> : kTJ<T, false, false>);
+}
 #define LV_WAVES (DEC ? (sizeof(TS) == 4 ? 4 : 1) : 5)
 #define LV_MAXP 128
 
@@ -135,13 +144,13 @@ __device__ __forceinline__ int xcd_tile(int bid, int nb) {
 // Recomposition stages the stored coefficients (zero at the coarse nodes)
 // and forms f = (P^T M)^{(x)3} C the same way.
 template <typename T, typename TS, bool DEC, bool NODAL, bool CO0, bool CO1, bool CO2>
-__global__ void __launch_bounds__(kNTHR<T>, LV_WAVES) k_loadvec(LoadArgs<T, TS> a) {
+__global__ void __launch_bounds__((kNTHR<T, DEC, NODAL>), LV_WAVES) k_loadvec(LoadArgs<T, TS> a) {
   // a decomposition forms its coefficients as differences of nearly equal
   // values, so it computes in FP64 whatever the storage type
   using A = std::conditional_t<DEC, double, Acc<T>>;
   // staged planes hold the loaded values, exact in the source type
   using P = TS;
-  constexpr int TJ = kTJ<T>, NTHR = kNTHR<T>;
+  constexpr int TJ = kTJ<T, DEC, NODAL>, NTHR = kNTHR<T, DEC, NODAL>;
   constexpr int SJ = CO1 ? 2 : 1, HJ = CO1 ? 2 : 0;
   constexpr int SK = CO2 ? 2 : 1, HK = CO2 ? 2 : 0;
   constexpr int NJ = SJ * (TJ - 1) + 1 + 2 * HJ;
@@ -1592,7 +1601,9 @@ int64_t pick_chunk(int64_t c0, int64_t tiles, int64_t slots, int halo, int64_t m
 
 template <typename T, typename TS, bool DEC, bool NODAL, bool C0, bool C1, bool C2>
 void launch_loadvec_t(LoadArgs<T, TS> a, Ctx &cx) {
-  static const int slots = resident_slots((const void *)k_loadvec<T, TS, DEC, NODAL, C0, C1, C2>, kNTHR<T>);
+  static const int slots =
+      resident_slots((const void *)k_loadvec<T, TS, DEC, NODAL, C0, C1, C2>, kNTHR<T, DEC, NODAL>);
+  a.gy = (int)((a.c1 + kTJ<T, DEC, NODAL> - 1) / kTJ<T, DEC, NODAL>);
   const int64_t tiles = (int64_t)a.gx * a.gy;
   // chunks short enough for the kernel's LDS plane window (2 TI + 3 planes)
   const int64_t maxti = (LV_MAXP - 3) / 2;
@@ -1617,7 +1628,8 @@ void launch_loadvec_t(LoadArgs<T, TS> a, Ctx &cx) {
                  std::string("k_loadvec<") + tname<T>() + ", " + tname<TS>() + ", " + bname(DEC) + ", " +
                      bname(NODAL) + ", " + bname(C0) + ", " + bname(C1) + ", " + bname(C2) + ">",
                  bytes);
-  hipLaunchKernelGGL((k_loadvec<T, TS, DEC, NODAL, C0, C1, C2>), grid, dim3(kNTHR<T>), 0, cx.stream, a);
+  hipLaunchKernelGGL((k_loadvec<T, TS, DEC, NODAL, C0, C1, C2>), grid, dim3(kNTHR<T, DEC, NODAL>), 0, cx.stream,
+                     a);
 }
 
 // Suffix of a solve's timing label naming what its store does (the kernel
@@ -1645,8 +1657,7 @@ void launch_loadvec(const Level &L, LoadArgs<T, TS> a, Ctx &cx) {
   a.c0 = L.c[0]; a.c1 = L.c[1]; a.c2 = L.c[2];
   a.r0 = L.d[0].r; a.r1 = L.d[1].r; a.r2 = L.d[2].r;
   a.W0 = L.d[0].W; a.W1 = L.d[1].W; a.W2 = L.d[2].W;
-  a.gx = (int)((a.c2 + TK - 1) / TK);
-  a.gy = (int)((a.c1 + kTJ<T> - 1) / kTJ<T>);
+  a.gx = (int)((a.c2 + TK - 1) / TK);  // a.gy: by the kernel's tile, in launch_loadvec_t
   const int key = (L.co[0] ? 4 : 0) | (L.co[1] ? 2 : 0) | (L.co[2] ? 1 : 0);
   // on coarser levels the field-side array (decompose: out; recompose: src)
   // goes through the nodal tables
@@ -2390,9 +2401,10 @@ bool autotune_t(Plan &pl, const T *in, T *out, void *ws, hipStream_t stream, std
   for (int s = 0; s < nt && cx.ok; ++s) {
     const Level &L = pl.lev[s];
     const double nl = (double)L.m[0] * L.m[1] * L.m[2];
-    const int64_t tiles_lv = ((L.c[2] + TK - 1) / TK) * ((L.c[1] + kTJ<T> - 1) / kTJ<T>);
     const int halo_lv = L.co[0] ? 2 : 0;
     for (int dec = 1; dec >= 0 && cx.ok; --dec) {
+      const int tj = tile_rows<T>(dec != 0, s > 0);  // the field-side array is nodal below level 0
+      const int64_t tiles_lv = ((L.c[2] + TK - 1) / TK) * ((L.c[1] + tj - 1) / tj);
       // level s's load vector as the decomposition (FP64 level grid from
       // level 1 on) or the recomposition launches it
       auto lv = [&]() {
