@@ -1745,7 +1745,11 @@ void launch_long(double *F, const Level &L, int axis, const Epi<T> &ep, Ctx &cx)
 template <typename T>
 void launch_solve(double *F, const Level &L, int axis, const Epi<T> &ep, Ctx &cx) {
   const DimTabs &d = L.d[axis];
-  if (d.P > kMaxBlocks) {
+  if (d.P > kMaxBlocks || (d.S == 64 && axis != 2)) {
+    // Strided lines of 64-position partitions go to the long-line solver as
+    // well: beside a workgroup of up to 1024 threads a register partition of
+    // 64 doubles does not fit and would spill whole (measured 1.8x slower
+    // than the long-line solver's second pass over the line).
     launch_long<T>(F, L, axis, ep, cx);
   } else if (d.S == 0) {  // the plan chose one sequential partition (tables built for it)
     const int64_t nlines = L.c[0] * L.c[1] * L.c[2] / L.c[axis];
@@ -1761,11 +1765,10 @@ void launch_solve(double *F, const Level &L, int axis, const Epi<T> &ep, Ctx &cx
       default: launch_rows_s<T, 64>(F, L, ep, cx); break;
     }
   } else {
-    switch (d.S) {
+    switch (d.S) {  // 8, 16 or 32 here
       case 8: launch_strided_s<T, 8>(F, L, axis, ep, cx); break;
       case 16: launch_strided_s<T, 16>(F, L, axis, ep, cx); break;
-      case 32: launch_strided_s<T, 32>(F, L, axis, ep, cx); break;
-      default: launch_strided_s<T, 64>(F, L, axis, ep, cx); break;
+      default: launch_strided_s<T, 32>(F, L, axis, ep, cx); break;
     }
   }
   cx.check("correction solve launch");

@@ -91,7 +91,9 @@ SMALL = [
     ((2049, 9), 1, False, np.float64),          # 1025 unknowns: 17 partitions of 64
     ((2100,), 2, True, np.float32),             # 1-D long line, FP32
     ((2500, 3, 4), 2, True, np.float64),        # long dim-0 lines in 3-D
-    ((1500, 30), 2, True, np.float64),          # 64-partition strided solve
+    ((1500, 30), 2, True, np.float64),          # 64-partition strided lines: long-line solver
+    ((9, 1100, 20), 2, True, np.float32),       # the same along dim 1, FP32
+    ((1030, 6, 40), 3, False, np.float64),      # dim 0 of 515: nine partitions of 64
     ((30, 1500), 2, True, np.float64),          # 64-partition row solve
     ((129, 129, 129), None, True, np.float64),
     ((65, 65, 65), 5, False, np.float32),
