@@ -157,6 +157,7 @@ __global__ void __launch_bounds__((kNTHR<T, DEC, NODAL>), LV_WAVES) k_loadvec(Lo
   constexpr int NK = SK * (TK - 1) + 1 + 2 * HK;
   constexpr int NE = NJ * NK;
   constexpr int EPT = (NE + NTHR - 1) / NTHR;  // tile elements per thread
+  static_assert(EPT <= 8, "the per-thread flags hold 4 bits for each of at most 8 tile elements");
   constexpr int NG = NJ * TK;                  // dim-2 reduced rows of one plane
   __shared__ P sA[NE];      // plane b (coarse along dim 0)
   __shared__ P sB[NE];      // plane a (fine along dim 0)
