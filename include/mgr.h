@@ -47,7 +47,7 @@ extern "C" {
 typedef enum {
   MGR_OK = 0,
   MGR_ERR_INVALID_ARG = 1,   /* bad ndim/shape/coords/nlevels/pointer/overlap */
-  MGR_ERR_UNSUPPORTED = 2,   /* valid request this build does not handle */
+  MGR_ERR_UNSUPPORTED = 2,   /* valid request the library does not handle */
   MGR_ERR_WORKSPACE = 3,     /* workspace NULL or smaller than required */
   MGR_ERR_OUT_OF_MEMORY = 4, /* plan tables could not be allocated */
   MGR_ERR_DEVICE = 5         /* a HIP call or kernel launch failed */
