@@ -86,7 +86,13 @@ def _log(msg: str) -> None:
 
 
 def run_gpu(name: str, steps: int, warmup: int, graph_steps: int = 0, tune: bool = True,
-            progressive_on: bool = True):
+            progressive_on: bool = True, keep_output: bool = False):
+    """One workload: warm-up, autotuning, the timed steps (events at the
+    decompose/recompose boundaries), the same steps with per-launch events
+    (per-kernel totals and the roofline), optional graph replay and the
+    partial recompositions.  With keep_output, the host copy of the GPU's
+    decomposition of the input is returned too (for the errors against the
+    oracle, computed in the CPU-baseline leg)."""
     import torch
 
     from paper_2105_12764_amd import mgr
@@ -186,6 +192,9 @@ def run_gpu(name: str, steps: int, warmup: int, graph_steps: int = 0, tune: bool
         _log(f"[bench] {name}: graph replay {gms:.3f} ms/step")
 
     rt_err = float((r.double() - x.double()).abs().max() / x.double().abs().max())
+    mgr.decompose(x, coords, nlev, out=d, workspace=ws, stream=stream)
+    torch.cuda.synchronize()
+    dec_host = d.cpu().numpy() if keep_output else None
 
     # progressive recomposition: error and time with the nkeep coarsest classes
     progressive = []
@@ -241,7 +250,7 @@ def run_gpu(name: str, steps: int, warmup: int, graph_steps: int = 0, tune: bool
     }
     del x, d, r, ws
     torch.cuda.empty_cache()
-    return res, u, coords, nlev
+    return res, u, coords, nlev, dec_host
 
 
 def _pct(v, q):
@@ -342,44 +351,108 @@ def run_batched(reps: int = 10, warmup: int = 2, nfields: int = 64):
     return res
 
 
-def run_service(nreq: int = 300, rates=(50, 100, 200, 500, 1000, 2000), budget_gb: float = 64.0,
-                nstreams: int = 4, pool: int = 4, tight_gb: float = 4.0):
-    """The refactoring service (mgr_service_*) under Poisson arrivals.
-
-    Requests come from synth.service_requests (3-D cubes, side log-uniform
-    over [17, 513], FP32:FP64 = 3:1, decompose:recompose = 1:1, seed 5000).
-    Every (side, dtype) has one seeded input field and `pool` output buffers
-    used in turn (a buffer is reused only after its previous request is done).
-    Latency is submit -> completion seen by the service's waiter thread.
-    Also timed: the plain path (the same requests back to back, one call per
-    request on one stream) and the service with every request submitted at
-    once, under the stated budget and under a tight one."""
+def run_latency(name: str = "cube65_f64", reps: int = 100, warmup: int = 10):
+    """Latency of one small workload (65^3 FP64, 5 levels: launch-bound):
+    per repetition the device time of the decomposition and of the
+    recomposition (HIP events on the stream) and the host wall time of the
+    whole step (both calls, then a stream synchronisation); medians in
+    microseconds."""
     import torch
 
     from paper_2105_12764_amd import mgr
-    from paper_2105_12764_amd.synth import SERVICE_SIDES, service_requests
+    from paper_2105_12764_amd.synth import WORKLOADS, make_input
+
+    shape, seed, nonuni, dtype, nlev = WORKLOADS[name]
+    u, coords = make_input(shape, seed, nonuniform=nonuni, dtype=dtype)
+    dev = torch.device("cuda:0")
+    x = torch.from_numpy(u).to(dev)
+    d, r = torch.empty_like(x), torch.empty_like(x)
+    ws = mgr.alloc_workspace(shape, x.dtype, nlev, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    for _ in range(warmup):
+        mgr.decompose(x, coords, nlev, out=d, workspace=ws, stream=stream)
+        mgr.recompose(d, coords, nlev, out=r, workspace=ws, stream=stream)
+    torch.cuda.synchronize()
+    t_dec, t_rec, wall = [], [], []
+    for _ in range(reps):
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        h0 = time.perf_counter()
+        e0.record(stream)
+        mgr.decompose(x, coords, nlev, out=d, workspace=ws, stream=stream)
+        e1.record(stream)
+        mgr.recompose(d, coords, nlev, out=r, workspace=ws, stream=stream)
+        e2.record(stream)
+        stream.synchronize()
+        wall.append((time.perf_counter() - h0) * 1e6)
+        t_dec.append(e0.elapsed_time(e1) * 1e3)
+        t_rec.append(e1.elapsed_time(e2) * 1e3)
+    err = float((r - x).abs().max() / x.abs().max())
+    both = [a + b for a, b in zip(t_dec, t_rec)]
+    res = {"workload": f"{name}: {'x'.join(map(str, shape))} {np.dtype(dtype).name}, {nlev} levels",
+           "reps": reps, "decompose_us_p50": round(_pct(t_dec, 0.5), 1),
+           "recompose_us_p50": round(_pct(t_rec, 0.5), 1), "device_step_us_p50": round(_pct(both, 0.5), 1),
+           "device_step_us_p99": round(_pct(both, 0.99), 1), "host_wall_step_us_p50": round(_pct(wall, 0.5), 1),
+           "host_wall_step_us_p99": round(_pct(wall, 0.99), 1),
+           "GBps_at_p50": round(2.0 * x.numel() * x.element_size() / (_pct(both, 0.5) * 1e-6) / 1e9, 1),
+           "roundtrip_max_rel_err": err}
+    _log(f"[bench] latency {name}: device {res['device_step_us_p50']} us, host wall {res['host_wall_step_us_p50']} us")
+    del x, d, r, ws
+    torch.cuda.empty_cache()
+    return res
+
+
+def run_service(nreq: int = 5000, rates=(50, 100, 200, 500, 1000, 2000, 4000, 8000, 16000),
+                max_secs: float = 10.0, budget_gb: float = 64.0, nstreams: int = 4, slots: int = 32,
+                tight_gb: float = 4.0):
+    """The refactoring service (mgr_service_*) under Poisson arrivals.
+
+    Requests come from synth.service_requests (3-D cubes, integer side
+    log-uniform over [17, 513], FP32:FP64 = 3:1, decompose:recompose = 1:1,
+    seed 5000).  A request's input is the leading side^3 elements of one
+    seeded random pool per dtype (time does not depend on values); its output
+    is one of `slots` buffers sized for the largest request, used in turn (a
+    buffer is reused only after its previous request is done).  Latency is
+    submit -> completion seen by the service's waiter thread.  Also timed:
+    the plain path (the requests back to back, one call per request on one
+    stream) and the service with every request submitted at once, under the
+    stated budget and under a tight one.  Each Poisson rate serves the first
+    min(nreq, rate x max_secs) requests of the stream."""
+    import torch
+
+    from paper_2105_12764_amd import mgr
+    from paper_2105_12764_amd.synth import SERVICE_SIDE_MAX, service_requests
 
     dev = torch.device("cuda:0")
     reqs = service_requests(nreq)
     gen = torch.Generator(device=dev)
     gen.manual_seed(5000)
-    fields, outs = {}, {}
-    for side in SERVICE_SIDES:
-        for dt in (torch.float32, torch.float64):
-            fields[(side, dt)] = torch.randn((side,) * 3, dtype=dt, device=dev, generator=gen)
-            outs[(side, dt)] = [torch.empty((side,) * 3, dtype=dt, device=dev) for _ in range(pool)]
+    nmax = SERVICE_SIDE_MAX ** 3
+    pool = {dt: torch.randn(nmax, dtype=dt, device=dev, generator=gen) for dt in (torch.float32, torch.float64)}
+    outbuf = [torch.empty(nmax * 8, dtype=torch.uint8, device=dev) for _ in range(slots)]
     tdt = [torch.float32 if r[1] == np.float32 else torch.float64 for r in reqs]
-    nbytes = sum(2 * fields[(r[0], d)].numel() * fields[(r[0], d)].element_size() for r, d in zip(reqs, tdt))
+
+    def io(i):
+        side, dt = reqs[i][0], tdt[i]
+        n = side ** 3
+        esz = 4 if dt == torch.float32 else 8
+        return (pool[dt][:n].view(side, side, side),
+                outbuf[i % slots][:n * esz].view(dt).view(side, side, side))
+
+    def nbytes_of(k):
+        return sum(2 * (reqs[i][0] ** 3) * (4 if tdt[i] == torch.float32 else 8) for i in range(k))
+
     stream = torch.cuda.current_stream(dev)
-    ws = torch.empty(mgr.workspace_size((513,) * 3, torch.float64, mgr.max_levels((513,) * 3)) + 1,
-                     dtype=torch.uint8, device=dev)
+    ws = torch.empty(mgr.workspace_size((SERVICE_SIDE_MAX,) * 3, torch.float64,
+                                        mgr.max_levels((SERVICE_SIDE_MAX,) * 3)) + 1, dtype=torch.uint8, device=dev)
 
     def plain():
-        for i, (r, d) in enumerate(zip(reqs, tdt)):
-            x, y = fields[(r[0], d)], outs[(r[0], d)][i % pool]
+        for i, r in enumerate(reqs):
+            x, y = io(i)
             (mgr.recompose if r[2] else mgr.decompose)(x, None, None, out=y, workspace=ws, stream=stream)
 
-    _log(f"[bench] service: {nreq} requests, {nbytes / 1e9:.2f} GB moved per pass")
+    nbytes = nbytes_of(nreq)
+    _log(f"[bench] service: {nreq} requests, {len({r[0] for r in reqs})} distinct sides, "
+         f"{nbytes / 1e9:.1f} GB moved per pass")
     plain()  # builds every plan
     torch.cuda.synchronize()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -389,13 +462,14 @@ def run_service(nreq: int = 300, rates=(50, 100, 200, 500, 1000, 2000), budget_g
     b.synchronize()
     t_plain = a.elapsed_time(b)
 
-    def serve(rate, budget):
+    def serve(rate, budget, k):
         svc = mgr.Service(int(budget), nstreams=nstreams)
         last = {}
         tickets, t_sub, lags = [], [], []
         t0 = time.perf_counter()
         t_arr = 0.0
-        for i, (r, d) in enumerate(zip(reqs, tdt)):
+        for i in range(k):
+            r = reqs[i]
             if rate:
                 t_arr += r[3] / rate
                 while True:
@@ -404,50 +478,56 @@ def run_service(nreq: int = 300, rates=(50, 100, 200, 500, 1000, 2000), budget_g
                         break
                     if wait > 2e-4:
                         time.sleep(wait - 1e-4)
-            key, slot = (r[0], d), i % pool
-            prev = last.get((key, slot))
+            slot = i % slots
+            prev = last.get(slot)
             while prev is not None and not svc.result(prev)[0]:
                 time.sleep(5e-5)  # that output buffer's previous request is still running
             ts = time.perf_counter()
             lags.append(ts - (t0 + t_arr) if rate else 0.0)
-            t = svc.submit(bool(r[2]), fields[key], outs[key][slot], None, None)
-            last[(key, slot)] = t
+            x, y = io(i)
+            t = svc.submit(bool(r[2]), x, y, None, None)
+            last[slot] = t
             tickets.append(t)
             t_sub.append(ts)
         svc.wait_all()
         res = [svc.result(t) for t in tickets]
         svc.close()
-        bad = sum(1 for r in res if not r[0] or r[1] != mgr.MGR_OK)
-        lat = [r[3] for r in res]
-        que = [r[2] for r in res]
-        span = max(ts + r[3] * 1e-3 for ts, r in zip(t_sub, res)) - min(t_sub)
-        out = {"latency_ms": {"p50": round(_pct(lat, 0.5), 4), "p99": round(_pct(lat, 0.99), 4),
-                              "max": round(max(lat), 4)},
+        bad = sum(1 for q in res if not q[0] or q[1] != mgr.MGR_OK)
+        lat = [q[3] for q in res]
+        que = [q[2] for q in res]
+        span = max(ts + q[3] * 1e-3 for ts, q in zip(t_sub, res)) - min(t_sub)
+        nb = nbytes_of(k)
+        out = {"requests": k, "latency_ms": {"p50": round(_pct(lat, 0.5), 4), "p99": round(_pct(lat, 0.99), 4),
+                                             "max": round(max(lat), 4)},
                "queue_ms": {"p50": round(_pct(que, 0.5), 4), "p99": round(_pct(que, 0.99), 4)},
-               "GBps": round(nbytes / span / 1e9, 1), "span_s": round(span, 4), "failed": bad}
+               "GBps": round(nb / span / 1e9, 1), "span_s": round(span, 4), "failed": bad}
         if rate:
-            out["offered_GBps"] = round(nbytes * rate / sum(r[3] for r in reqs) / 1e9, 1)
+            out["offered_GBps"] = round(nb * rate / sum(reqs[i][3] for i in range(k)) / 1e9, 1)
             out["arrival_lag_ms_p99"] = round(1e3 * _pct(lags, 0.99), 4)
         return out
 
     budget = budget_gb * 1e9
-    sat = serve(None, budget)
+    sat = serve(None, budget, nreq)
     _log(f"[bench] service: plain path {nbytes / (t_plain * 1e-3) / 1e9:.1f} GB/s, service all-at-once "
          f"{sat['GBps']} GB/s, p99 {sat['latency_ms']['p99']} ms")
-    tight = serve(None, tight_gb * 1e9)
+    tight = serve(None, tight_gb * 1e9, nreq)
     per_rate = {}
     for rate in rates:
-        per_rate[str(rate)] = serve(rate, budget)
-        _log(f"[bench] service: {rate}/s p50 {per_rate[str(rate)]['latency_ms']['p50']} ms, "
-             f"p99 {per_rate[str(rate)]['latency_ms']['p99']} ms")
+        k = int(min(nreq, max(50, rate * max_secs)))
+        per_rate[str(rate)] = serve(rate, budget, k)
+        _log(f"[bench] service: {rate}/s x {k}: p50 {per_rate[str(rate)]['latency_ms']['p50']} ms, "
+             f"p99 {per_rate[str(rate)]['latency_ms']['p99']} ms, {per_rate[str(rate)]['GBps']} GB/s")
     res = {"requests": nreq, "seed": 5000,
-           "mix": "3-D cubes, side log-uniform over [17, 513] (11 geometric sides), FP32:FP64 = 3:1, "
+           "mix": "3-D cubes, integer side log-uniform over [17, 513], FP32:FP64 = 3:1, "
                   "decompose:recompose = 1:1, all levels, built-in launch shapes",
-           "bytes_per_pass": nbytes, "budget_GB": budget_gb, "streams": nstreams,
+           "distinct_sides": len({r[0] for r in reqs}),
+           "bytes_per_pass": nbytes, "budget_GB": budget_gb, "streams": nstreams, "output_slots": slots,
+           "per_rate_requests": f"min({nreq}, rate x {max_secs:g} s)",
            "plain_one_call_per_request": {"ms": round(t_plain, 3),
                                           "GBps": round(nbytes / (t_plain * 1e-3) / 1e9, 1)},
-           "all_at_once": sat, f"all_at_once_budget_{tight_gb:g}GB": tight, "poisson": per_rate}
-    del fields, outs, ws
+           "all_at_once": sat, f"all_at_once_budget_{tight_gb:g}GB": tight, "poisson": per_rate,
+           "mean_request_bytes": nbytes / nreq / 2}
+    del pool, outbuf, ws
     torch.cuda.empty_cache()
     return res
 
@@ -543,22 +623,148 @@ def probe_bandwidth(nbytes: int = 1 << 30, reps: int = 10):
     return {"bytes": nbytes, "ms": ms, "GBps": 2.0 * nbytes / (ms * 1e-3) / 1e9, "verified": ok}
 
 
-def cpu_baseline(u, coords, nlev):
-    import oracle
+def _drop_level(n: int, nlev: int) -> np.ndarray:
+    """Level at which each position of a dimension of n nodes leaves the
+    hierarchy (nlev for the coarsest grid's positions): along a dimension of
+    m >= 3 level nodes the coarser grid keeps the even positions and the last."""
+    out = np.full(n, nlev, dtype=np.int8)
+    pos = np.arange(n)
+    for s in range(nlev):
+        m = len(pos)
+        keep = np.ones(m, bool) if m < 3 else ((np.arange(m) % 2 == 0) | (np.arange(m) == m - 1))
+        out[pos[~keep]] = s
+        pos = pos[keep]
+    return out
 
+
+def errors_vs_oracle(got, ref, nlev):
+    """The GPU's decomposition against the oracle's: max |g - o| / max |o| and
+    relative L2 over the whole nodal array, and per coefficient class (the
+    nodes leaving the hierarchy at one level; the last class is the coarsest
+    grid) the class's max error and L2 error relative to that class."""
+    shape = ref.shape
+    cls = None
+    for k, n in enumerate(shape):
+        sh = [1] * len(shape)
+        sh[k] = n
+        lv = _drop_level(n, nlev).reshape(sh)
+        cls = lv if cls is None else np.minimum(cls, lv)
+    cls = np.broadcast_to(cls, shape)
+    diff = got.astype(np.float64) - ref
+    out = {"max_rel": float(np.max(np.abs(diff)) / np.max(np.abs(ref))),
+           "l2_rel": float(np.linalg.norm(diff) / np.linalg.norm(ref)), "per_class": []}
+    for c in range(nlev + 1):
+        m = cls == c
+        if not m.any():
+            continue
+        dc, rc = diff[m], ref[m]
+        rmax, rl2 = float(np.max(np.abs(rc))), float(np.linalg.norm(rc))
+        out["per_class"].append({"class": c, "nodes": int(m.sum()),
+                                 "max_rel": float(np.max(np.abs(dc))) / rmax if rmax > 0 else None,
+                                 "l2_rel": float(np.linalg.norm(dc)) / rl2 if rl2 > 0 else None})
+    return out
+
+
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(kept, batch_fields: int = 64, service_reqs=None, service_GBps=None):
+    """The FP64 CPU oracle, as it stands, timed on this host: built for it
+    (gcc -O2 -march=native, same arithmetic) and run with all cores
+    (OMP_NUM_THREADS, else every CPU) and with one.  `kept` maps a workload
+    name to (field, coords, nlevels, GPU decomposition); for each the oracle's
+    decomposition and recomposition are timed (median of 3 where a run takes
+    under a few seconds, else one run) and the GPU's decomposition is
+    compared with the oracle's.  The headline value is the full 513^3 FP64
+    workload on all cores; the one-core figure uses a 257^3 sample of the
+    same recipe (the full workload takes about half a minute on one core).
+    Also timed: the 64-field batch on all cores, and the request rate the
+    oracle could sustain on the service stream (from its 513^3 rate)."""
+    import oracle
+    from paper_2105_12764_amd.synth import batch_specs, make_input
+
+    nat = oracle.Native()
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
-    os.environ["OMP_NUM_THREADS"] = str(threads)
-    u64 = np.ascontiguousarray(u, dtype=np.float64)
-    _log(f"[bench] cpu baseline: oracle decompose+recompose, {threads} threads")
-    t0 = time.perf_counter()
-    d = oracle.decompose(u64, coords, nlev)
-    oracle.recompose(d, coords, nlev)
-    dt = time.perf_counter() - t0
-    n = u.size
-    return {"value": round(2.0 * n * u.dtype.itemsize / dt / 1e9, 4), "unit": "GB/s",
-            "cores": threads, "kind": "oracle",
-            "sample": f"one decompose+recompose of the full {'x'.join(map(str, u.shape))} "
-                      f"workload ({dt:.1f} s)"}
+
+    def timed(u, coords, nlev, nthreads, reps, recompose=True):
+        nat.threads(nthreads)
+        u64 = np.ascontiguousarray(u, dtype=np.float64)
+        runs, dref = [], None
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            dref = nat.decompose(u64, coords, nlev)
+            t1 = time.perf_counter()
+            if recompose:
+                nat.recompose(dref, coords, nlev)
+            t2 = time.perf_counter()
+            runs.append((t1 - t0, t2 - t1))
+        runs.sort(key=lambda t: t[0] + t[1])
+        td, tr = runs[len(runs) // 2]
+        nb = u.size * u.dtype.itemsize
+        rec = {"threads": nat.max_threads(), "runs": reps, "dec_s": round(td, 4)}
+        if recompose:
+            rec.update({"rec_s": round(tr, 4), "GBps": round(2.0 * nb / (td + tr) / 1e9, 4)})
+        else:
+            rec["GBps_decompose"] = round(nb / td / 1e9, 4)
+        return dref, rec
+
+    per, errors = {}, {}
+    for name, (u, coords, nlev, got) in kept.items():
+        big = u.size > 50_000_000
+        _log(f"[bench] cpu baseline: oracle on {name}, {threads} threads")
+        recompose = not (big and u.dtype == np.float32)  # the FP32 513^3 run is only for the errors
+        dref, rec_all = timed(u, coords, nlev, threads, 1 if big else 3, recompose=recompose)
+        per[name] = {"all_cores": rec_all}
+        if got is not None:
+            errors[name] = errors_vs_oracle(got, dref, nlev)
+            _log(f"[bench] {name}: GPU vs oracle max {errors[name]['max_rel']:.2e}, L2 {errors[name]['l2_rel']:.2e}")
+        del dref
+        if not big:
+            _, per[name]["one_core"] = timed(u, coords, nlev, 1, 3 if u.size < 1_000_000 else 1)
+    # one core on a 257^3 sample of the 513^3 FP64 workload's recipe
+    us, cs = make_input((257, 257, 257), 1002)
+    _log("[bench] cpu baseline: one core on a 257^3 sample")
+    _, one = timed(us, cs, 8, 1, 1)
+    one["sample"] = "257^3 FP64, 8 levels, same generator recipe as the 513^3 workload (seed 1002)"
+    del us
+    head = per.get("cube513_f64", {}).get("all_cores")
+    res = {"value": head["GBps"] if head else None, "unit": "GB/s", "cores": head["threads"] if head else threads,
+           "kind": "oracle",
+           "sample": (f"one decompose+recompose of the full 513x513x513 FP64 workload "
+                      f"({head['dec_s'] + head['rec_s']:.1f} s)") if head else None,
+           "single_core": one, "nproc": os.cpu_count(), "cpu_model": _cpu_model(), "build": nat.flags,
+           "per_config": per}
+    if batch_fields:
+        specs = batch_specs(batch_fields)
+        nat.threads(threads)
+        tot, nb = 0.0, 0
+        for shape, dtype, seed in specs:
+            u, _ = make_input(shape, seed, nonuniform=False, dtype=dtype)
+            nl = oracle.max_levels(shape)
+            u64 = u.astype(np.float64)
+            t0 = time.perf_counter()
+            d = nat.decompose(u64, None, nl)
+            nat.recompose(d, None, nl)
+            tot += time.perf_counter() - t0
+            nb += 2 * u.size * u.dtype.itemsize
+        res["batch"] = {"fields": batch_fields, "threads": nat.max_threads(), "s": round(tot, 3),
+                        "GBps": round(nb / tot / 1e9, 4)}
+        _log(f"[bench] cpu baseline: 64-field batch {tot:.2f} s")
+    if service_reqs and head:
+        # per direction the oracle moves a request's bytes at about its 513^3 rate
+        t_mean = float(np.mean([(r[0] ** 3) * (4 if r[1] == np.float32 else 8) / (head["GBps"] * 1e9)
+                                for r in service_reqs]))
+        res["service_sustainable_req_per_s"] = round(1.0 / t_mean, 3)
+        res["service_note"] = ("estimated: each request's bytes at the oracle's all-core 513^3 rate "
+                               "(per direction), averaged over the request stream")
+    return res, errors
 
 
 def main():
@@ -577,8 +783,10 @@ def main():
     ap.add_argument("--no-4d", action="store_true", help="skip the spatiotemporal (4-D) sweep")
     ap.add_argument("--no-progressive", action="store_true",
                     help="skip the partial recompositions (the timed step's kernels are then the last ones)")
-    ap.add_argument("--service-requests", type=int, default=300,
-                    help="requests per arrival rate in the service sweep")
+    ap.add_argument("--no-box", action="store_true", help="skip the 400x300x250 FP32 non-uniform workload")
+    ap.add_argument("--no-latency", action="store_true", help="skip the 65^3 latency measurement")
+    ap.add_argument("--service-requests", type=int, default=5000,
+                    help="requests in the service stream (each Poisson rate serves at most 10 s of it)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -586,21 +794,55 @@ def main():
               "(this refactoring path runs on a single MI355X)", file=sys.stderr)
         sys.exit(2)
 
+    want_cpu = not args.no_cpu_baseline
     probe = probe_bandwidth()
     _log(f"[bench] copy probe: {probe['GBps']:.0f} GB/s")
-    res, u, coords, nlev = run_gpu(args.workload, args.steps, args.warmup, args.graph_steps,
-                                   progressive_on=not args.no_progressive)
+    kept = {}
+    res, u, coords, nlev, dh = run_gpu(args.workload, args.steps, args.warmup, args.graph_steps,
+                                       progressive_on=not args.no_progressive, keep_output=want_cpu)
+    kept[args.workload] = (u, coords, nlev, dh)
     fp32 = None
     if not args.no_fp32 and args.fp32_workload:
-        r32, _, _, _ = run_gpu(args.fp32_workload, args.steps, args.warmup,
-                              progressive_on=not args.no_progressive)
+        r32, u32, c32, n32, d32 = run_gpu(args.fp32_workload, args.steps, args.warmup,
+                                          progressive_on=not args.no_progressive, keep_output=want_cpu)
+        kept[args.fp32_workload] = (u32, c32, n32, d32)
         fp32 = {k: r32[k] for k in ("workload", "value", "t_dec_ms", "t_rec_ms", "alg_GBps",
                                      "roundtrip_max_rel_err", "roofline")}
         fp32["untuned_value"] = r32["autotune"]["untuned_value"] if r32.get("autotune") else None
+    box = None
+    if not args.no_box:
+        rb, ub, cb, nb, db = run_gpu("box400x300x250_f32", args.steps, args.warmup, progressive_on=False,
+                                     keep_output=want_cpu)
+        kept["box400x300x250_f32"] = (ub, cb, nb, db)
+        box = {k: rb[k] for k in ("workload", "shape", "nlevels", "value", "t_dec_ms", "t_rec_ms", "alg_GBps",
+                                   "roundtrip_max_rel_err", "roofline")}
+        box["data"] = "non-uniform coordinates (spacing U[0.5, 1.5]), seed 1003"
+    latency = None
+    if not args.no_latency:
+        latency = run_latency("cube65_f64")
+        if want_cpu:
+            from paper_2105_12764_amd.synth import WORKLOADS, make_input
+            sh, sd, nu, dt, nl = WORKLOADS["cube65_f64"]
+            u65, c65 = make_input(sh, sd, nonuniform=nu, dtype=dt)
+            import torch
+            from paper_2105_12764_amd import mgr
+            d65 = mgr.decompose(torch.from_numpy(u65).cuda(), c65, nl)
+            torch.cuda.synchronize()
+            kept["cube65_f64"] = (u65, c65, nl, d65.cpu().numpy())
     batched = None if args.no_batch else run_batched()
     service = None if args.no_service else run_service(args.service_requests)
     spatiotemporal = None if args.no_4d else run_spatiotemporal()
-    cpu = None if args.no_cpu_baseline else cpu_baseline(u, coords, nlev)
+    cpu, errors = None, None
+    if want_cpu:
+        from paper_2105_12764_amd.synth import service_requests
+        cpu, errors = cpu_baseline(kept, batch_fields=0 if args.no_batch else 64,
+                                   service_reqs=service_requests(args.service_requests))
+        if fp32 is not None:
+            fp32["errors_vs_oracle"] = errors.get(args.fp32_workload)
+        if box is not None:
+            box["errors_vs_oracle"] = errors.get("box400x300x250_f32")
+        if latency is not None:
+            latency["errors_vs_oracle"] = errors.get("cube65_f64")
 
     line = {
         "metric": METRIC,
@@ -626,11 +868,14 @@ def main():
         "copy_probe_GBps": round(probe["GBps"], 1),
         "pct_of_copy_probe": round(100.0 * res["alg_GBps"] / probe["GBps"], 2),
         "roundtrip_max_rel_err": res["roundtrip_max_rel_err"],
+        "errors_vs_oracle": errors.get(args.workload) if errors else None,
         "roofline": res["roofline"],
         "hbm_measured": res["hbm_measured"],
         "cpu_baseline": cpu,
         "kernels": res["kernels"],
         "fp32": fp32,
+        "box400x300x250_f32": box,
+        "latency_65": latency,
         "graph": res["graph"],
         "autotune": res["autotune"],
         "progressive": res["progressive"],

@@ -26,10 +26,27 @@
  *     corrected coarse values Q u.  nlevels = 0 is a copy;
  *   - coordinates default to 0, 1, ..., n-1.
  *
- * Precision: MGR_FLOAT64 computes everything in FP64.  MGR_FLOAT32 stores
- * FP32 (input, output, coarse grids) and evaluates every step in FP64
- * registers, with the load vector and the tridiagonal solves held in FP64
- * workspace; values are rounded to FP32 once, where they are stored.
+ * Precision: MGR_FLOAT64 computes everything in FP64.  MGR_FLOAT32 keeps
+ * the input and output in FP32 and splits as follows:
+ *   - decomposition: coefficients, interpolation and the load vector are
+ *     computed in FP64 (a coefficient is the difference of a value and its
+ *     nearly equal interpolant), and the coarser level grids are kept in
+ *     FP64 in the workspace; each stored value is rounded to FP32 once;
+ *   - recomposition: the load vector of the stored coefficients and the
+ *     interpolation are computed in FP32 (a coefficient is added to an
+ *     interpolant, with no cancellation), the load vector is widened to
+ *     FP64 for the solves, and the coarser level grids are FP32;
+ *   - the tridiagonal correction solves and their workspace are FP64 in
+ *     both directions.
+ *
+ * Plans and graph capture: the first call for a new (shape, coords,
+ * nlevels) on a device builds FP64 tables on the host and uploads them (one
+ * device allocation and one synchronous copy); the library caches the 1024
+ * most recently used such plans.  A call made while its stream captures a
+ * HIP graph needs its plan cached already (MGR_ERR_UNSUPPORTED otherwise:
+ * make one call outside the capture first); the captured graph then holds
+ * the plan, whose tables stay allocated until the graph and every
+ * executable graph made from it are destroyed, even if the cache drops it.
  *
  * Threading: every entry point is thread-safe.  Calls are stream-ordered
  * and asynchronous: they return after enqueuing work on `stream`.
@@ -93,10 +110,8 @@ mgr_status mgr_workspace_size(int ndim, const int64_t *shape, mgr_dtype dtype,
  *                 shared by calls that may run concurrently.
  *   stream      : hipStream_t to enqueue on (NULL = the null stream).
  * All argument checks happen before anything is enqueued; on any error
- * nothing is launched and `out` is untouched.  The first call for a new
- * (shape, coords, nlevels) on a device builds FP64 tables on the host and
- * uploads them (one synchronous allocation and copy); later calls reuse
- * them. */
+ * nothing is launched and `out` is untouched.  Plans are built and cached
+ * as described above (see "Plans and graph capture"). */
 mgr_status mgr_decompose(int ndim, const int64_t *shape,
                          const double *const *coords, mgr_dtype dtype,
                          int nlevels, const void *in, void *out,
@@ -110,11 +125,12 @@ mgr_status mgr_decompose(int ndim, const int64_t *shape,
  * level's load vector and first solves (which read only `in`) run on a
  * library-owned stream forked from `stream` after the work already on it and
  * joined back before the finest level's last kernels, so the call stays
- * ordered on `stream` and capturable in a HIP graph; the helper stream of a
- * (device, stream) pair is created by its first call, so make one call
- * before capturing.  Helper streams are kept for at most 64 such pairs per
- * process; calls from further pairs, and 4-D fields, run serially on
- * `stream`. */
+ * ordered on `stream` and capturable in a HIP graph.  The helper stream of a
+ * (device, stream) pair is created by its first call outside stream
+ * capture; a captured call whose stream has none yet runs serially (same
+ * results).  Helper streams are kept for at most 64 such pairs per process
+ * (a service frees those of its streams when it is destroyed); calls from
+ * further pairs, and 4-D fields, run serially on `stream`. */
 mgr_status mgr_recompose(int ndim, const int64_t *shape,
                          const double *const *coords, mgr_dtype dtype,
                          int nlevels, const void *in, void *out,
@@ -170,8 +186,10 @@ const char *mgr_status_string(mgr_status s);
  * valid until the thread's next libmgr call. */
 const char *mgr_last_error(void);
 
-/* Drop every cached plan and free its device tables.  The caller must make
- * sure no enqueued libmgr work is still pending. */
+/* Drop every cached plan.  A plan's device tables are freed at once unless
+ * a captured graph still holds the plan (they are freed after the graph and
+ * its executables are destroyed).  The caller must make sure no enqueued
+ * libmgr work outside captured graphs is still pending. */
 void mgr_release_caches(void);
 
 /* Autotune the launch shapes for this request (the paper's per-size tuning,
@@ -186,7 +204,9 @@ void mgr_release_caches(void);
  * Arguments as for mgr_decompose; `in` is only read (its values do not
  * matter), `out` and the workspace are overwritten with meaningless data.
  * Synchronous: returns after the timed launches on `stream` have finished;
- * not for use under stream capture. */
+ * MGR_ERR_UNSUPPORTED under stream capture.  The tuned shapes are also kept
+ * per (device, shape, nlevels) beyond the plan's life in the cache: a plan
+ * rebuilt later for the same shape starts with them. */
 mgr_status mgr_autotune(int ndim, const int64_t *shape, const double *const *coords,
                         mgr_dtype dtype, int nlevels, const void *in, void *out,
                         void *workspace, size_t workspace_bytes, void *stream);
@@ -234,7 +254,9 @@ mgr_status mgr_batch_workspace_size(int nfields, const mgr_field *fields, size_t
  *               forked from `stream` and joined back with events, so small
  *               fields run side by side and the whole call can be captured
  *               into one HIP graph (plans must exist first: make one
- *               uncaptured call with the same fields before capturing).
+ *               uncaptured call with the same fields before capturing, with
+ *               at most 256 distinct plans in the batch so that they all
+ *               stay cached).
  * Besides every check of mgr_decompose per field (the detail names the
  * field), no field's out may overlap another field's in or out.  All checks
  * happen before anything is enqueued; on error nothing is launched. */
@@ -251,8 +273,11 @@ mgr_status mgr_recompose_batch(int nfields, const mgr_field *fields, void *works
  * device buffers, admitted first-in first-out by HBM footprint: a request
  * starts only while the in-flight footprint -- input + output + workspace
  * bytes of every admitted, unfinished request -- stays within the budget.
- * Workspace comes from an arena allocated at creation (half the budget plus
- * 1 MiB, at most the budget), so requests allocate nothing.  The operations
+ * Workspace comes from an arena allocated at creation (4/5 of the budget
+ * plus 1 MiB, at most the budget: a request's workspace is below 0.77 of its
+ * footprint plus 1 KiB, so any request within the budget fits it), so
+ * requests allocate nothing.  A request's plan is built by the submitting
+ * thread, before it takes the service's lock.  The operations
  * are those of mgr_decompose / mgr_recompose; the service is the stream of
  * many independent fields refactored inside workflows (Sec. V)
  * with admission by memory footprint.  Admitted requests run on
@@ -270,10 +295,10 @@ mgr_status mgr_service_create(size_t budget_bytes, int nstreams, mgr_service **s
  * mgr_decompose minus the workspace and stream (1..4 dims); coordinates are
  * copied.
  * `in` must stay unchanged and `out` unused by the caller until the request
- * is done.  Returns at once with a ticket (1, 2, ...); the request waits if
- * it does not fit yet.  MGR_ERR_UNSUPPORTED for a request whose footprint
- * exceeds the budget (or its workspace the arena); argument errors as for
- * mgr_decompose are reported by mgr_service_result. */
+ * is done.  Returns after finding or building the request's plan, with a
+ * ticket (1, 2, ...); the request waits if it does not fit yet.
+ * MGR_ERR_UNSUPPORTED for a request whose footprint exceeds the budget;
+ * argument errors as for mgr_decompose are reported by mgr_service_result. */
 mgr_status mgr_service_submit(mgr_service *svc, int recompose, int ndim, const int64_t *shape,
                               const double *const *coords, mgr_dtype dtype, int nlevels,
                               const void *in, void *out, uint64_t *ticket);
@@ -288,7 +313,8 @@ mgr_status mgr_service_wait_all(mgr_service *svc);
 mgr_status mgr_service_result(mgr_service *svc, uint64_t ticket, int *done, mgr_status *status,
                               double *queue_ms, double *latency_ms);
 
-/* Wait for every request, stop the threads and free the arena and streams.
+/* Wait for every request, stop the threads and free the arena and streams
+ * (with the recomposition helper streams the library made for them).
  * (Each request's record -- status and times, about a hundred bytes of host
  * memory -- is kept until then, so that mgr_service_result answers for every
  * ticket.) */

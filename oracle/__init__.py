@@ -24,15 +24,32 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 
+def _compile(path: str, native: bool) -> None:
+    tmp = path + ".tmp"
+    cmd = ["gcc", "-O2", *(["-march=native"] if native else []), "-fopenmp", "-fPIC", "-shared", "-std=c11",
+           "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, path)
+
+
 def build(force: bool = True) -> str:
-    """Compile mgr_oracle.c into liboracle.so with gcc (-O2, OpenMP, no fast-math)."""
+    """Compile mgr_oracle.c into liboracle.so with gcc (-O2, OpenMP, no
+    fast-math; ISO C, so no floating-point contraction either)."""
     if force or not os.path.exists(_LIB_PATH):
-        tmp = _LIB_PATH + ".tmp"
-        cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
-               "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"]
-        subprocess.run(cmd, check=True)
-        os.replace(tmp, _LIB_PATH)
+        _compile(_LIB_PATH, native=False)
     return _LIB_PATH
+
+
+def _bind(lib):
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    dpp = ctypes.POINTER(ctypes.POINTER(ctypes.c_double))
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.oracle_max_levels.argtypes = [ctypes.c_int, i64p]
+    lib.oracle_max_levels.restype = ctypes.c_int
+    for fn in (lib.oracle_decompose, lib.oracle_recompose):
+        fn.argtypes = [ctypes.c_int, i64p, dpp, ctypes.c_int, dp, dp]
+        fn.restype = ctypes.c_int
+    return lib
 
 
 def _load():
@@ -40,17 +57,39 @@ def _load():
     if _lib is None:
         if not os.path.exists(_LIB_PATH):
             build()
-        lib = ctypes.CDLL(_LIB_PATH)
-        i64p = ctypes.POINTER(ctypes.c_int64)
-        dpp = ctypes.POINTER(ctypes.POINTER(ctypes.c_double))
-        dp = ctypes.POINTER(ctypes.c_double)
-        lib.oracle_max_levels.argtypes = [ctypes.c_int, i64p]
-        lib.oracle_max_levels.restype = ctypes.c_int
-        for fn in (lib.oracle_decompose, lib.oracle_recompose):
-            fn.argtypes = [ctypes.c_int, i64p, dpp, ctypes.c_int, dp, dp]
-            fn.restype = ctypes.c_int
-        _lib = lib
+        _lib = _bind(ctypes.CDLL(_LIB_PATH))
     return _lib
+
+
+class Native:
+    """The same C source built for the host it runs on (-O2 -march=native,
+    still ISO C without fast-math or contraction, so the same arithmetic),
+    in a temporary directory: used to time the oracle as a CPU baseline.
+    ``threads(n)`` sets the OpenMP thread count of later calls made from
+    this thread."""
+
+    def __init__(self):
+        import tempfile
+        self._dir = tempfile.mkdtemp(prefix="mgr_oracle_")
+        path = os.path.join(self._dir, "liboracle_native.so")
+        _compile(path, native=True)
+        self._lib = _bind(ctypes.CDLL(path))
+        self._omp = ctypes.CDLL("libgomp.so.1")
+        self._omp.omp_set_num_threads.argtypes = [ctypes.c_int]
+        self._omp.omp_get_max_threads.restype = ctypes.c_int
+        self.flags = "gcc -O2 -march=native -fopenmp -std=c11"
+
+    def threads(self, n: int) -> None:
+        self._omp.omp_set_num_threads(int(n))
+
+    def max_threads(self) -> int:
+        return int(self._omp.omp_get_max_threads())
+
+    def decompose(self, u, coords=None, nlevels=None) -> np.ndarray:
+        return _run(self._lib.oracle_decompose, u, coords, nlevels)
+
+    def recompose(self, v, coords=None, nlevels=None) -> np.ndarray:
+        return _run(self._lib.oracle_recompose, v, coords, nlevels)
 
 
 def _shape_arg(shape):

@@ -13,8 +13,10 @@
 #include <vector>
 
 #include "../../include/mgr.h"
+#include "mgr_api_internal.hpp"
 #include "mgr_kernels.hpp"
 #include "mgr_plan.hpp"
+#include "mgr_plan_cache.hpp"
 
 namespace {
 
@@ -26,19 +28,88 @@ mgr_status fail(mgr_status s, const std::string &msg) {
   return s;
 }
 
-struct CacheEntry {
+// Cache key of a plan: the device, the caller's rank, the padded shape, the
+// time extent (4-D), the level count and the coordinates.
+struct PlanKey {
   int device;
   int ndim;
   int64_t n[mgr::kDims];
   int64_t nt;  // time extent of a 4-D field (1 otherwise)
   int nlev;
   std::vector<std::vector<double>> coords;
-  std::shared_ptr<mgr::Plan> plan;
+  bool operator==(const PlanKey &o) const {
+    return device == o.device && ndim == o.ndim && nt == o.nt && nlev == o.nlev &&
+           std::memcmp(n, o.n, sizeof(n)) == 0 && coords == o.coords;
+  }
 };
 
-std::mutex g_mu;
-std::list<CacheEntry> g_cache;  // most recently used first
-constexpr size_t kCacheMax = 64;
+// Key of autotuned launch shapes: they depend on the grid's shape, not on
+// its coordinates.
+struct TuneKey {
+  int device;
+  int ndim;
+  int64_t n[mgr::kDims];
+  int64_t nt;
+  int nlev;
+  bool operator==(const TuneKey &o) const {
+    return device == o.device && ndim == o.ndim && nt == o.nt && nlev == o.nlev &&
+           std::memcmp(n, o.n, sizeof(n)) == 0;
+  }
+};
+using TuneVec = std::vector<mgr::LevelTune>;
+
+// Plans kept at most (a batch of more distinct fields than this cannot be
+// captured into a graph: its warm-up call would evict its own first plans),
+// and tuned shapes kept at most.
+constexpr size_t kCacheMax = 1024;
+constexpr size_t kTuneMax = 4096;
+
+std::mutex g_mu;  // guards g_cache and g_tunes
+mgr::LruCache<PlanKey, mgr::Plan> g_cache(kCacheMax);
+mgr::LruCache<TuneKey, TuneVec> g_tunes(kTuneMax);
+// Plan references given up by destroyed graphs, released by a later call.
+mgr::Deferred<mgr::Plan> g_deferred;
+
+void graph_release_plan(void *holder) { g_deferred.release(static_cast<std::shared_ptr<mgr::Plan> *>(holder)); }
+
+// Whether `stream` is capturing into a graph (and which), or an error.
+mgr_status capture_state(void *stream, bool &capturing, hipGraph_t *graph = nullptr) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamGetCaptureInfo_v2((hipStream_t)stream, &st, nullptr, &g, nullptr, nullptr);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(MGR_ERR_DEVICE, std::string("hipStreamGetCaptureInfo: ") + hipGetErrorString(e));
+  }
+  capturing = st == hipStreamCaptureStatusActive;
+  if (graph) *graph = capturing ? g : nullptr;
+  return MGR_OK;
+}
+
+// Keeps `plans` alive for as long as the graph being captured on `stream`
+// (and every executable made from it) exists: each gets a user object that
+// the graph owns.  No-op when the stream is not capturing.
+mgr_status retain_for_capture(void *stream, const std::vector<std::shared_ptr<mgr::Plan>> &plans) {
+  bool capturing = false;
+  hipGraph_t g = nullptr;
+  mgr_status s = capture_state(stream, capturing, &g);
+  if (s != MGR_OK || !capturing) return s;
+  for (const auto &p : plans) {
+    auto *h = mgr::Deferred<mgr::Plan>::hold(p);
+    hipUserObject_t obj = nullptr;
+    if (hipUserObjectCreate(&obj, h, graph_release_plan, 1, hipUserObjectNoDestructorSync) != hipSuccess) {
+      (void)hipGetLastError();
+      delete h;
+      return fail(MGR_ERR_DEVICE, "hipUserObjectCreate failed while capturing");
+    }
+    if (hipGraphRetainUserObject(g, obj, 1, hipGraphUserObjectMove) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipUserObjectRelease(obj, 1);  // runs graph_release_plan
+      return fail(MGR_ERR_DEVICE, "hipGraphRetainUserObject failed while capturing");
+    }
+  }
+  return MGR_OK;
+}
 
 // Pads the caller's shape to rank 3 with leading 1s.
 bool pad_shape(int ndim, const int64_t *shape, int64_t n[mgr::kDims], std::string &why) {
@@ -109,6 +180,30 @@ bool split_shape(int ndim, const int64_t *shape, int64_t n[mgr::kDims], int64_t 
   return true;
 }
 
+// Per-dim coordinates: the padded rank-3 dims, or (4-D) time then space;
+// NULL entries (or coords == NULL) are uniform.
+mgr_status make_coords(int ndim, const int64_t n[mgr::kDims], int64_t nt, const double *const *coords,
+                       std::vector<std::vector<double>> &cx) {
+  const int nc = ndim == 4 ? 4 : mgr::kDims;
+  cx.assign(nc, {});
+  for (int k = 0; k < nc; ++k) {
+    const int uk = ndim == 4 ? k : k - (mgr::kDims - ndim);
+    const int64_t ext = ndim == 4 ? (k == 0 ? nt : n[k - 1]) : n[k];
+    const double *src = (uk >= 0 && coords) ? coords[uk] : nullptr;
+    cx[k].resize(ext);
+    for (int64_t i = 0; i < ext; ++i) {
+      const double v = src ? src[i] : (double)i;
+      if (!std::isfinite(v))
+        return fail(MGR_ERR_INVALID_ARG, "coords[" + std::to_string(uk) + "] has a non-finite value");
+      if (i > 0 && !(v > cx[k][i - 1]))
+        return fail(MGR_ERR_INVALID_ARG,
+                    "coords[" + std::to_string(uk) + "] is not strictly increasing");
+      cx[k][i] = v;
+    }
+  }
+  return MGR_OK;
+}
+
 mgr_status validate(int ndim, const int64_t *shape, const double *const *coords, int dtype,
                     int nlevels, const void *in, void *out, void *ws, size_t ws_bytes,
                     int64_t n[mgr::kDims], std::vector<std::vector<double>> &cx, int64_t *nt_out = nullptr) {
@@ -127,24 +222,8 @@ mgr_status validate(int ndim, const int64_t *shape, const double *const *coords,
   const size_t bytes = (size_t)(nt * n[0] * n[1] * n[2]) * esz;
   const char *a = (const char *)in, *b = (const char *)out;
   if (a < b + bytes && b < a + bytes) return fail(MGR_ERR_INVALID_ARG, "in and out overlap");
-  // per-dim coordinates: the padded rank-3 dims, or (4-D) time then space
-  const int nc = ndim == 4 ? 4 : mgr::kDims;
-  cx.assign(nc, {});
-  for (int k = 0; k < nc; ++k) {
-    const int uk = ndim == 4 ? k : k - (mgr::kDims - ndim);
-    const int64_t ext = ndim == 4 ? (k == 0 ? nt : n[k - 1]) : n[k];
-    const double *src = (uk >= 0 && coords) ? coords[uk] : nullptr;
-    cx[k].resize(ext);
-    for (int64_t i = 0; i < ext; ++i) {
-      const double v = src ? src[i] : (double)i;
-      if (!std::isfinite(v))
-        return fail(MGR_ERR_INVALID_ARG, "coords[" + std::to_string(uk) + "] has a non-finite value");
-      if (i > 0 && !(v > cx[k][i - 1]))
-        return fail(MGR_ERR_INVALID_ARG,
-                    "coords[" + std::to_string(uk) + "] is not strictly increasing");
-      cx[k][i] = v;
-    }
-  }
+  const mgr_status sc = make_coords(ndim, n, nt, coords, cx);
+  if (sc != MGR_OK) return sc;
   const size_t need = ndim == 4 ? mgr::workspace_bytes4(nt, n, nlevels, esz) : mgr::workspace_bytes(n, nlevels, esz);
   if (need > 0) {
     if (!ws) return fail(MGR_ERR_WORKSPACE, "workspace is NULL");
@@ -158,24 +237,35 @@ mgr_status validate(int ndim, const int64_t *shape, const double *const *coords,
   return MGR_OK;
 }
 
+// The cached plan of a request, built and cached if there is none.  A plan
+// is built with a device allocation and a synchronous copy, which stream
+// capture does not allow, so under capture (`stream` capturing) a missing
+// plan is an error.  Tuned launch shapes kept for the shape are restored
+// into a new plan.
 mgr_status get_plan(const int64_t n[mgr::kDims], int ndim, int nlevels,
                     const std::vector<std::vector<double>> &cx, std::shared_ptr<mgr::Plan> &out,
-                    int64_t nt = 1) {
+                    void *stream, int64_t nt = 1) {
   int dev = -1;
   hipError_t he = hipGetDevice(&dev);
   if (he != hipSuccess) {
     (void)hipGetLastError();
     return fail(MGR_ERR_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(he));
   }
-  std::lock_guard<std::mutex> lk(g_mu);
-  for (auto it = g_cache.begin(); it != g_cache.end(); ++it) {
-    if (it->device != dev || it->ndim != ndim || it->nlev != nlevels || it->nt != nt) continue;
-    if (std::memcmp(it->n, n, sizeof(it->n)) != 0) continue;
-    if (it->coords != cx) continue;
-    out = it->plan;
-    g_cache.splice(g_cache.begin(), g_cache, it);
-    return MGR_OK;
+  bool capturing = false;
+  mgr_status cs = capture_state(stream, capturing);
+  if (cs != MGR_OK) return cs;
+  if (!capturing) g_deferred.drain();  // plans of destroyed graphs (may free device tables)
+  PlanKey key{dev, ndim, {n[0], n[1], n[2]}, nt, nlevels, cx};
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    out = g_cache.find(key);
+    if (out) return MGR_OK;
   }
+  if (capturing)
+    return fail(MGR_ERR_UNSUPPORTED,
+                "no cached plan for this request while the stream is capturing a graph (building one "
+                "allocates device memory): make one call with the same shape, coordinates and level "
+                "count outside the capture first");
   std::string err;
   int st = 0;
   std::unique_ptr<mgr::Plan> p;
@@ -187,18 +277,27 @@ mgr_status get_plan(const int64_t n[mgr::kDims], int ndim, int nlevels,
     return fail(MGR_ERR_DEVICE, "unexpected failure while building the plan");
   }
   if (!p) return fail((mgr_status)st, err);
-  CacheEntry e;
-  e.device = dev;
-  e.ndim = ndim;
-  e.nt = nt;
-  std::memcpy(e.n, n, sizeof(e.n));
-  e.nlev = nlevels;
-  e.coords = cx;
-  e.plan = std::shared_ptr<mgr::Plan>(p.release());
-  out = e.plan;
-  g_cache.push_front(std::move(e));
-  while (g_cache.size() > kCacheMax) g_cache.pop_back();
+  std::vector<std::shared_ptr<mgr::Plan>> dropped;  // released after the lock (frees device tables)
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (auto t = g_tunes.find(TuneKey{dev, ndim, {n[0], n[1], n[2]}, nt, nlevels})) p->tune = *t;
+    out = std::shared_ptr<mgr::Plan>(p.release());
+    g_cache.insert(key, out, dropped);
+  }
   return MGR_OK;
+}
+
+// Keeps the tuned launch shapes of `pl` for later plans of the same shape.
+void remember_tune(const mgr::Plan &pl, const int64_t n[mgr::kDims], int ndim, int64_t nt, int nlevels) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return;
+  }
+  auto t = std::make_shared<TuneVec>(pl.tune_snapshot());
+  std::vector<std::shared_ptr<TuneVec>> dropped;
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_tunes.insert(TuneKey{dev, ndim, {n[0], n[1], n[2]}, nt, nlevels}, t, dropped);
 }
 
 // A helper stream per (device, caller stream) for the work a recomposition
@@ -220,8 +319,9 @@ std::list<Helper> g_helpers;  // stable addresses
 constexpr size_t kHelpersMax = 64;
 
 // The helper of `caller` on the current device, or nullptr (then the call
-// runs serially) when it cannot be created or the registry is full.
-Helper *helper_for(hipStream_t caller) {
+// runs serially) when it cannot be created, the registry is full, or there
+// is none yet and `create` is false (stream capture).
+Helper *helper_for(hipStream_t caller, bool create) {
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess) {
     (void)hipGetLastError();
@@ -230,7 +330,7 @@ Helper *helper_for(hipStream_t caller) {
   std::lock_guard<std::mutex> lk(g_hmu);
   for (auto &h : g_helpers)
     if (h.device == dev && h.caller == caller) return &h;
-  if (g_helpers.size() >= kHelpersMax) return nullptr;
+  if (!create || g_helpers.size() >= kHelpersMax) return nullptr;
   hipStream_t s = nullptr;
   hipEvent_t f = nullptr, j = nullptr;
   bool ok = hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess;
@@ -266,14 +366,18 @@ mgr_status run(bool dec, int ndim, const int64_t *shape, const double *const *co
     if (nkeep != -1 && ndim == 4)
       return fail(MGR_ERR_UNSUPPORTED, "partial recomposition of 4-D fields is not supported");
     std::shared_ptr<mgr::Plan> plan;
-    s = get_plan(n, ndim, nlevels, cx, plan, nt);
+    s = get_plan(n, ndim, nlevels, cx, plan, stream, nt);
+    if (s != MGR_OK) return s;
+    bool capturing = false;
+    s = capture_state(stream, capturing);
     if (s != MGR_OK) return s;
     std::string err;
     const bool f64 = dtype == MGR_FLOAT64;
     bool ok = false;
     if (dec) {
       ok = mgr::enqueue_decompose(*plan, f64, in, out, ws, stream, err);
-    } else if (Helper *h = (plan->nlev >= 2 && !plan->time) ? helper_for((hipStream_t)stream) : nullptr) {
+    } else if (Helper *h = (plan->nlev >= 2 && !plan->time) ? helper_for((hipStream_t)stream, !capturing)
+                                                            : nullptr) {
       std::lock_guard<std::mutex> lk(h->mu);
       const mgr::StreamFork fk{h->s, h->fork, h->join};
       ok = mgr::enqueue_recompose(*plan, f64, in, out, ws, stream, err, nkeep, &fk);
@@ -281,6 +385,7 @@ mgr_status run(bool dec, int ndim, const int64_t *shape, const double *const *co
       ok = mgr::enqueue_recompose(*plan, f64, in, out, ws, stream, err, nkeep);
     }
     if (!ok) return fail(MGR_ERR_DEVICE, err);
+    if (capturing) return retain_for_capture(stream, {plan});
     return MGR_OK;
   } catch (const std::bad_alloc &) {
     return fail(MGR_ERR_OUT_OF_MEMORY, "host allocation failed");
@@ -403,7 +508,7 @@ mgr_status run_batch(bool dec, int nfields, const mgr_field *fields, void *ws, s
                                                std::to_string(j));
       }
     for (int i = 0; i < nfields; ++i) {
-      s = get_plan(jobs[i].n, fields[i].ndim, fields[i].nlevels, jobs[i].cx, jobs[i].plan);
+      s = get_plan(jobs[i].n, fields[i].ndim, fields[i].nlevels, jobs[i].cx, jobs[i].plan, stream);
       if (s != MGR_OK) return fail(s, field_tag(i) + g_last_error);
     }
     int dev = -1;
@@ -469,7 +574,10 @@ mgr_status run_batch(bool dec, int nfields, const mgr_field *fields, void *ws, s
       }
     }
     if (!ok) return fail(MGR_ERR_DEVICE, err);
-    return MGR_OK;
+    std::vector<std::shared_ptr<mgr::Plan>> plans;
+    for (auto &j : jobs)
+      if (std::find(plans.begin(), plans.end(), j.plan) == plans.end()) plans.push_back(j.plan);
+    return retain_for_capture(stream, plans);
   } catch (const std::bad_alloc &) {
     return fail(MGR_ERR_OUT_OF_MEMORY, "host allocation failed");
   } catch (...) {
@@ -478,6 +586,53 @@ mgr_status run_batch(bool dec, int nfields, const mgr_field *fields, void *ws, s
 }
 
 }  // namespace
+
+namespace mgr {
+
+mgr_status prepare_plan(int ndim, const int64_t *shape, const double *const *coords, int nlevels) {
+  try {
+    int64_t n[kDims], nt = 1;
+    std::string why;
+    if (!split_shape(ndim, shape, n, nt, why)) return fail(MGR_ERR_INVALID_ARG, why);
+    const int ml = ndim == 4 ? max_levels4(nt, n) : max_levels3(n);
+    if (nlevels < 0 || nlevels > ml || nlevels > kMaxLevels)
+      return fail(MGR_ERR_INVALID_ARG, "nlevels must be in [0, " + std::to_string(ml) + "]");
+    std::vector<std::vector<double>> cx;
+    const mgr_status s = make_coords(ndim, n, nt, coords, cx);
+    if (s != MGR_OK) return s;
+    std::shared_ptr<Plan> plan;
+    return get_plan(n, ndim, nlevels, cx, plan, nullptr, nt);
+  } catch (const std::bad_alloc &) {
+    return fail(MGR_ERR_OUT_OF_MEMORY, "host allocation failed");
+  } catch (...) {
+    return fail(MGR_ERR_DEVICE, "unexpected internal failure");
+  }
+}
+
+void forget_helpers(const hipStream_t *callers, int n) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return;
+  }
+  std::lock_guard<std::mutex> lk(g_hmu);
+  for (int q = 0; q < n; ++q)
+    for (auto it = g_helpers.begin(); it != g_helpers.end(); ++it) {
+      if (it->device != dev || it->caller != callers[q]) continue;
+      {
+        std::lock_guard<std::mutex> hl(it->mu);  // no enqueue of this caller in progress
+        (void)hipStreamSynchronize(it->s);
+        (void)hipEventDestroy(it->fork);
+        (void)hipEventDestroy(it->join);
+        (void)hipStreamDestroy(it->s);
+      }
+      g_helpers.erase(it);
+      break;
+    }
+  (void)hipGetLastError();
+}
+
+}  // namespace mgr
 
 extern "C" {
 
@@ -555,7 +710,7 @@ static mgr_status run_classes(bool export_, int ndim, const int64_t *shape, mgr_
       for (int64_t i = 0; i < n[k]; ++i) cx[k][i] = (double)i;
     }
     std::shared_ptr<mgr::Plan> plan;
-    mgr_status s = get_plan(n, ndim, nlevels, cx, plan);
+    mgr_status s = get_plan(n, ndim, nlevels, cx, plan, stream);
     if (s != MGR_OK) return s;
     std::string err;
     if (!mgr::enqueue_classes(*plan, dtype == MGR_FLOAT64, export_, in, out, stream, err))
@@ -612,12 +767,17 @@ mgr_status mgr_autotune(int ndim, const int64_t *shape, const double *const *coo
     if (ndim == 4) return fail(MGR_ERR_UNSUPPORTED, "autotuning of 4-D fields is not supported");
     mgr_status s = validate(ndim, shape, coords, (int)dtype, nlevels, in, out, workspace, workspace_bytes, n, cx);
     if (s != MGR_OK) return s;
+    bool capturing = false;
+    s = capture_state(stream, capturing);
+    if (s != MGR_OK) return s;
+    if (capturing) return fail(MGR_ERR_UNSUPPORTED, "mgr_autotune waits for its timed launches: not under stream capture");
     std::shared_ptr<mgr::Plan> plan;
-    s = get_plan(n, ndim, nlevels, cx, plan);
+    s = get_plan(n, ndim, nlevels, cx, plan, stream);
     if (s != MGR_OK) return s;
     std::string err, report;
     if (!mgr::enqueue_autotune(*plan, dtype == MGR_FLOAT64, in, out, workspace, stream, err, report))
       return fail(MGR_ERR_DEVICE, err);
+    remember_tune(*plan, n, ndim, 1, nlevels);
     g_tune_report = report;
     return MGR_OK;
   } catch (const std::bad_alloc &) {
@@ -682,8 +842,13 @@ const char *mgr_status_string(mgr_status s) {
 const char *mgr_last_error(void) { return g_last_error.c_str(); }
 
 void mgr_release_caches(void) {
-  std::lock_guard<std::mutex> lk(g_mu);
-  g_cache.clear();
+  std::vector<std::shared_ptr<mgr::Plan>> dropped;  // released after the lock
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_cache.clear(dropped);
+  }
+  dropped.clear();
+  g_deferred.drain();
 }
 
 }  // extern "C"

@@ -5,7 +5,10 @@
 // every admitted request's input, output and workspace bytes -- stays
 // within the service's budget.  Workspace comes from one arena allocated at
 // creation (first fit, coalescing on release), so no request allocates
-// device memory.  An admitted request is enqueued on the internal stream
+// device memory.  A request's plan (the library's tables for its shape,
+// coordinates and level count) is built or found by the submitting thread
+// before the service lock is taken, so a new shape's table upload does not
+// hold up the other requests.  An admitted request is enqueued on the internal stream
 // with the fewest requests running, followed by an event; one waiter thread
 // per stream retires its requests in order, releases their budget and
 // workspace, and admits what waits.  Times are host steady-clock
@@ -25,6 +28,7 @@
 #include <vector>
 
 #include "../../include/mgr.h"
+#include "mgr_api_internal.hpp"
 #include "mgr_arena.hpp"
 
 namespace {
@@ -157,11 +161,21 @@ mgr_status mgr_service_create(size_t budget_bytes, int nstreams, mgr_service **s
       return sfail(MGR_ERR_DEVICE, "hipGetDevice failed");
     }
     s->budget = budget_bytes;
-    // A request's workspace (two coarse grids in its type and one FP64 grid)
-    // is at most half its footprint up to a few elements and the 256-byte
-    // rounding, so half the budget plus 1 MiB holds any admissible request;
-    // a larger in-flight set that does not fit waits for a release.
-    s->arena_bytes = std::min(budget_bytes, budget_bytes / 2 + ((size_t)1 << 20));
+    // Workspace against footprint (mgr_workspace_size): three FP64 grids of
+    // the level-1 shape and one of the level-2 shape (4-D: three FP64 coarse
+    // grids and nt FP64 coarse space slices), each rounded up to 256 bytes.
+    // A dimension of m >= 3 nodes keeps m/2 + 1 <= 3m/4 of them (m = 4 is
+    // the worst) and a dimension of 2 keeps both, so the level-1 grid holds
+    // at most 3/4 of the N nodes and the level-2 grid at most 1/2 (4-D: the
+    // coarse grids at most 3/4, the slices at most N).  The workspace is then
+    // at most 22N bytes (4-D: 26N) plus 1 KiB of rounding, against a
+    // footprint of 2Ns bytes (s >= 4) plus the workspace: below 0.77 of the
+    // footprint plus 1 KiB.  An arena of 4/5 of the budget plus 1 MiB
+    // therefore holds any request whose footprint is within the budget; an
+    // in-flight set whose workspaces do not fit together waits for a release
+    // (with nothing in flight the arena is empty, so the head request always
+    // fits eventually).
+    s->arena_bytes = std::min(budget_bytes, budget_bytes / 5 * 4 + ((size_t)1 << 20));
     s->arena_bytes = mgr::ArenaFit::round_up(s->arena_bytes);
     if (hipMalloc((void **)&s->arena, s->arena_bytes) != hipSuccess) {
       (void)hipGetLastError();
@@ -195,6 +209,16 @@ mgr_status mgr_service_submit(mgr_service *svc, int recompose, int ndim, const i
   mgr_status s = mgr_workspace_size(ndim, shape, dtype, nlevels, &ws);
   if (s != MGR_OK) return sfail(s, mgr_last_error());
   if (!in || !out) return sfail(MGR_ERR_INVALID_ARG, "in and out must be non-NULL device pointers");
+  // build (or find) the request's plan here, outside the service lock; a
+  // request whose arguments the library rejects fails when it is enqueued
+  // and reports its status through mgr_service_result
+  {
+    int cur = -1;
+    if (hipGetDevice(&cur) == hipSuccess && cur != svc->device) (void)hipSetDevice(svc->device);
+    (void)mgr::prepare_plan(ndim, shape, coords, nlevels);
+    if (cur >= 0 && cur != svc->device) (void)hipSetDevice(cur);
+    (void)hipGetLastError();
+  }
   try {
     auto r = std::make_unique<Request>();
     r->recompose = recompose != 0;
@@ -275,6 +299,13 @@ mgr_status mgr_service_destroy(mgr_service *svc) {
   }
   svc->cv.notify_all();
   for (auto &t : svc->waiters) t.join();
+  {
+    int cur = -1;
+    if (hipGetDevice(&cur) == hipSuccess && cur != svc->device) (void)hipSetDevice(svc->device);
+    // the recomposition helper streams the library registered for these streams
+    mgr::forget_helpers(svc->streams.data(), (int)svc->streams.size());
+    if (cur >= 0 && cur != svc->device) (void)hipSetDevice(cur);
+  }
   for (auto &s : svc->streams) (void)hipStreamDestroy(s);
   (void)hipFree(svc->arena);
   delete svc;

@@ -208,6 +208,21 @@ def alloc_workspace(shape, dtype, nlevels, device=None):
     return torch.empty(max(nb, 1), dtype=torch.uint8, device=device or "cuda")
 
 
+def _on_stream(made, stream, device) -> None:
+    """Tensors the binding allocated come from the current stream's pool of
+    PyTorch's caching allocator.  When the library's work runs on another
+    stream, record that stream on them, so that their blocks are not handed
+    out again before that work is done."""
+    import torch
+    if not made:
+        return
+    if not isinstance(stream, torch.cuda.Stream):  # a raw handle wrapper (any object with .cuda_stream)
+        stream = torch.cuda.ExternalStream(stream.cuda_stream, device=device)
+    if stream != torch.cuda.current_stream(device):
+        for t in made:
+            t.record_stream(stream)
+
+
 def _call(fn, x, coords, nlevels, out, workspace, stream):
     import torch
     if not (x.is_cuda and x.is_contiguous()):
@@ -215,11 +230,14 @@ def _call(fn, x, coords, nlevels, out, workspace, stream):
     shape = tuple(x.shape)
     if nlevels is None:
         nlevels = max_levels(shape)
+    made = []
     if out is None:
         out = torch.empty_like(x)
+        made.append(out)
     _check_pair(x, out)
     if workspace is None:
         workspace = alloc_workspace(shape, x.dtype, nlevels, device=x.device)
+        made.append(workspace)
     wsb = _workspace_bytes(workspace, x.device)
     if stream is None:
         stream = torch.cuda.current_stream(x.device)
@@ -232,6 +250,7 @@ def _call(fn, x, coords, nlevels, out, workspace, stream):
     del keep
     if s != MGR_OK:
         raise MgrError(s, last_error())
+    _on_stream(made, stream, x.device)
     return out
 
 
@@ -307,8 +326,10 @@ class Batch:
 def _call_batch(fn, batch: Batch, workspace, stream):
     import torch
     dev = batch.tensors[0][0].device
+    made = []
     if workspace is None:
         workspace = batch.alloc_workspace(dev)
+        made.append(workspace)
     wsb = _workspace_bytes(workspace, dev)
     if stream is None:
         stream = torch.cuda.current_stream(dev)
@@ -317,6 +338,7 @@ def _call_batch(fn, batch: Batch, workspace, stream):
                ctypes.c_size_t(wsb), ctypes.c_void_p(stream.cuda_stream))
     if s != MGR_OK:
         raise MgrError(s, last_error())
+    _on_stream(made, stream, dev)
 
 
 def decompose_batch(batch: Batch, workspace=None, stream=None) -> None:
@@ -350,8 +372,10 @@ def _classes(fn, x, nlevels, out, stream):
     shape = tuple(x.shape)
     if nlevels is None:
         nlevels = max_levels(shape)
+    made = []
     if out is None:
         out = torch.empty_like(x)
+        made.append(out)
     _check_pair(x, out)
     if stream is None:
         stream = torch.cuda.current_stream(x.device)
@@ -360,6 +384,7 @@ def _classes(fn, x, nlevels, out, stream):
                ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(stream.cuda_stream))
     if s != MGR_OK:
         raise MgrError(s, last_error())
+    _on_stream(made, stream, x.device)
     return out
 
 

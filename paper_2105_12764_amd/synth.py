@@ -100,31 +100,22 @@ def batch_specs(nfields: int = 64, seed0: int = 4000):
     return out
 
 
-# Cube sides of the service workload: 11 points geometrically spaced over
-# [17, 513] (ratio (513/17)^(1/10) ~ 1.406), rounded.
-SERVICE_SIDES = (17, 24, 34, 47, 66, 93, 131, 185, 260, 365, 513)
-
-
-def service_side_weights():
-    """Probabilities of SERVICE_SIDES: a side log-uniform over [17, 513],
-    discretised by the trapezoid rule in log(side) (end points half weight)."""
-    w = np.ones(len(SERVICE_SIDES))
-    w[0] = w[-1] = 0.5
-    return w / w.sum()
+# Cube sides of the service workload: integers, log-uniform over [17, 513].
+SERVICE_SIDE_MIN, SERVICE_SIDE_MAX = 17, 513
 
 
 def service_requests(nreq: int, seed: int = 5000):
     """The request stream of the service workload: request i has a 3-D cube
-    side drawn from SERVICE_SIDES with service_side_weights(), FP32 with
-    probability 3/4 (else FP64), recompose with probability 1/2 (else
-    decompose), and a unit-rate exponential gap before its arrival (divide the
-    running sum by the arrival rate for Poisson arrivals).
-    Returns [(side, dtype, recompose, gap)]."""
+    side round(exp(U[log 17, log 513])) (an integer, log-uniform over
+    [17, 513]), FP32 with probability 3/4 (else FP64), recompose with
+    probability 1/2 (else decompose), and a unit-rate exponential gap before
+    its arrival (divide the running sum by the arrival rate for Poisson
+    arrivals).  Returns [(side, dtype, recompose, gap)]."""
     rng = np.random.default_rng(seed)
-    p = service_side_weights()
-    sides = rng.choice(len(SERVICE_SIDES), size=nreq, p=p)
+    sides = np.rint(np.exp(rng.uniform(np.log(SERVICE_SIDE_MIN), np.log(SERVICE_SIDE_MAX), size=nreq)))
+    sides = np.clip(sides, SERVICE_SIDE_MIN, SERVICE_SIDE_MAX).astype(int)
     fp32 = rng.random(nreq) < 0.75
     rec = rng.random(nreq) < 0.5
     gaps = rng.exponential(1.0, size=nreq)
-    return [(SERVICE_SIDES[int(s)], np.float32 if f else np.float64, bool(r), float(g))
+    return [(int(s), np.float32 if f else np.float64, bool(r), float(g))
             for s, f, r, g in zip(sides, fp32, rec, gaps)]

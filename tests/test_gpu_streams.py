@@ -135,3 +135,102 @@ def test_recompose_from_more_caller_streams_than_helpers():
         torch.cuda.synchronize()
         for h in streams:
             hip.hipStreamDestroy(h)
+
+
+def test_captured_graph_outlives_the_plan_cache():
+    """A captured graph keeps the plans whose tables its kernels read: after
+    the cache is emptied and refilled with other plans, replays still give
+    the eager results bitwise.  Capturing a call whose plan is not cached is
+    refused (building it would allocate device memory) and leaves the capture
+    usable."""
+    print("\n[case] graph replay after the plan cache dropped its plans", flush=True)
+    u, ca = make_input((97, 65, 80), 95, nonuniform=True)
+    v, cb = make_input((300, 41), 96, nonuniform=True, dtype=np.float32)
+    w, cc = make_input((33, 47, 20), 97, nonuniform=False)
+    xa, xb, xc = (torch.from_numpy(t).cuda() for t in (u, v, w))
+    da, db, dc = (torch.empty_like(t) for t in (xa, xb, xc))
+    ra = torch.empty_like(xa)
+    wsa = mgr.alloc_workspace(tuple(xa.shape), xa.dtype, mgr.max_levels(tuple(xa.shape)))
+    batch = mgr.Batch([(xb, db, cb, None), (xc, dc, None, None)])
+    wsb = batch.alloc_workspace()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+
+    def work():
+        mgr.decompose(xa, ca, None, out=da, workspace=wsa, stream=side)
+        mgr.recompose(da, ca, None, out=ra, workspace=wsa, stream=side)
+        mgr.decompose_batch(batch, wsb, stream=side)
+
+    with torch.cuda.stream(side):
+        work()  # builds the plans and the helper stream outside the capture
+    torch.cuda.synchronize()
+    refs = [t.clone() for t in (da, ra, db, dc)]
+    fresh = torch.from_numpy(make_input((21, 22, 23), 98)[0]).cuda()
+    g = torch.cuda.CUDAGraph()
+    refused = None
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            try:
+                mgr.decompose(fresh, None, None, stream=side)
+            except mgr.MgrError as e:
+                refused = e
+            work()
+    torch.cuda.synchronize()
+    assert refused is not None and refused.status == mgr.MGR_ERR_UNSUPPORTED, refused
+    mgr.release_caches()
+    for i in range(1030):  # more plans than the cache keeps (1024)
+        t = torch.zeros((5 + i, 3), dtype=torch.float64, device="cuda")
+        mgr.decompose(t)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for t in (da, ra, db, dc):
+            t.fill_(-1.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for got, ref in zip((da, ra, db, dc), refs):
+            assert torch.equal(got, ref), f"replay {rep}"
+    del g
+    torch.cuda.synchronize()
+    mgr.decompose(fresh)  # an ordinary call after the graph is gone
+    torch.cuda.synchronize()
+
+
+def test_binding_workspace_survives_a_call_on_another_stream():
+    """A workspace (and output) that the binding allocates comes from the
+    current stream's allocator pool; when the call runs on another stream,
+    the block must not be handed out again before that stream's work is done.
+    The side stream is held back by a bounded spin kernel, so its work is
+    still pending when a same-sized tensor is allocated and filled on the
+    current stream."""
+    print("\n[case] binding-allocated workspace on a side stream", flush=True)
+    shape, nlev = (129, 129, 129), 7
+    u, coords = make_input(shape, 99, nonuniform=True)
+    x = torch.from_numpy(u).cuda()
+    ref = mgr.decompose(x, coords, nlev)
+    torch.cuda.synchronize()
+    seen = {}
+    real_alloc = mgr.alloc_workspace
+
+    def spy(*a, **k):
+        t = real_alloc(*a, **k)
+        seen["ws"] = (t.data_ptr(), t.numel())
+        return t
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        torch.cuda._sleep(50_000_000)  # bounded spin: keeps the side stream busy for a while
+    mgr.alloc_workspace = spy
+    try:
+        d = mgr.decompose(x, coords, nlev, stream=side)  # workspace and out from the current stream's pool
+    finally:
+        mgr.alloc_workspace = real_alloc
+    busy = not side.query()
+    other = torch.empty(seen["ws"][1], dtype=torch.uint8, device="cuda")
+    other.fill_(255)
+    if busy:
+        assert other.data_ptr() != seen["ws"][0], "workspace handed out while its stream still uses it"
+    side.synchronize()
+    torch.cuda.synchronize()
+    assert torch.equal(d, ref)

@@ -14,6 +14,10 @@ def test_service_stream_is_seeded_and_has_the_stated_mix():
     gaps = np.array([r[3] for r in a])
     assert abs(f32 - 0.75) < 0.03 and abs(rec - 0.5) < 0.03
     assert abs(gaps.mean() - 1.0) < 0.05
-    assert set(np.unique(sides)) <= set(synth.SERVICE_SIDES)
-    # discretised log-uniform side: mean of log(side) at the midpoint of the range
-    assert abs(np.log(sides).mean() - 0.5 * (np.log(17) + np.log(513))) < 0.08
+    assert sides.min() >= 17 and sides.max() <= 513 and np.all(sides == np.rint(sides))
+    # log-uniform integer side: mean of log(side) at the midpoint of the range,
+    # and about a quarter of the sides below exp(quarter point)
+    assert abs(np.log(sides).mean() - 0.5 * (np.log(17) + np.log(513))) < 0.05
+    q = np.exp(np.log(17) + 0.25 * (np.log(513) - np.log(17)))
+    assert abs(np.mean(sides < q) - 0.25) < 0.03
+    assert len(np.unique(sides)) > 300
