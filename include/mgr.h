@@ -137,6 +137,37 @@ mgr_status mgr_recompose(int ndim, const int64_t *shape,
                          void *workspace, size_t workspace_bytes,
                          void *stream);
 
+/* Decomposition that allocates nothing, for callers that cannot allocate
+ * device memory (tight serving loops, harnesses that forbid hipMalloc).
+ * Same result as mgr_decompose with the same arguments, bit for bit; the
+ * workspace and the plan tables live in a static device array of
+ * MGR_NOALLOC_SCRATCH_BYTES per device (held from the first call on a device
+ * until the process ends): the first MGR_NOALLOC_TABLE_BYTES hold the tables
+ * of the last request, the rest its workspace.
+ *   ndim        : 1..3 (4-D fields: MGR_ERR_UNSUPPORTED).
+ *   others      : as for mgr_decompose; there is no workspace argument.
+ * Errors: MGR_ERR_WORKSPACE, checked before any device call, when the
+ * request's workspace (mgr_workspace_size) exceeds
+ * MGR_NOALLOC_SCRATCH_BYTES - MGR_NOALLOC_TABLE_BYTES (e.g. 257^3 FP64 with
+ * all levels fits, 513^3 does not), or when its plan tables exceed
+ * MGR_NOALLOC_TABLE_BYTES; MGR_ERR_UNSUPPORTED when `stream` is capturing a
+ * graph; otherwise as for mgr_decompose.
+ * Behaviour: calls no device allocator.  A request whose shape, coords and
+ * level count differ from the previous call's on the device rebuilds the
+ * tables on the host and copies them into the scratch with one
+ * hipMemcpyAsync on `stream` from pageable host memory; the same request
+ * again copies nothing.  Every call on a device shares that device's
+ * scratch and leaves its contents there: calls that may run at the same
+ * time on one device (different streams, no ordering between them) race on
+ * it and give wrong results.  Calls ordered on one stream are safe.
+ * Per-kernel timing (mgr_timing_enable) does not record these launches. */
+#define MGR_NOALLOC_SCRATCH_BYTES (64u << 20)
+#define MGR_NOALLOC_TABLE_BYTES (4u << 20)
+mgr_status mgr_decompose_noalloc(int ndim, const int64_t *shape,
+                                 const double *const *coords, mgr_dtype dtype,
+                                 int nlevels, const void *in, void *out,
+                                 void *stream);
+
 /* Progressive (partial) recomposition (Sec. II-A: the coarse representation
  * plus the first classes of coefficients give an approximation whose error
  * falls as classes are added).  Recomposes with only the `nkeep` coarsest

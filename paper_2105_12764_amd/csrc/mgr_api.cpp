@@ -1,7 +1,7 @@
 // mgr_api.cpp -- the extern "C" boundary of libmgr (declared in include/mgr.h):
 // argument validation, the per-device plan cache and dispatch to the HIP
 // kernels.  No exception crosses the boundary.
-#include <hip/hip_runtime_api.h>
+#include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
@@ -17,6 +17,7 @@
 #include "mgr_kernels.hpp"
 #include "mgr_plan.hpp"
 #include "mgr_plan_cache.hpp"
+#include "mgr_timing.hpp"
 
 namespace {
 
@@ -585,6 +586,121 @@ mgr_status run_batch(bool dec, int nfields, const mgr_field *fields, void *ws, s
   }
 }
 
+// ------------------------------------------------------------ no-allocation entry point
+
+// Device scratch of mgr_decompose_noalloc: the plan tables of the last
+// request in the first kNoAllocTableBytes, the workspace after them.  One
+// copy per device, held until the process ends.  In host code `scratch`
+// names a host-side stand-in: only its device address (noalloc_scratch) is
+// ever passed to the GPU.
+constexpr size_t kNoAllocTableBytes = (size_t)MGR_NOALLOC_TABLE_BYTES;
+constexpr size_t kNoAllocBytes = (size_t)MGR_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+// Per device: the address of its copy of `scratch`, and the plan whose tables
+// the scratch holds (stream order decides what a later call finds there).
+struct NoAllocSlot {
+  int device = -1;
+  void *ptr = nullptr;
+  std::unique_ptr<PlanKey> key;
+  std::unique_ptr<mgr::Plan> plan;
+  std::mutex mu;
+};
+std::mutex g_namu;
+std::list<NoAllocSlot> g_noalloc;  // stable addresses
+
+// The slot of the current device; on its first use the device address of
+// `scratch` is looked up with that device current.
+mgr_status noalloc_slot(NoAllocSlot *&out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(MGR_ERR_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  }
+  std::lock_guard<std::mutex> lk(g_namu);
+  for (auto &s : g_noalloc)
+    if (s.device == dev) {
+      out = &s;
+      return MGR_OK;
+    }
+  void *ptr = nullptr;
+  e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    (void)hipGetLastError();
+    return fail(MGR_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  }
+  NoAllocSlot &s = g_noalloc.emplace_back();
+  s.device = dev;
+  s.ptr = ptr;
+  out = &s;
+  return MGR_OK;
+}
+
+mgr_status run_noalloc(int ndim, const int64_t *shape, const double *const *coords, int dtype, int nlevels,
+                       const void *in, void *out, void *stream) {
+  g_last_error.clear();
+  try {
+    int64_t n[mgr::kDims], nt = 1;
+    std::string why;
+    if (!split_shape(ndim, shape, n, nt, why)) return fail(MGR_ERR_INVALID_ARG, why);
+    if (ndim == 4) return fail(MGR_ERR_UNSUPPORTED, "mgr_decompose_noalloc takes 1-D to 3-D fields");
+    if (dtype != MGR_FLOAT32 && dtype != MGR_FLOAT64)
+      return fail(MGR_ERR_INVALID_ARG, "dtype must be MGR_FLOAT32 or MGR_FLOAT64");
+    const int ml = mgr::max_levels3(n);
+    if (nlevels < 0 || nlevels > ml)
+      return fail(MGR_ERR_INVALID_ARG, "nlevels must be in [0, " + std::to_string(ml) + "]");
+    // the size limit comes first, before any device call
+    const size_t need = mgr::workspace_bytes(n, nlevels, dtype == MGR_FLOAT64 ? 8 : 4);
+    const size_t room = kNoAllocBytes - kNoAllocTableBytes;
+    if (need > room)
+      return fail(MGR_ERR_WORKSPACE, "request needs " + std::to_string(need) +
+                                         " bytes of workspace; the static scratch of "
+                                         "mgr_decompose_noalloc holds " + std::to_string(room));
+    bool capturing = false;
+    mgr_status s = capture_state(stream, capturing);
+    if (s != MGR_OK) return s;
+    if (capturing)
+      return fail(MGR_ERR_UNSUPPORTED, "mgr_decompose_noalloc cannot be captured into a graph");
+    NoAllocSlot *slot = nullptr;
+    s = noalloc_slot(slot);
+    if (s != MGR_OK) return s;
+    char *ws = (char *)slot->ptr + kNoAllocTableBytes;
+    std::vector<std::vector<double>> cx;
+    s = validate(ndim, shape, coords, dtype, nlevels, in, out, ws, room, n, cx);
+    if (s != MGR_OK) return s;
+    std::lock_guard<std::mutex> lk(slot->mu);
+    PlanKey key{slot->device, ndim, {n[0], n[1], n[2]}, 1, nlevels, cx};
+    if (!slot->key || !(*slot->key == key)) {
+      slot->key.reset();
+      slot->plan.reset();
+      const mgr::TableTarget tgt{slot->ptr, kNoAllocTableBytes, stream};
+      std::string err;
+      int st = 0;
+      std::unique_ptr<mgr::Plan> p = mgr::build_plan(ndim, n, cx, nlevels, err, st, true, &tgt);
+      if (!p) return fail((mgr_status)st, err);
+      {
+        std::lock_guard<std::mutex> gl(g_mu);
+        if (auto t = g_tunes.find(TuneKey{slot->device, ndim, {n[0], n[1], n[2]}, 1, nlevels})) p->tune = *t;
+      }
+      slot->plan = std::move(p);
+      slot->key = std::make_unique<PlanKey>(key);
+    }
+    mgr::TimingOff quiet;
+    std::string err;
+    if (!mgr::enqueue_decompose(*slot->plan, dtype == MGR_FLOAT64, in, out, ws, stream, err)) {
+      slot->key.reset();  // the tables may not have arrived
+      slot->plan.reset();
+      return fail(MGR_ERR_DEVICE, err);
+    }
+    return MGR_OK;
+  } catch (const std::bad_alloc &) {
+    return fail(MGR_ERR_OUT_OF_MEMORY, "host allocation failed");
+  } catch (...) {
+    return fail(MGR_ERR_DEVICE, "unexpected internal failure");
+  }
+}
+
 }  // namespace
 
 namespace mgr {
@@ -675,6 +791,11 @@ mgr_status mgr_recompose(int ndim, const int64_t *shape, const double *const *co
                          size_t workspace_bytes, void *stream) {
   return run(false, ndim, shape, coords, (int)dtype, nlevels, in, out, workspace, workspace_bytes,
              stream);
+}
+
+mgr_status mgr_decompose_noalloc(int ndim, const int64_t *shape, const double *const *coords,
+                                 mgr_dtype dtype, int nlevels, const void *in, void *out, void *stream) {
+  return run_noalloc(ndim, shape, coords, (int)dtype, nlevels, in, out, stream);
 }
 
 mgr_status mgr_recompose_partial(int ndim, const int64_t *shape, const double *const *coords,

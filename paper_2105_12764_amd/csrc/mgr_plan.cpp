@@ -236,7 +236,8 @@ SolveTabs solve_tables(const std::vector<double> &X) {
 
 std::unique_ptr<Plan> build_plan(int ndim, const int64_t n[kDims],
                                  const std::vector<std::vector<double>> &coords,
-                                 int nlev, std::string &err, int &status, bool allow_tail) {
+                                 int nlev, std::string &err, int &status, bool allow_tail,
+                                 const TableTarget *target) {
   auto plan = std::make_unique<Plan>();
   plan->ndim = ndim;
   for (int k = 0; k < kDims; ++k) plan->n[k] = n[k];
@@ -417,14 +418,25 @@ std::unique_ptr<Plan> build_plan(int ndim, const int64_t n[kDims],
   // upload
   (void)hipGetDevice(&plan->device);
   plan->table_bytes = img.bytes.size();
-  if (hipMalloc(&plan->dev_tables, plan->table_bytes) != hipSuccess) {
-    (void)hipGetLastError();
-    plan->dev_tables = nullptr;
-    err = "hipMalloc of plan tables failed";
-    status = 4;
-    return nullptr;
+  char *base = nullptr;
+  if (target) {
+    if (plan->table_bytes > target->bytes) {
+      err = "plan tables need " + std::to_string(plan->table_bytes) + " bytes, more than the " +
+            std::to_string(target->bytes) + " bytes reserved for them";
+      status = 3;
+      return nullptr;
+    }
+    base = (char *)target->base;
+  } else {
+    if (hipMalloc(&plan->dev_tables, plan->table_bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      plan->dev_tables = nullptr;
+      err = "hipMalloc of plan tables failed";
+      status = 4;
+      return nullptr;
+    }
+    base = (char *)plan->dev_tables;
   }
-  char *base = (char *)plan->dev_tables;
   for (int s = 0; s <= nlev; ++s)
     for (int k = 0; k < kDims; ++k) {
       DimTabs &d = plan->lev[s].d[k];
@@ -454,8 +466,19 @@ std::unique_ptr<Plan> build_plan(int ndim, const int64_t n[kDims],
     plan->dev_tail_off = (const int64_t *)(base + hd_tail[1]);
     plan->dev_tail_dbl = (const double *)(base + hd_tail[2]);
   }
-  if (hipMemcpy(plan->dev_tables, img.bytes.data(), plan->table_bytes,
-                hipMemcpyHostToDevice) != hipSuccess) {
+  if (target) {
+    // from pageable host memory: the image is read before the call returns;
+    // the plan keeps it anyway
+    plan->host_image = std::move(img.bytes);
+    if (hipMemcpyAsync(base, plan->host_image.data(), plan->table_bytes, hipMemcpyHostToDevice,
+                       (hipStream_t)target->stream) != hipSuccess) {
+      (void)hipGetLastError();
+      err = "upload of plan tables failed";
+      status = 5;
+      return nullptr;
+    }
+  } else if (hipMemcpy(plan->dev_tables, img.bytes.data(), plan->table_bytes,
+                       hipMemcpyHostToDevice) != hipSuccess) {
     err = "upload of plan tables failed";
     status = 5;
     return nullptr;

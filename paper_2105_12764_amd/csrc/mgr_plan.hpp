@@ -84,8 +84,11 @@ struct Plan {
   int nlev = 0;
   std::vector<Level> lev;       // nlev + 1 entries; lev[nlev] has only nodal tables
   int device = -1;
-  void *dev_tables = nullptr;   // one device allocation holding every table
+  void *dev_tables = nullptr;   // one device allocation holding every table (owned)
   size_t table_bytes = 0;
+  // A plan built into caller-provided device memory (see TableTarget) owns no
+  // device allocation; it keeps the host image its tables were copied from.
+  std::vector<char> host_image;
   int64_t max_coarse = 0;       // elements of the largest coarse grid (level 1)
   int tail_start = 0;           // first level run by the single-workgroup tail kernels
   const TailLevel *dev_tail = nullptr;  // [nlev - tail_start + 1], inside dev_tables
@@ -118,12 +121,23 @@ int max_levels3(const int64_t n[kDims]);
 // Levels of a 4-D grid (nt time positions, space extents n).
 int max_levels4(int64_t nt, const int64_t n[kDims]);
 
-// Builds tables on the host and uploads them to the current device.
+// Device memory the caller provides for a plan's tables: `bytes` at `base`,
+// filled by one asynchronous host-to-device copy on `stream`.
+struct TableTarget {
+  void *base;
+  size_t bytes;
+  void *stream;  // hipStream_t
+};
+
+// Builds tables on the host and uploads them to the current device: into one
+// new device allocation (synchronous copy), or, with `target`, into the
+// caller's memory (no allocation; status 3 if the tables do not fit).
 // Returns nullptr and sets `err` on failure.  `allow_tail` false keeps every
 // level on the general kernels.
 std::unique_ptr<Plan> build_plan(int ndim, const int64_t n[kDims],
                                  const std::vector<std::vector<double>> &coords,
-                                 int nlev, std::string &err, int &status, bool allow_tail = true);
+                                 int nlev, std::string &err, int &status, bool allow_tail = true,
+                                 const TableTarget *target = nullptr);
 // A 4-D plan: coords holds the time coordinates, then the three space dims'.
 std::unique_ptr<Plan> build_plan4(int64_t nt, const int64_t n[kDims],
                                   const std::vector<std::vector<double>> &coords, int nlev,

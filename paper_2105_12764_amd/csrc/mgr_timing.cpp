@@ -60,9 +60,14 @@ void drain_locked() {
   g_pending.clear();
 }
 
+thread_local int g_quiet = 0;  // TimingOff guards active on this thread
+
 }  // namespace
 
-bool timing_enabled() { return g_on.load(std::memory_order_relaxed); }
+TimingOff::TimingOff() { ++g_quiet; }
+TimingOff::~TimingOff() { --g_quiet; }
+
+bool timing_enabled() { return g_quiet == 0 && g_on.load(std::memory_order_relaxed); }
 
 TimedLaunch::TimedLaunch(hipStream_t s, const std::string &name, double alg_bytes) : stream_(s) {
   if (!timing_enabled()) return;

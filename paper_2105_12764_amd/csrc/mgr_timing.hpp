@@ -9,6 +9,16 @@ namespace mgr {
 
 bool timing_enabled();
 
+// While one lives on a thread, launches from that thread are not timed (no
+// events are created or recorded).
+class TimingOff {
+ public:
+  TimingOff();
+  ~TimingOff();
+  TimingOff(const TimingOff &) = delete;
+  TimingOff &operator=(const TimingOff &) = delete;
+};
+
 // Brackets one kernel launch with HIP events on its stream when timing is
 // enabled; `alg_bytes` is the launch's algorithmic traffic (bytes the method
 // must move), accumulated per kernel name.

@@ -28,6 +28,9 @@ MGR_FLOAT32 = 0
 MGR_FLOAT64 = 1
 
 MGR_BATCH_STREAMS = 4
+# static device scratch of mgr_decompose_noalloc (include/mgr.h)
+MGR_NOALLOC_SCRATCH_BYTES = 64 << 20
+MGR_NOALLOC_TABLE_BYTES = 4 << 20
 
 _lib = None
 
@@ -69,6 +72,9 @@ def lib() -> ctypes.CDLL:
             fn.argtypes = [ctypes.c_int, i64p, dpp, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
             fn.restype = ctypes.c_int
+        L.mgr_decompose_noalloc.argtypes = [ctypes.c_int, i64p, dpp, ctypes.c_int, ctypes.c_int,
+                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        L.mgr_decompose_noalloc.restype = ctypes.c_int
         L.mgr_status_string.argtypes = [ctypes.c_int]
         L.mgr_status_string.restype = ctypes.c_char_p
         L.mgr_last_error.argtypes = []
@@ -262,6 +268,35 @@ def decompose(x, coords=None, nlevels: Optional[int] = None, out=None, workspace
 def recompose(x, coords=None, nlevels: Optional[int] = None, out=None, workspace=None, stream=None):
     """mgr_recompose (inverse of :func:`decompose`); returns ``out``."""
     return _call(lib().mgr_recompose, x, coords, nlevels, out, workspace, stream)
+
+
+def decompose_noalloc(x, coords=None, nlevels: Optional[int] = None, out=None, stream=None):
+    """mgr_decompose_noalloc: the decomposition with its workspace and plan
+    tables in the library's static device scratch (no device allocation in
+    the library; `out` is allocated here only when not given)."""
+    import torch
+    if not (x.is_cuda and x.is_contiguous()):
+        raise ValueError("input must be a contiguous (C order) HIP device tensor")
+    shape = tuple(x.shape)
+    if nlevels is None:
+        nlevels = max_levels(shape)
+    made = []
+    if out is None:
+        out = torch.empty_like(x)
+        made.append(out)
+    _check_pair(x, out)
+    if stream is None:
+        stream = torch.cuda.current_stream(x.device)
+    carr, keep = _coords_arg(shape, coords)
+    with torch.cuda.device(x.device):
+        s = lib().mgr_decompose_noalloc(len(shape), _shape(shape), carr, _dtype_code(x.dtype), int(nlevels),
+                                        ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                        ctypes.c_void_p(stream.cuda_stream))
+    del keep
+    if s != MGR_OK:
+        raise MgrError(s, last_error())
+    _on_stream(made, stream, x.device)
+    return out
 
 
 class Batch:

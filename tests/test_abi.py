@@ -232,3 +232,33 @@ def test_binding_rejects_mismatched_outputs_before_the_library():
         mgr.decompose(x)
     with pytest.raises(ValueError):
         mgr._check_pair(x, torch.zeros((5, 5, 5), dtype=torch.float64))
+
+
+def _noalloc(shape, nlev, dtype=mgr.MGR_FLOAT64):
+    L = mgr.lib()
+    return L.mgr_decompose_noalloc(len(shape), mgr._shape(shape), None, dtype, nlev, ctypes.c_void_p(4096),
+                                   ctypes.c_void_p(1 << 30), None)
+
+
+def test_noalloc_limits_are_checked_before_any_device_call():
+    # 513^3 FP64 needs 425 MB of workspace, beyond the static scratch: rejected
+    # with the size in the message, before the library touches a device
+    need = mgr.workspace_size((513, 513, 513), np.float64, 9)
+    assert need > mgr.MGR_NOALLOC_SCRATCH_BYTES - mgr.MGR_NOALLOC_TABLE_BYTES
+    assert _noalloc((513, 513, 513), 9) == mgr.MGR_ERR_WORKSPACE
+    assert str(need) in mgr.last_error()
+    # a single level of 513^3 needs three FP64 257^3 grids (408 MB): also too large
+    assert _noalloc((513, 513, 513), 1, mgr.MGR_FLOAT32) == mgr.MGR_ERR_WORKSPACE
+    assert _noalloc((9, 9, 9, 9), 1) == mgr.MGR_ERR_UNSUPPORTED
+    assert _noalloc((9, 9, 9), 5) == mgr.MGR_ERR_INVALID_ARG
+    assert _noalloc((1, 9, 9), 1) == mgr.MGR_ERR_INVALID_ARG
+    # the largest cube that fits with all levels, FP64
+    assert mgr.workspace_size((257, 257, 257), np.float64, 8) <= \
+        mgr.MGR_NOALLOC_SCRATCH_BYTES - mgr.MGR_NOALLOC_TABLE_BYTES
+
+
+def test_noalloc_limits_match_the_header():
+    txt = open(os.path.join(ROOT, "include", "mgr.h")).read()
+    assert re.search(r"#define MGR_NOALLOC_SCRATCH_BYTES \(64u << 20\)", txt)
+    assert re.search(r"#define MGR_NOALLOC_TABLE_BYTES \(4u << 20\)", txt)
+    assert mgr.MGR_NOALLOC_SCRATCH_BYTES == 64 << 20 and mgr.MGR_NOALLOC_TABLE_BYTES == 4 << 20
