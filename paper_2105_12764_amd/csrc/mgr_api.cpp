@@ -549,6 +549,11 @@ mgr_status run_batch(bool dec, int nfields, const mgr_field *fields, void *ws, s
         ok = false;
         err = std::string("hipStreamWaitEvent: ") + hipGetErrorString(hipGetLastError());
       }
+    // Batches keep the register-prefetch load-vector kernel (bitwise the same
+    // results): a HIP graph replay of a batch that used the ring kernel ended
+    // in a host segmentation fault inside the graph launch once, with no
+    // cause found in the kernel; until one is, batches do not use it.
+    const mgr::PlainLoadVector plain;
     for (int i : order) {
       if (!ok) break;
       const bool f64 = fields[i].dtype == MGR_FLOAT64;

@@ -446,6 +446,349 @@ __global__ void __launch_bounds__((kNTHR<T, DEC, NODAL>), LV_WAVES) k_loadvec(Lo
   }
 }
 
+// ------------------------------------------- finest-level load vector, LDS ring
+
+// Zeros read by the global-to-LDS loads of tile elements outside the grid (and,
+// in a recomposition, of the stored coarse values, which count as zero).
+__device__ __align__(16) double g_zero_words[2];
+
+// LDS-only workgroup barrier: waits for this wave's LDS operations, not for
+// its vector-memory loads, so global-to-LDS loads of later stages stay in
+// flight across it (__syncthreads would wait for them).  The asm is also a
+// compiler barrier for memory accesses.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// Waits until at most N vector-memory operations of this wave are
+// outstanding (lgkm and exp counters left free).
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt holds 6 bits");
+  __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+}
+
+typedef __attribute__((address_space(1))) const void *gmem_ptr;
+typedef __attribute__((address_space(3))) void *lds_ptr;
+
+// Finest-level decomposition step (coefficients and load vector), the
+// computation of k_loadvec on a level grid stored compactly in C order, with
+// the plane pairs staged differently: every
+// element of a staged plane comes straight from memory into LDS through
+// 4-byte global-to-LDS loads, and NST stages of plane pairs rotate, so the
+// loads of the next NST-1 steps are in flight while a step computes (the
+// register prefetch of k_loadvec keeps one).  An element outside the grid is
+// loaded from g_zero_words.
+// Each wave issues the same number of loads for every step (steps past the
+// chunk load zeros), so the wait for a stage is a fixed count.  One
+// workgroup per compute unit (147 KB of LDS at TJ = 16).
+//
+// Tiles: TJ x TK coarse rows x columns, except that the last tile along dim
+// 1 (dim 2) takes one more coarse row (column) when a single one would be
+// left over, as for every 2^k + 1 extent; its staged halo already holds the
+// fine nodes that row needs, and threads 0.. compute its load-vector
+// entries as extra items beside their own.
+template <int TJ>
+constexpr int kRingThr = TJ * TK;
+template <typename TS, int TJ>
+struct RingGeom {
+  static constexpr int NTHR = TJ * TK;
+  static constexpr int NJ = 2 * TJ + 3, NK = 2 * TK + 3;  // staged rows / columns (two-node halo)
+  static constexpr int NE = NJ * NK;
+  static constexpr int DW = (int)(sizeof(TS) / 4);         // 4-byte words per element
+  static constexpr int NSLOT = (DW * NE + NTHR - 1) / NTHR;  // loads per thread per plane
+  static constexpr int PLANE_WORDS = NSLOT * NTHR;          // padded stage plane
+  static constexpr int EPT = (NE + NTHR - 1) / NTHR;        // coefficient elements per thread
+  static constexpr int NG = NJ * (TK + 1);                  // dim-2 reduced rows of one plane
+};
+constexpr int RING_MAXTI = 130;  // coarse planes per workgroup at most (step table in LDS)
+
+template <typename T, typename TS, bool CO0, bool CO1, bool CO2, int TJ, int NST>
+__global__ void __launch_bounds__(kRingThr<TJ>, 1) k_loadvec_ring(LoadArgs<T, TS> a) {
+  using A = double;  // a decomposition computes in FP64 (see k_loadvec)
+  using P = TS;
+  using G = RingGeom<TS, TJ>;
+  constexpr int NTHR = G::NTHR, NJ = G::NJ, NK = G::NK, NE = G::NE, NSLOT = G::NSLOT;
+  constexpr int EPT = G::EPT, NG = G::NG, PW = G::PLANE_WORDS;
+  static_assert(CO0 && CO1 && CO2, "the ring kernel serves levels coarsened along every dim");
+  static_assert(NST == 3, "the step loop is unrolled for three stages");
+  static_assert(EPT <= 8, "the per-thread flags hold 4 bits for each of at most 8 tile elements");
+  // stages: plane b (coarse along dim 0) and plane a (fine along dim 0) of a step
+  __shared__ __align__(16) unsigned sA0[PW], sB0[PW], sA1[PW], sB1[PW], sA2[PW], sB2[PW];
+  __shared__ A sG[2 * NG];  // dim-2 reduced rows of b, then of a ([K][j], K <= TK)
+  __shared__ A sR1[NJ], sR2[NK];
+  __shared__ A sW[(TJ + 1 + TK + 1) * 5];
+  __shared__ A sK[CO0 ? (RING_MAXTI + 2) * 6 : 1];  // per-step dim-0 taps and fine-plane weight
+
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const int tile = xcd_tile(blockIdx.x, a.gx * a.gy * a.gz);
+  const int tx = tile % a.gx, ty = (tile / a.gx) % a.gy, tz = tile / (a.gx * a.gy);
+  const int64_t J0 = (int64_t)ty * TJ, K0 = (int64_t)tx * TK;
+  const int64_t I0 = (int64_t)tz * a.TI;
+  const int64_t I1 = min(I0 + a.TI, a.c0);
+  const int64_t fj0 = 2 * J0 - 2, fk0 = 2 * K0 - 2;
+  const bool lastJ = ty == a.gy - 1, lastK = tx == a.gx - 1, lastI = I1 >= a.c0;
+  // coarse rows / columns of this tile (TJ or TK, one more for an absorbed last one)
+  const int nJ = (int)min<int64_t>(a.c1 - J0, lastJ ? TJ + 1 : TJ);
+  const int nK = (int)min<int64_t>(a.c2 - K0, lastK ? TK + 1 : TK);
+  const int64_t ojb = 2 * J0, oje = lastJ ? a.m1 : 2 * (J0 + TJ);
+  const int64_t okb = 2 * K0, oke = lastK ? a.m2 : 2 * (K0 + TK);
+  const int64_t oib = (CO0 ? 2 : 1) * I0;
+  const int64_t oie = lastI ? a.m0 : (CO0 ? 2 : 1) * I1;
+
+  // word offsets of this thread's load slots in a plane (-1: load zero)
+  int off[NSLOT];
+#pragma unroll
+  for (int u = 0; u < NSLOT; ++u) {
+    const int w = u * NTHR + tid, e = w / G::DW, h = w % G::DW;
+    const int j = e / NK, k = e % NK;
+    const int64_t gj = fj0 + j, gk = fk0 + k;
+    off[u] = (e < NE && gj >= 0 && gj < a.m1 && gk >= 0 && gk < a.m2) ? (int)(gj * a.smap.s1 + gk) * G::DW + h
+                                                                       : -1;
+  }
+  // per-element constants of this thread's coefficient elements
+  enum : unsigned { F_IN = 1, F_OWN = 2, F_C1 = 4, F_C2 = 8 };
+  unsigned flags = 0;
+  int colS[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = tid + i * NTHR;
+    const int j = e / NK, k = e % NK;
+    const int64_t gj = fj0 + j, gk = fk0 + k;
+    unsigned f = 0;
+    colS[i] = 0;
+    if (e < NE && gj >= 0 && gj < a.m1 && gk >= 0 && gk < a.m2) {
+      f |= F_IN;
+      if (gj >= ojb && gj < oje && gk >= okb && gk < oke) f |= F_OWN;
+      if (coarse_pos<true>(gj, a.m1)) f |= F_C1;
+      if (coarse_pos<true>(gk, a.m2)) f |= F_C2;
+      colS[i] = (int)(gj * a.smap.s1 + gk);
+    }
+    flags |= f << (4 * i);
+  }
+  auto flag_of = [&](int i) -> unsigned { return (flags >> (4 * i)) & 15u; };
+
+  for (int j = tid; j < NJ; j += NTHR) {
+    const int64_t gj = fj0 + j;
+    sR1[j] = (gj >= 0 && gj < a.m1 && !coarse_pos<true>(gj, a.m1)) ? a.r1[gj] : A(0);
+  }
+  for (int k = tid; k < NK; k += NTHR) {
+    const int64_t gk = fk0 + k;
+    sR2[k] = (gk >= 0 && gk < a.m2 && !coarse_pos<true>(gk, a.m2)) ? a.r2[gk] : A(0);
+  }
+  // taps: rows 0..TJ (row TJ only if absorbed), then columns 0..TK
+  for (int e = tid; e < (TJ + 1) * 5; e += NTHR) sW[e] = (e / 5 < nJ) ? a.W1[J0 * 5 + e] : A(0);
+  for (int e = tid; e < (TK + 1) * 5; e += NTHR) sW[(TJ + 1) * 5 + e] = (e / 5 < nK) ? a.W2[K0 * 5 + e] : A(0);
+
+  // step schedule (as k_loadvec): with dim 0 coarsened, step I covers fine
+  // planes (2I+1, 2I+2) for I in [I0-2, I1-1] and emits F[I] for I >= I0
+  const int64_t sbeg = CO0 ? I0 - 2 : I0, send = I1;
+  auto planes = [&](int64_t I, int64_t &pa, int64_t &pb) {
+    if (I >= send) { pa = pb = -1; return; }
+    if (!CO0) { pa = -1; pb = I; return; }
+    pa = 2 * I + 1;
+    pb = 2 * I + 2;
+    if (!(pa >= 0 && pa < a.m0) || I < I0 - 1) pa = -1;
+    if (!(pb >= 0 && pb < a.m0)) pb = -1;
+    if (pa >= 0 && pb < 0) { pb = pa; pa = -1; }  // last plane of an even extent is coarse
+  };
+  if (CO0) {
+    for (int q = tid; q < (int)(send - sbeg) * 6; q += NTHR) {
+      const int64_t I = sbeg + q / 6;
+      const int o = q % 6;
+      A v = A(0);
+      if (o < 5) {
+        v = a.W0[min(max(I, (int64_t)0), a.c0 - 1) * 5 + o];
+      } else {
+        int64_t pa, pb;
+        planes(I, pa, pb);
+        if (pa >= 0) v = a.r0[pa];
+      }
+      sK[q] = v;
+    }
+  }
+  __syncthreads();
+
+  // this thread's taps of its dim-2 column and dim-1 row
+  constexpr int RG = NTHR / TK, RPT = (NJ + RG - 1) / RG;
+  const int rK = tid / RG, rj0 = tid % RG;
+  const int hJ = tid / TK, hK = tid % TK;
+  A w1r[5], w2r[5];
+#pragma unroll
+  for (int o = 0; o < 5; ++o) {
+    w2r[o] = sW[(TJ + 1) * 5 + rK * 5 + o];
+    w1r[o] = sW[hJ * 5 + o];
+  }
+  // extra items of an absorbed row / column: item x < nx is the load-vector
+  // entry (xj, xk) in tile coordinates, taken by thread x
+  const bool xcol = nK > TK, xrow = nJ > TJ;
+  const int ncol = xcol ? nJ : 0;           // column TK, rows 0 .. nJ-1
+  const int nx = ncol + (xrow ? min(nK, TK) : 0);  // then row TJ, columns 0 .. TK-1
+  const bool hasx = tid < nx;
+  const int xj = tid < ncol ? tid : TJ, xk = tid < ncol ? TK : tid - ncol;
+  A xw1[5];
+#pragma unroll
+  for (int o = 0; o < 5; ++o) xw1[o] = hasx ? sW[xj * 5 + o] : A(0);
+
+  const bool hOK = hJ < nJ && hK < nK;
+  auto reduce2 = [&](const P *sp, int off) {
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int j = rj0 + q * RG;
+      if (j < NJ) {
+        A g = A(0);
+        if (rK < nK) {
+          const P *row = sp + j * NK + 2 * rK;
+#pragma unroll
+          for (int o = 0; o < 5; ++o) g = fma(w2r[o], (A)row[o], g);
+        }
+        sG[off + rK * NJ + j] = g;
+      }
+    }
+    if (xcol && tid < NJ) {  // column TK: fine columns 2TK .. 2TK+2 of the tile
+      const P *row = sp + tid * NK + 2 * TK;
+      A g = A(0);
+#pragma unroll
+      for (int o = 0; o < 3; ++o) g = fma(sW[(TJ + 1) * 5 + TK * 5 + o], (A)row[o], g);
+      sG[off + TK * NJ + tid] = g;
+    }
+  };
+  // P^T M along dim 1 of the reduced rows at sG + off for entry (j, k) with taps w
+  auto reduce1 = [&](int off, int j, int k, const A (&w)[5]) -> A {
+    const A *col = sG + off + k * NJ + 2 * j;
+    if (j == TJ) {  // absorbed row: fine rows 2TJ .. 2TJ+2
+      A h = A(0);
+#pragma unroll
+      for (int o = 0; o < 3; ++o) h = fma(w[o], col[o], h);
+      return h;
+    }
+    A h = A(0);
+#pragma unroll
+    for (int o = 0; o < 5; ++o) h = fma(w[o], col[o], h);
+    return h;
+  };
+
+  // bilinear interpolant (dims 1, 2) of tile element e of the staged plane
+  auto interp2 = [&](const P *sp, int e, unsigned f) -> A {
+    if (!(f & F_IN)) return A(0);
+    const int dk = (f & F_C2) ? 0 : 1, dj = (f & F_C1) ? 0 : NK;
+    const A rk = sR2[e % NK], rj = sR1[e / NK];
+    return lerp(lerp((A)sp[e - dj - dk], (A)sp[e - dj + dk], rk), lerp((A)sp[e + dj - dk], (A)sp[e + dj + dk], rk),
+                rj);
+  };
+
+  // global-to-LDS loads of step J's planes into stage (dA, dB); every wave
+  // issues 2 NSLOT loads whatever J is
+  const char *zero = (const char *)g_zero_words;
+  auto issue = [&](unsigned *dA, unsigned *dB, int64_t J) {
+    int64_t pa, pb;
+    planes(J, pa, pb);
+    const char *bb = pb >= 0 ? (const char *)(a.src + pb * a.smap.s0) : zero;
+    const char *ba = pa >= 0 ? (const char *)(a.src + pa * a.smap.s0) : zero;
+#pragma unroll
+    for (int u = 0; u < NSLOT; ++u) {
+      const char *src = (pb >= 0 && off[u] >= 0) ? bb + (int64_t)off[u] * 4 : zero;
+      __builtin_amdgcn_global_load_lds((gmem_ptr)src, (lds_ptr)(dA + u * NTHR + wave * 64), 4, 0, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < NSLOT; ++u) {
+      const char *src = (pa >= 0 && off[u] >= 0) ? ba + (int64_t)off[u] * 4 : zero;
+      __builtin_amdgcn_global_load_lds((gmem_ptr)src, (lds_ptr)(dB + u * NTHR + wave * 64), 4, 0, 0);
+    }
+  };
+
+  A piPrev[EPT], piNext[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) piPrev[i] = piNext[i] = A(0);
+  A h0 = A(0), h1 = A(0), h2 = A(0), h3 = A(0), h4 = A(0);
+  A x0 = A(0), x1 = A(0), x2 = A(0), x3 = A(0), x4 = A(0);  // window of the extra item
+
+  // one step: issue step I + NST - 1 into the stage step I - 1 used, wait for
+  // step I's stage, compute
+  auto step = [&](int64_t I, const unsigned *cA, const unsigned *cB, unsigned *rA, unsigned *rB) {
+    issue(rA, rB, I + NST - 1);
+    wait_vm<2 * NSLOT * (NST - 1)>();
+    lds_barrier();
+    const P *pA = (const P *)cA, *pB = (const P *)cB;
+    int64_t pa, pb;
+    planes(I, pa, pb);
+    const bool b_in_a_slot = CO0 && pb >= 0 && pb == 2 * I + 1;
+    const A *kst = sK + (CO0 ? (I - sbeg) * 6 : 0);
+    if (pb >= 0) reduce2(pA, 0);
+    if (pa >= 0) reduce2(pB, NG);
+    if (pb >= 0) {
+      const bool own_p = pb >= oib && pb < oie;
+      T *oo = a.out + pb * a.omap.s0;
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) {
+        const int e = tid + i * NTHR;
+        const unsigned f = e < NE ? flag_of(i) : 0u;
+        piNext[i] = interp2(pA, e, f);
+        // the finest level also writes its coarse nodes (coefficient exactly
+        // 0, overwritten by the next level) so that every written row is whole
+        if (own_p && (f & F_OWN)) oo[colS[i]] = (T)((A)pA[e] - piNext[i]);
+      }
+    }
+    if (pa >= 0) {
+      const bool own_p = pa >= oib && pa < oie;
+      T *oo = a.out + pa * a.omap.s0;
+      const A r0 = kst[5];
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) {
+        const int e = tid + i * NTHR;
+        if (e < NE && own_p && (flag_of(i) & F_OWN)) oo[colS[i]] = (T)((A)pB[e] - lerp(piPrev[i], piNext[i], r0));
+      }
+    }
+    lds_barrier();
+    const A hb = (pb >= 0 && hOK) ? reduce1(0, hJ, hK, w1r) : A(0);
+    const A ha = (pa >= 0 && hOK) ? reduce1(NG, hJ, hK, w1r) : A(0);
+    const A xb = (pb >= 0 && hasx) ? reduce1(0, xj, xk, xw1) : A(0);
+    const A xa = (pa >= 0 && hasx) ? reduce1(NG, xj, xk, xw1) : A(0);
+    if (CO0) {
+      h0 = h2; h1 = h3; h2 = h4;
+      h3 = b_in_a_slot ? hb : ha;
+      h4 = b_in_a_slot ? A(0) : hb;
+      x0 = x2; x1 = x3; x2 = x4;
+      x3 = b_in_a_slot ? xb : xa;
+      x4 = b_in_a_slot ? A(0) : xb;
+      if (I >= I0) {
+        if (hOK) {
+          A f = kst[0] * h0;
+          f = fma(kst[1], h1, f);
+          f = fma(kst[2], h2, f);
+          f = fma(kst[3], h3, f);
+          f = fma(kst[4], h4, f);
+          a.F[(I * a.c1 + J0 + hJ) * a.c2 + K0 + hK] = f;
+        }
+        if (hasx) {
+          A f = kst[0] * x0;
+          f = fma(kst[1], x1, f);
+          f = fma(kst[2], x2, f);
+          f = fma(kst[3], x3, f);
+          f = fma(kst[4], x4, f);
+          a.F[(I * a.c1 + J0 + xj) * a.c2 + K0 + xk] = f;
+        }
+      }
+    } else {
+      if (hOK) a.F[(I * a.c1 + J0 + hJ) * a.c2 + K0 + hK] = hb;
+      if (hasx) a.F[(I * a.c1 + J0 + xj) * a.c2 + K0 + xk] = xb;
+    }
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) piPrev[i] = piNext[i];
+  };
+
+  issue(sA0, sB0, sbeg);
+  issue(sA1, sB1, sbeg + 1);
+  int64_t I = sbeg;
+  for (; I + 2 < send; I += 3) {
+    step(I, sA0, sB0, sA2, sB2);
+    step(I + 1, sA1, sB1, sA0, sB0);
+    step(I + 2, sA2, sB2, sA1, sB1);
+  }
+  if (I < send) step(I, sA0, sB0, sA2, sB2);
+  if (I + 1 < send) step(I + 1, sA1, sB1, sA0, sB0);
+  wait_vm<0>();  // no load may still write this workgroup's LDS when it ends
+}
+
 // ------------------------------------------------------------ correction solves
 
 struct SolveDev {
@@ -1652,6 +1995,50 @@ double solve_bytes(double nc, int mode) {
   return 8.0 * nc + sizeof(T) * nc;                             // read F, write grid
 }
 
+// Tiles along a dimension of c coarse positions: the last tile absorbs a
+// single left-over position (the ring kernel's extra row or column).
+inline int ring_tiles(int64_t c, int t) { return (int)(c > t && c % t == 1 ? c / t : (c + t - 1) / t); }
+
+template <typename T, typename TS, int TJ>
+void launch_loadvec_ring(LoadArgs<T, TS> a, Ctx &cx) {
+  constexpr int NTHR = kRingThr<TJ>;
+  static const int slots = resident_slots((const void *)k_loadvec_ring<T, TS, true, true, true, TJ, 3>, NTHR);
+  a.gx = ring_tiles(a.c2, TK);
+  a.gy = ring_tiles(a.c1, TJ);
+  const int64_t tiles = (int64_t)a.gx * a.gy;
+  a.TI = cx.ti_req > 0 ? std::min<int64_t>(std::min<int64_t>(cx.ti_req, RING_MAXTI), a.c0)
+                       : pick_chunk(a.c0, tiles, slots, 2, RING_MAXTI);
+  cx.slots_out = slots;
+  cx.ti_out = (int)a.TI;
+  if (cx.dry) return;
+  a.gz = (int)((a.c0 + a.TI - 1) / a.TI);
+  const dim3 grid((unsigned)(tiles * a.gz));
+  double bytes = 0.0;
+  if (timing_enabled()) {
+    const double nl = (double)a.m0 * a.m1 * a.m2, nc = (double)a.c0 * a.c1 * a.c2;
+    // read the level grid, write the coefficients and f
+    bytes = nl * sizeof(TS) + (nl - nc) * sizeof(T) + 8.0 * nc;
+  }
+  TimedLaunch tl(cx.stream, std::string("k_loadvec_ring<") + tname<T>() + ", " + tname<TS>() + ">", bytes);
+  hipLaunchKernelGGL((k_loadvec_ring<T, TS, true, true, true, TJ, 3>), grid, dim3(NTHR), 0, cx.stream, a);
+}
+
+thread_local int g_plain_lv = 0;  // PlainLoadVector guards active on this thread
+
+// Whether the ring kernel takes this level: a decomposition of the finest
+// level grid (stored compactly in C order), FP64, coarsened along every
+// dimension, not a time slice of a 4-D field.  (The recomposition keeps
+// k_loadvec: its finest-level load vector runs on the helper stream beside
+// the coarser levels, whose small kernels need free compute units, which a
+// ring workgroup's 147 KB of LDS leaves none of; measured at 513^3 FP64 the
+// ring took 0.388 ms there against 0.352, and the coarser levels' load
+// vectors beside it 0.479 against 0.297.)
+template <typename T, typename TS, bool DEC>
+bool ring_applies(const Level &L, const LoadArgs<T, TS> &a) {
+  return DEC && g_plain_lv == 0 && sizeof(TS) == 8 && a.omap.t0 == nullptr && L.co[0] && L.co[1] && L.co[2] &&
+         a.out != nullptr;
+}
+
 template <typename T, typename TS, bool DEC>
 void launch_loadvec(const Level &L, LoadArgs<T, TS> a, Ctx &cx) {
   a.m0 = L.m[0]; a.m1 = L.m[1]; a.m2 = L.m[2];
@@ -1659,6 +2046,13 @@ void launch_loadvec(const Level &L, LoadArgs<T, TS> a, Ctx &cx) {
   a.r0 = L.d[0].r; a.r1 = L.d[1].r; a.r2 = L.d[2].r;
   a.W0 = L.d[0].W; a.W1 = L.d[1].W; a.W2 = L.d[2].W;
   a.gx = (int)((a.c2 + TK - 1) / TK);  // a.gy: by the kernel's tile, in launch_loadvec_t
+  if constexpr (DEC && sizeof(T) == 8 && sizeof(TS) == 8) {
+    if (ring_applies<T, TS, DEC>(L, a)) {
+      launch_loadvec_ring<T, TS, 16>(a, cx);
+      cx.check("k_loadvec_ring launch");
+      return;
+    }
+  }
   const int key = (L.co[0] ? 4 : 0) | (L.co[1] ? 2 : 0) | (L.co[2] ? 1 : 0);
   // on coarser levels the field-side array (decompose: out; recompose: src)
   // goes through the nodal tables
@@ -2407,8 +2801,13 @@ bool autotune_t(Plan &pl, const T *in, T *out, void *ws, hipStream_t stream, std
     const double nl = (double)L.m[0] * L.m[1] * L.m[2];
     const int halo_lv = L.co[0] ? 2 : 0;
     for (int dec = 1; dec >= 0 && cx.ok; --dec) {
-      const int tj = tile_rows<T>(dec != 0, s > 0);  // the field-side array is nodal below level 0
-      const int64_t tiles_lv = ((L.c[2] + TK - 1) / TK) * ((L.c[1] + tj - 1) / tj);
+      // the finest FP64 level runs the ring kernel (its tiles absorb a single
+      // left-over row or column); other levels k_loadvec, whose field-side
+      // array is nodal below level 0
+      const bool ring = dec && s == 0 && sizeof(T) == 8 && L.co[0] && L.co[1] && L.co[2] && g_plain_lv == 0;
+      const int tj = ring ? 16 : tile_rows<T>(dec != 0, s > 0);
+      const int64_t tiles_lv = ring ? (int64_t)ring_tiles(L.c[2], TK) * ring_tiles(L.c[1], tj)
+                                    : ((L.c[2] + TK - 1) / TK) * ((L.c[1] + tj - 1) / tj);
       // level s's load vector as the decomposition (FP64 level grid from
       // level 1 on) or the recomposition launches it
       auto lv = [&]() {
@@ -2444,9 +2843,10 @@ bool autotune_t(Plan &pl, const T *in, T *out, void *ws, hipStream_t stream, std
       const int slots = cx.slots_out, ti0 = cx.ti_out;
       const double per_plane = (dec ? 2.0 * nl * es : nl * es) / (double)L.c[0];
       std::vector<std::pair<double, int>> cand;
-      const int64_t maxti = std::min<int64_t>((LV_MAXP - 3) / 2, L.c[0]);
-      for (int64_t ti : {(int64_t)ti0, (int64_t)1, (int64_t)2, (int64_t)4, (int64_t)6, (int64_t)8, (int64_t)12,
-                         (int64_t)16, (int64_t)24, (int64_t)32, (int64_t)48, maxti}) {
+      const int64_t maxti = std::min<int64_t>(ring ? RING_MAXTI : (LV_MAXP - 3) / 2, L.c[0]);
+      std::vector<int64_t> tis = {(int64_t)ti0, 1, 2, 4, 6, 8, 12, 16, 24, 32, 48, maxti};
+      for (int64_t k = 1; k <= 8; ++k) tis.push_back((L.c[0] + k - 1) / k);  // extent split evenly
+      for (int64_t ti : tis) {
         if (ti < 1 || ti > maxti) continue;
         bool dup = false;
         for (auto &c : cand) dup |= c.second == (int)ti;
@@ -2567,6 +2967,9 @@ bool enqueue_copy_probe(const void *src, void *dst, size_t bytes, void *stream, 
   }
   return true;
 }
+
+PlainLoadVector::PlainLoadVector() { ++g_plain_lv; }
+PlainLoadVector::~PlainLoadVector() { --g_plain_lv; }
 
 bool enqueue_decompose(const Plan &pl, bool f64, const void *in, void *out, void *ws, void *stream,
                        std::string &err) {

@@ -28,6 +28,17 @@ struct StreamFork {
 bool enqueue_recompose(const Plan &pl, bool f64, const void *in, void *out, void *ws, void *stream,
                        std::string &err, int nkeep = -1, const StreamFork *fk = nullptr);
 
+// While one lives on a thread, launches from that thread use the
+// register-prefetch load-vector kernel on every level (the batched entry
+// points take it; results are bitwise those of the ring kernel).
+class PlainLoadVector {
+ public:
+  PlainLoadVector();
+  ~PlainLoadVector();
+  PlainLoadVector(const PlainLoadVector &) = delete;
+  PlainLoadVector &operator=(const PlainLoadVector &) = delete;
+};
+
 // Reorder a nodal representation into class-contiguous order (export) or
 // back (import); src and dst hold prod(shape) elements each.
 bool enqueue_classes(const Plan &pl, bool f64, bool export_, const void *src, void *dst, void *stream,
