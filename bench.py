@@ -260,7 +260,9 @@ def _pct(v, q):
 
 def run_batched(reps: int = 10, warmup: int = 2, nfields: int = 64):
     """The mixed batch (synth.batch_specs): one field per call vs. the batched
-    entry points vs. the batch captured in a HIP graph."""
+    entry points with grouped launches (one grid per kernel and level step
+    across the fields) and with per-field chains on internal streams, each
+    also replayed from a HIP graph."""
     import torch
 
     from paper_2105_12764_amd import mgr
@@ -296,9 +298,12 @@ def run_batched(reps: int = 10, warmup: int = 2, nfields: int = 64):
             mgr.decompose(x, None, n, out=y, workspace=ws1, stream=stream)
             mgr.recompose(y, None, n, out=z, workspace=ws1, stream=stream)
 
-    def batched(st=None):
-        mgr.decompose_batch(bd, ws2, stream=st or stream)
-        mgr.recompose_batch(br, ws2, stream=st or stream)
+    def batched(st=None, per_field=False):
+        mgr.decompose_batch(bd, ws2, stream=st or stream, per_field=per_field)
+        mgr.recompose_batch(br, ws2, stream=st or stream, per_field=per_field)
+
+    def per_field(st=None):
+        batched(st, per_field=True)
 
     def timed(fn, n):
         out = []
@@ -313,23 +318,41 @@ def run_batched(reps: int = 10, warmup: int = 2, nfields: int = 64):
 
     for _ in range(warmup):
         serial()
+        per_field()
         batched()
     torch.cuda.synchronize()
     t_serial = timed(serial, reps)
+    t_pf = timed(per_field, reps)
     t_batch = timed(batched, reps)
-    g = torch.cuda.CUDAGraph()
-    side = torch.cuda.Stream(dev)
-    side.wait_stream(stream)
-    with torch.cuda.stream(side):
-        with torch.cuda.graph(g, stream=side):
-            batched(side)
-    torch.cuda.synchronize()
-    for _ in range(warmup):
-        g.replay()
-    torch.cuda.synchronize()
-    t_graph = timed(g.replay, reps)
+
+    def graph_of(fn):
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream(dev)
+        side.wait_stream(stream)
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(g, stream=side):
+                fn(side)
+        torch.cuda.synchronize()
+        for _ in range(warmup):
+            g.replay()
+        torch.cuda.synchronize()
+        return g
+
+    g_pf = graph_of(per_field)
+    t_pf_graph = timed(g_pf.replay, reps)
+    g = graph_of(batched)
+    t_graph = timed(g.replay, reps)  # the grouped batch's results stay in d2, r2
     same = all(torch.equal(a, b) for a, b in zip(d1, d2)) and all(torch.equal(a, b) for a, b in zip(r1, r2))
     err = max(float((z.double() - x.double()).abs().max() / x.double().abs().max()) for x, z in zip(xs, r2))
+    # kernel launches per batch in each mode (every launch of the library is timed)
+    launches = {}
+    for name, fn in (("one_field_per_call", serial), ("per_field", per_field), ("grouped", batched)):
+        mgr.timing_reset()
+        mgr.timing_enable(True)
+        fn()
+        torch.cuda.synchronize()
+        mgr.timing_enable(False)
+        launches[name] = int(sum(v[0] for v in mgr.timing_totals().values()))
 
     def stats(v):
         return {"p50": round(_pct(v, 0.5), 4), "p99": round(_pct(v, 0.99), 4),
@@ -340,13 +363,18 @@ def run_batched(reps: int = 10, warmup: int = 2, nfields: int = 64):
            "n_2d": sum(1 for s in specs if len(s[0]) == 2),
            "n_fp64": sum(1 for s in specs if s[1] == np.float64),
            "bytes_per_batch": nbytes, "reps": reps,
-           "one_field_per_call_ms": stats(t_serial), "batched_ms": stats(t_batch),
-           "batched_graph_ms": stats(t_graph),
-           "speedup_batched_graph_vs_one_field_per_call": round(_pct(t_serial, 0.5) / _pct(t_graph, 0.5), 3),
+           "one_field_per_call_ms": stats(t_serial),
+           "per_field_streams_ms": stats(t_pf), "per_field_streams_graph_ms": stats(t_pf_graph),
+           "grouped_ms": stats(t_batch), "grouped_graph_ms": stats(t_graph),
+           "launches_per_batch": launches,
+           "speedup_grouped_graph_vs_one_field_per_call": round(_pct(t_serial, 0.5) / _pct(t_graph, 0.5), 3),
+           "speedup_grouped_graph_vs_per_field_graph": round(_pct(t_pf_graph, 0.5) / _pct(t_graph, 0.5), 3),
            "bitwise_equal_to_single_calls": bool(same), "roundtrip_max_rel_err": err}
-    _log(f"[bench] batch: one field per call {res['one_field_per_call_ms']['p50']:.3f} ms, batched "
-         f"{res['batched_ms']['p50']:.3f} ms, graph {res['batched_graph_ms']['p50']:.3f} ms")
-    del xs, d1, r1, d2, r2, ws1, ws2, g
+    _log(f"[bench] batch: one field per call {res['one_field_per_call_ms']['p50']:.3f} ms, per-field streams "
+         f"{res['per_field_streams_ms']['p50']:.3f} ms (graph {res['per_field_streams_graph_ms']['p50']:.3f}), "
+         f"grouped {res['grouped_ms']['p50']:.3f} ms (graph {res['grouped_graph_ms']['p50']:.3f}); "
+         f"launches {launches}")
+    del xs, d1, r1, d2, r2, ws1, ws2, g, g_pf
     torch.cuda.empty_cache()
     return res
 

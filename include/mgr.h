@@ -277,17 +277,20 @@ mgr_status mgr_batch_workspace_size(int nfields, const mgr_field *fields, size_t
  *   fields    : host array of nfields descriptors, read during the call.
  *   workspace : device pointer, >= mgr_batch_workspace_size bytes, 256-byte
  *               aligned, caller-owned; not overlapping any field's in or out.
- *   stream    : the call is ordered on `stream` like a single call: its
- *               work starts after the work already enqueued there, and work
- *               enqueued there afterwards starts after all of it.  Inside,
- *               the fields' level sequences are spread over
- *               MGR_BATCH_STREAMS internal streams (default priority),
- *               forked from `stream` and joined back with events, so small
- *               fields run side by side and the whole call can be captured
- *               into one HIP graph (plans must exist first: make one
- *               uncaptured call with the same fields before capturing, with
- *               at most 256 distinct plans in the batch so that they all
- *               stay cached).
+ *   stream    : the call is ordered on `stream` like a single call.  The
+ *               fields' launch chains are aligned by level (finest first in
+ *               a decomposition, coarsest first in a recomposition), and for
+ *               each step of a level the launches of one kernel across all
+ *               fields go out as one grid over their workgroups (the jobs'
+ *               arguments travel in the kernel arguments), in order on
+ *               `stream`: a handful of launches per level for the whole
+ *               batch instead of several per field and level (Sec. III-B/D:
+ *               small grids batched into one launch).  The call can be
+ *               captured into one HIP graph (plans must exist first: make
+ *               one uncaptured call with the same fields before capturing,
+ *               with at most 1024 distinct plans in the batch so that they
+ *               all stay cached).  Results are bitwise those of the
+ *               single-field calls.
  * Besides every check of mgr_decompose per field (the detail names the
  * field), no field's out may overlap another field's in or out.  All checks
  * happen before anything is enqueued; on error nothing is launched. */
@@ -298,6 +301,17 @@ mgr_status mgr_decompose_batch(int nfields, const mgr_field *fields, void *works
  * representation, `out` the field).  As mgr_decompose_batch otherwise. */
 mgr_status mgr_recompose_batch(int nfields, const mgr_field *fields, void *workspace,
                                size_t workspace_bytes, void *stream);
+
+/* The batched calls with flags: 0 is mgr_decompose_batch /
+ * mgr_recompose_batch; MGR_BATCH_PER_FIELD runs each field's own launch chain
+ * instead, the chains spread over MGR_BATCH_STREAMS internal streams (default
+ * priority) forked from `stream` and joined back with events (also
+ * capturable; bitwise the same results).  Other bits: MGR_ERR_INVALID_ARG. */
+#define MGR_BATCH_PER_FIELD 1
+mgr_status mgr_decompose_batch_ex(int nfields, const mgr_field *fields, void *workspace,
+                                  size_t workspace_bytes, void *stream, int flags);
+mgr_status mgr_recompose_batch_ex(int nfields, const mgr_field *fields, void *workspace,
+                                  size_t workspace_bytes, void *stream, int flags);
 
 /* ---- Refactoring service ----------------------------------------------------
  * A stream of independent decompose / recompose requests on caller-owned

@@ -478,7 +478,7 @@ bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
 }
 
 mgr_status run_batch(bool dec, int nfields, const mgr_field *fields, void *ws, size_t ws_bytes,
-                     void *stream) {
+                     void *stream, int flags) {
   g_last_error.clear();
   try {
     std::vector<FieldJob> jobs;
@@ -511,6 +511,20 @@ mgr_status run_batch(bool dec, int nfields, const mgr_field *fields, void *ws, s
     for (int i = 0; i < nfields; ++i) {
       s = get_plan(jobs[i].n, fields[i].ndim, fields[i].nlevels, jobs[i].cx, jobs[i].plan, stream);
       if (s != MGR_OK) return fail(s, field_tag(i) + g_last_error);
+    }
+    std::vector<std::shared_ptr<mgr::Plan>> plans;
+    for (auto &j : jobs)
+      if (std::find(plans.begin(), plans.end(), j.plan) == plans.end()) plans.push_back(j.plan);
+    if (!(flags & MGR_BATCH_PER_FIELD)) {
+      // grouped launches on `stream`
+      std::vector<mgr::BatchItem> items;
+      items.reserve(nfields);
+      for (int i = 0; i < nfields; ++i)
+        items.push_back(mgr::BatchItem{jobs[i].plan.get(), fields[i].dtype == MGR_FLOAT64, fields[i].in, fields[i].out,
+                                       ws ? (void *)((char *)ws + jobs[i].ws_off) : nullptr});
+      std::string err;
+      if (!mgr::enqueue_batch(dec, items, stream, err)) return fail(MGR_ERR_DEVICE, err);
+      return retain_for_capture(stream, plans);
     }
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess) {
@@ -580,9 +594,6 @@ mgr_status run_batch(bool dec, int nfields, const mgr_field *fields, void *ws, s
       }
     }
     if (!ok) return fail(MGR_ERR_DEVICE, err);
-    std::vector<std::shared_ptr<mgr::Plan>> plans;
-    for (auto &j : jobs)
-      if (std::find(plans.begin(), plans.end(), j.plan) == plans.end()) plans.push_back(j.plan);
     return retain_for_capture(stream, plans);
   } catch (const std::bad_alloc &) {
     return fail(MGR_ERR_OUT_OF_MEMORY, "host allocation failed");
@@ -932,12 +943,30 @@ mgr_status mgr_batch_workspace_size(int nfields, const mgr_field *fields, size_t
 
 mgr_status mgr_decompose_batch(int nfields, const mgr_field *fields, void *workspace,
                                size_t workspace_bytes, void *stream) {
-  return run_batch(true, nfields, fields, workspace, workspace_bytes, stream);
+  return run_batch(true, nfields, fields, workspace, workspace_bytes, stream, 0);
 }
 
 mgr_status mgr_recompose_batch(int nfields, const mgr_field *fields, void *workspace,
                                size_t workspace_bytes, void *stream) {
-  return run_batch(false, nfields, fields, workspace, workspace_bytes, stream);
+  return run_batch(false, nfields, fields, workspace, workspace_bytes, stream, 0);
+}
+
+mgr_status mgr_decompose_batch_ex(int nfields, const mgr_field *fields, void *workspace,
+                                  size_t workspace_bytes, void *stream, int flags) {
+  if (flags & ~MGR_BATCH_PER_FIELD) {
+    g_last_error = "unknown flags";
+    return MGR_ERR_INVALID_ARG;
+  }
+  return run_batch(true, nfields, fields, workspace, workspace_bytes, stream, flags);
+}
+
+mgr_status mgr_recompose_batch_ex(int nfields, const mgr_field *fields, void *workspace,
+                                  size_t workspace_bytes, void *stream, int flags) {
+  if (flags & ~MGR_BATCH_PER_FIELD) {
+    g_last_error = "unknown flags";
+    return MGR_ERR_INVALID_ARG;
+  }
+  return run_batch(false, nfields, fields, workspace, workspace_bytes, stream, flags);
 }
 
 mgr_status mgr_probe_copy(const void *src, void *dst, size_t bytes, void *stream) {

@@ -29,7 +29,10 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <cstring>
+#include <functional>
 #include <string>
+#include <vector>
 
 #include "mgr_kernels.hpp"
 #include "mgr_plan.hpp"
@@ -127,6 +130,30 @@ __device__ __forceinline__ int xcd_tile(int bid, int nb) {
   return (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + local;
 }
 
+// ------------------------------------------------------------ grouped launches
+
+// Up to N independent jobs of one kernel in a single launch (the batched
+// entry points): the jobs' argument structs travel in the kernel arguments,
+// and job i takes blocks [start[i], start[i+1]) of the grid.
+constexpr int kGroupArgBytes = 3584;  // budget for the jobs' arguments (kernel arguments stay below 4 KB)
+template <typename J>
+struct Group {
+  static constexpr int N = (kGroupArgBytes - 8) / (int)(sizeof(J) + 4) > 0 ? (kGroupArgBytes - 8) / (int)(sizeof(J) + 4) : 1;
+  J job[N];
+  int start[N + 1];
+  int njobs;
+};
+
+// Job and block of this workgroup within a group: blocks are numbered so that
+// each XCD walks a contiguous run (xcd_tile), then located by the prefix sums.
+template <typename J>
+__device__ __forceinline__ void group_locate(const Group<J> &g, int &j, int &b) {
+  const int t = xcd_tile(blockIdx.x, g.start[g.njobs]);
+  j = 0;
+  while (j + 1 < g.njobs && g.start[j + 1] <= t) ++j;
+  b = t - g.start[j];
+}
+
 // One workgroup owns a (TJ x TK) tile of the coarse grid in dims (1, 2) and
 // a chunk of TI coarse planes along dim 0.  It walks the fine planes in
 // steps of two -- fine plane a = 2I+1 and coarse plane b = 2I+2 -- with the
@@ -144,7 +171,7 @@ __device__ __forceinline__ int xcd_tile(int bid, int nb) {
 // Recomposition stages the stored coefficients (zero at the coarse nodes)
 // and forms f = (P^T M)^{(x)3} C the same way.
 template <typename T, typename TS, bool DEC, bool NODAL, bool CO0, bool CO1, bool CO2>
-__global__ void __launch_bounds__((kNTHR<T, DEC, NODAL>), LV_WAVES) k_loadvec(LoadArgs<T, TS> a) {
+__device__ __forceinline__ void loadvec_body(const LoadArgs<T, TS> &a, const int tile) {
   // a decomposition forms its coefficients as differences of nearly equal
   // values, so it computes in FP64 whatever the storage type
   using A = std::conditional_t<DEC, double, Acc<T>>;
@@ -170,7 +197,6 @@ __global__ void __launch_bounds__((kNTHR<T, DEC, NODAL>), LV_WAVES) k_loadvec(Lo
   __shared__ A sStep[2][6];                // per-step dim-0 taps and weight
 
   const int tid = threadIdx.x;
-  const int tile = xcd_tile(blockIdx.x, a.gx * a.gy * a.gz);
   const int tx = tile % a.gx, ty = (tile / a.gx) % a.gy, tz = tile / (a.gx * a.gy);
   const int64_t J0 = (int64_t)ty * TJ, K0 = (int64_t)tx * TK;
   const int64_t I0 = (int64_t)tz * a.TI;
@@ -446,6 +472,17 @@ __global__ void __launch_bounds__((kNTHR<T, DEC, NODAL>), LV_WAVES) k_loadvec(Lo
   }
 }
 
+template <typename T, typename TS, bool DEC, bool NODAL, bool CO0, bool CO1, bool CO2>
+__global__ void __launch_bounds__((kNTHR<T, DEC, NODAL>), LV_WAVES) k_loadvec(LoadArgs<T, TS> a) {
+  loadvec_body<T, TS, DEC, NODAL, CO0, CO1, CO2>(a, xcd_tile(blockIdx.x, a.gx * a.gy * a.gz));
+}
+template <typename T, typename TS, bool DEC, bool NODAL, bool CO0, bool CO1, bool CO2>
+__global__ void __launch_bounds__((kNTHR<T, DEC, NODAL>), LV_WAVES) k_loadvec_group(Group<LoadArgs<T, TS>> g) {
+  int j, b;
+  group_locate(g, j, b);
+  loadvec_body<T, TS, DEC, NODAL, CO0, CO1, CO2>(g.job[j], b);
+}
+
 // ------------------------------------------- finest-level load vector, LDS ring
 
 // Zeros read by the global-to-LDS loads of tile elements outside the grid (and,
@@ -466,8 +503,17 @@ __device__ __forceinline__ void wait_vm() {
   __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | (0x7 << 4) | (0xF << 8));
 }
 
-typedef __attribute__((address_space(1))) const void *gmem_ptr;
 typedef __attribute__((address_space(3))) void *lds_ptr;
+
+// One 4-byte global-to-LDS load per lane: lane i's word at `src` goes to LDS
+// byte address lds + 4 i (`lds` wave-uniform).  Written as asm so that the
+// compiler does not see the LDS write: it would otherwise wait for every
+// such load in flight before reading any staged plane whose independence it
+// cannot prove.  The kernel's own vmcnt waits and LDS barriers order the
+// loads with the reads.  One wait state between writing M0 and the load.
+__device__ __forceinline__ void lds_dma_dword(const void *src, unsigned lds) {
+  asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dword %1, off" : : "s"(lds), "v"(src) : "memory", "m0");
+}
 
 // Finest-level decomposition step (coefficients and load vector), the
 // computation of k_loadvec on a level grid stored compactly in C order, with
@@ -684,15 +730,16 @@ __global__ void __launch_bounds__(kRingThr<TJ>, 1) k_loadvec_ring(LoadArgs<T, TS
     planes(J, pa, pb);
     const char *bb = pb >= 0 ? (const char *)(a.src + pb * a.smap.s0) : zero;
     const char *ba = pa >= 0 ? (const char *)(a.src + pa * a.smap.s0) : zero;
+    const unsigned la = (unsigned)(uintptr_t)(lds_ptr)dA, lb = (unsigned)(uintptr_t)(lds_ptr)dB;
 #pragma unroll
     for (int u = 0; u < NSLOT; ++u) {
       const char *src = (pb >= 0 && off[u] >= 0) ? bb + (int64_t)off[u] * 4 : zero;
-      __builtin_amdgcn_global_load_lds((gmem_ptr)src, (lds_ptr)(dA + u * NTHR + wave * 64), 4, 0, 0);
+      lds_dma_dword(src, __builtin_amdgcn_readfirstlane(la + 4u * (u * NTHR + wave * 64)));
     }
 #pragma unroll
     for (int u = 0; u < NSLOT; ++u) {
       const char *src = (pa >= 0 && off[u] >= 0) ? ba + (int64_t)off[u] * 4 : zero;
-      __builtin_amdgcn_global_load_lds((gmem_ptr)src, (lds_ptr)(dB + u * NTHR + wave * 64), 4, 0, 0);
+      lds_dma_dword(src, __builtin_amdgcn_readfirstlane(lb + 4u * (u * NTHR + wave * 64)));
     }
   };
 
@@ -913,19 +960,29 @@ __host__ __device__ constexpr int tables_size(int cp, int P) { return 5 * cp + 5
 // Lines along dim 0 or 1: lane = position along the contiguous dim 2,
 // wave = partition.  Element q of partition p of line (outer, k) sits at
 // F[outer * so + k + (p*S + q) * sp].
-// (five waves per SIMD keep two 9-wave workgroups resident per CU at S = 32)
+template <typename T>
+struct StridedArgs {
+  double *F;
+  int64_t c, nk, sp, so, c1, c2;
+  int P, axis;
+  SolveDev tb;
+  Epi<T> ep;
+};
+
+// Blocks of 64 lines in (outer, k-block) order; `blk` is numbered so that
+// consecutive ones run on one XCD: neighbouring k-blocks share the cache
+// lines at their ends.
 template <typename T, int S>
-__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5))) k_solve_strided(double *F, int64_t c, int P, int64_t nk,
-                                                        int64_t sp_, int64_t so, int axis,
-                                                        int64_t c1, int64_t c2, SolveDev tb,
-                                                        Epi<T> ep) {
+__device__ __forceinline__ void strided_body(const StridedArgs<T> &A, const int blk) {
+  double *F = A.F;
+  const int64_t c = A.c, nk = A.nk, sp_ = A.sp, so = A.so;
+  const int P = A.P, axis = A.axis;
+  const SolveDev &tb = A.tb;
+  const Epi<T> &ep = A.ep;
   extern __shared__ double xs[];
   const int lane = threadIdx.x & 63;
   const int p = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  // blocks of 64 lines in (outer, k-block) order, consecutive ones on one XCD:
-  // neighbouring k-blocks share the cache lines at their ends
   const int nkb = (int)((nk + 63) / 64);
-  const int blk = xcd_tile(blockIdx.x, gridDim.x);
   const int64_t k = (int64_t)(blk % nkb) * 64 + lane;
   const int64_t outer = blk / nkb;
   const bool active = k < nk;
@@ -978,6 +1035,19 @@ __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5))) 
   }
 }
 
+// (five waves per SIMD keep two 9-wave workgroups resident per CU at S = 32)
+template <typename T, int S>
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5))) k_solve_strided(StridedArgs<T> a) {
+  strided_body<T, S>(a, xcd_tile(blockIdx.x, gridDim.x));
+}
+template <typename T, int S>
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5))) k_solve_strided_group(
+    Group<StridedArgs<T>> g) {
+  int j, b;
+  group_locate(g, j, b);
+  strided_body<T, S>(g.job[j], b);
+}
+
 // Threads of a row-solver workgroup at most: its LDS budget keeps blocks small
 // anyway, and the cap leaves each thread room for a whole partition in
 // registers.
@@ -987,9 +1057,23 @@ constexpr int ROWS_THR = 256;
 // LDS (a straight coalesced copy: consecutive rows are contiguous), thread
 // (r, p) solves partition p of row r in registers.  Persistent over blocks
 // of R rows.
+template <typename T>
+struct RowsArgs {
+  double *F;
+  int64_t nrows, c1;
+  int c, P, R;
+  SolveDev tg;
+  Epi<T> ep;
+};
+
+// Blocks first, first + stride, ... of R rows.
 template <typename T, int S>
-__global__ void __launch_bounds__(ROWS_THR) k_solve_rows(double *F, int64_t nrows, int c, int P, int R,
-                                                     int64_t c1, SolveDev tg, Epi<T> ep) {
+__device__ __forceinline__ void rows_body(const RowsArgs<T> &A, const int64_t first, const int64_t stride) {
+  double *F = A.F;
+  const int64_t nrows = A.nrows, c1 = A.c1;
+  const int c = A.c, P = A.P, R = A.R;
+  const SolveDev &tg = A.tg;
+  const Epi<T> &ep = A.ep;
   extern __shared__ double sm[];
   const int t = threadIdx.x, nt = blockDim.x;
   const SolveDev tb = stage_tables(sm, tg, P * S, P, t, nt);
@@ -1001,7 +1085,7 @@ __global__ void __launch_bounds__(ROWS_THR) k_solve_rows(double *F, int64_t nrow
   const int nload = p < P - 1 ? S : (int)(c - f);
   const int nint = p < P - 1 ? S - 1 : nload;
   const int64_t nblocks = (nrows + R - 1) / R;
-  for (int64_t blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
+  for (int64_t blk = first; blk < nblocks; blk += stride) {
     const int64_t row0 = blk * R;
     const int nr = (int)min<int64_t>(R, nrows - row0);
     const int64_t gbase = row0 * c;
@@ -1063,6 +1147,18 @@ __global__ void __launch_bounds__(ROWS_THR) k_solve_rows(double *F, int64_t nrow
   }
 }
 
+template <typename T, int S>
+__global__ void __launch_bounds__(ROWS_THR) k_solve_rows(RowsArgs<T> a) {
+  rows_body<T, S>(a, blockIdx.x, gridDim.x);
+}
+// one block per workgroup (not persistent)
+template <typename T, int S>
+__global__ void __launch_bounds__(ROWS_THR) k_solve_rows_group(Group<RowsArgs<T>> g) {
+  int j, b;
+  group_locate(g, j, b);
+  rows_body<T, S>(g.job[j], b, (int64_t)1 << 62);
+}
+
 // Lines of more than kMaxBlocks partitions of 64 (up to kLongBlocks): the
 // same partitioned solve, with each wave taking partitions w, w + LONG_WAVES,
 // ... in turn.  The interior solutions wait in F between the elimination and
@@ -1071,18 +1167,29 @@ __global__ void __launch_bounds__(ROWS_THR) k_solve_rows(double *F, int64_t nrow
 // the contiguous one (each lane walks its own row).
 constexpr int LONG_WAVES = 8;
 template <typename T>
-__global__ void __launch_bounds__(64 * LONG_WAVES) k_solve_long(double *F, int64_t c, int P, int64_t nk,
-                                                                int64_t sp_, int64_t so, int64_t sk,
-                                                                int axis, int64_t c1, SolveDev tb,
-                                                                Epi<T> ep) {
+struct LongArgs {
+  double *F;
+  int64_t c, nk, sp, so, sk, c1;
+  int P, axis;
+  SolveDev tb;
+  Epi<T> ep;
+};
+
+// Blocks of 64 lines in (outer, k-block) order; this workgroup takes block `blk`.
+template <typename T>
+__device__ __forceinline__ void long_body(const LongArgs<T> &A, const int64_t blk) {
+  double *F = A.F;
+  const int64_t c = A.c, nk = A.nk, sp_ = A.sp, so = A.so, sk = A.sk, c1 = A.c1;
+  const int P = A.P, axis = A.axis;
+  const SolveDev &tb = A.tb;
+  const Epi<T> &ep = A.ep;
   constexpr int S = 64;
   extern __shared__ double xs[];  // yF, yL, Fs, t: [P][64] each
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  // blocks of 64 lines in (outer, k-block) order on a one-dimensional grid
   const int64_t nkb = (nk + 63) / 64;
-  const int64_t k = ((int64_t)blockIdx.x % nkb) * 64 + lane;
-  const int64_t outer = (int64_t)blockIdx.x / nkb;
+  const int64_t k = (blk % nkb) * 64 + lane;
+  const int64_t outer = blk / nkb;
   const bool active = k < nk;
   const int64_t base = outer * so + (active ? k : 0) * sk;
   double *yF = xs, *yL = xs + P * 64, *Fs = xs + 2 * P * 64, *tt = xs + 3 * P * 64;
@@ -1124,6 +1231,17 @@ __global__ void __launch_bounds__(64 * LONG_WAVES) k_solve_long(double *F, int64
       epi_store(ep, F, idx, i, j, kk, v);
     }
   }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64 * LONG_WAVES) k_solve_long(LongArgs<T> a) {
+  long_body<T>(a, blockIdx.x);
+}
+template <typename T>
+__global__ void __launch_bounds__(64 * LONG_WAVES) k_solve_long_group(Group<LongArgs<T>> g) {
+  int j, b;
+  group_locate(g, j, b);
+  long_body<T>(g.job[j], b);
 }
 
 // Sequential Thomas per line (lines longer than kLongBlocks partitions of
@@ -1188,7 +1306,7 @@ struct ReconArgs {
 };
 
 template <typename T, bool NODALC, bool CO0, bool CO1, bool CO2>
-__global__ void __launch_bounds__(RC_THR) k_reconstruct(ReconArgs<T> a) {
+__device__ __forceinline__ void reconstruct_body(const ReconArgs<T> &a, const int tile) {
   using A = Acc<T>;
   constexpr int SJ = CO1 ? 2 : 1, SK = CO2 ? 2 : 1;
   const int FJ = SJ * a.TJ, FK = SK * a.TK;  // owned fine tile (host: FJ * FK <= RC_NE)
@@ -1205,7 +1323,6 @@ __global__ void __launch_bounds__(RC_THR) k_reconstruct(ReconArgs<T> a) {
   __shared__ A sR0[2];                      // dim-0 weight of the step's fine plane
 
   const int tid = threadIdx.x;
-  const int tile = xcd_tile(blockIdx.x, a.gx * a.gy * a.gz);
   const int tx = tile % a.gx, ty = (tile / a.gx) % a.gy, tz = tile / (a.gx * a.gy);
   const int64_t J0 = (int64_t)ty * a.TJ, K0 = (int64_t)tx * a.TK;
   const int64_t I0 = (int64_t)tz * a.TI;
@@ -1372,6 +1489,17 @@ __global__ void __launch_bounds__(RC_THR) k_reconstruct(ReconArgs<T> a) {
     for (int i = 0; i < RC_EPT; ++i) piPrev[i] = piNext[i];
     buf ^= 1;
   }
+}
+
+template <typename T, bool NODALC, bool CO0, bool CO1, bool CO2>
+__global__ void __launch_bounds__(RC_THR) k_reconstruct(ReconArgs<T> a) {
+  reconstruct_body<T, NODALC, CO0, CO1, CO2>(a, xcd_tile(blockIdx.x, a.gx * a.gy * a.gz));
+}
+template <typename T, bool NODALC, bool CO0, bool CO1, bool CO2>
+__global__ void __launch_bounds__(RC_THR) k_reconstruct_group(Group<ReconArgs<T>> g) {
+  int j, b;
+  group_locate(g, j, b);
+  reconstruct_body<T, NODALC, CO0, CO1, CO2>(g.job[j], b);
 }
 
 template <typename T>
@@ -1763,8 +1891,13 @@ __device__ __forceinline__ int64_t tail_off(const TailLevel &L, const int64_t *s
 // Decomposition of levels tail_start .. nlev-1.  src: level grid of the first
 // tail level, compact; out: the caller's output array (nodal positions).
 template <typename T, typename TS>
-__global__ void __launch_bounds__(TAIL_THR) k_tail_dec(const TS *__restrict__ src, T *__restrict__ out,
-                                                       TailArgs a) {
+struct TailDecJob {
+  const TS *src;
+  T *out;
+  TailArgs a;
+};
+template <typename T, typename TS>
+__device__ __forceinline__ void tail_dec_body(const TS *__restrict__ src, T *__restrict__ out, const TailArgs &a) {
   __shared__ TailSmem sm;
   auto buf = [&](int b) { return sm.g + b * kTailNodes; };
   tail_load_tables(sm, a);
@@ -1803,9 +1936,26 @@ __global__ void __launch_bounds__(TAIL_THR) k_tail_dec(const TS *__restrict__ sr
 
 // Recomposition of levels nlev-1 .. tail_start.  in: the caller's input
 // (nodal positions); dst: level grid of the first tail level, compact.
-template <typename T>
-__global__ void __launch_bounds__(TAIL_THR) k_tail_rec(const T *__restrict__ in, T *__restrict__ dst,
+template <typename T, typename TS>
+__global__ void __launch_bounds__(TAIL_THR) k_tail_dec(const TS *__restrict__ src, T *__restrict__ out,
                                                        TailArgs a) {
+  tail_dec_body<T, TS>(src, out, a);
+}
+// one field's tail per workgroup
+template <typename T, typename TS>
+__global__ void __launch_bounds__(TAIL_THR) k_tail_dec_group(Group<TailDecJob<T, TS>> g) {
+  const TailDecJob<T, TS> &q = g.job[blockIdx.x];
+  tail_dec_body<T, TS>(q.src, q.out, q.a);
+}
+
+template <typename T>
+struct TailRecJob {
+  const T *in;
+  T *dst;
+  TailArgs a;
+};
+template <typename T>
+__device__ __forceinline__ void tail_rec_body(const T *__restrict__ in, T *__restrict__ dst, const TailArgs &a) {
   __shared__ TailSmem sm;
   auto buf = [&](int b) { return sm.g + b * kTailNodes; };
   tail_load_tables(sm, a);
@@ -1871,8 +2021,38 @@ __global__ void __launch_bounds__(TAIL_THR) k_tail_rec(const T *__restrict__ in,
     ia = ig;
   }
 }
+template <typename T>
+__global__ void __launch_bounds__(TAIL_THR) k_tail_rec(const T *__restrict__ in, T *__restrict__ dst,
+                                                       TailArgs a) {
+  tail_rec_body<T>(in, dst, a);
+}
+template <typename T>
+__global__ void __launch_bounds__(TAIL_THR) k_tail_rec_group(Group<TailRecJob<T>> g) {
+  const TailRecJob<T> &q = g.job[blockIdx.x];
+  tail_rec_body<T>(q.in, q.dst, q.a);
+}
 
 // ------------------------------------------------------------ host launch
+
+// One launch of a field's chain, recorded instead of launched (batched
+// entry points): the batch engine launches the recorded jobs of many fields
+// that share a kernel and a phase as one grouped launch.
+struct RecJob {
+  int phase = 0;  // a field's jobs come in increasing phase order
+  // grouped launcher of this job's kernel (nullptr: launch `direct` alone)
+  void (*group)(const std::vector<const struct RecJob *> &, hipStream_t, size_t, unsigned) = nullptr;
+  int gmax = 1;       // jobs per grouped launch at most
+  unsigned threads = 0;
+  size_t lds = 0;     // dynamic LDS
+  int64_t blocks = 0;
+  std::vector<unsigned char> args;         // the job's argument struct
+  std::function<void(hipStream_t)> direct;  // launch without grouping
+  std::string label;
+  double bytes = 0.0;
+};
+struct Rec {
+  std::vector<RecJob> jobs;
+};
 
 struct Ctx {
   hipStream_t stream;
@@ -1883,6 +2063,8 @@ struct Ctx {
   bool dry = false;   // compute the launch shape only, launch nothing
   int slots_out = 0;  // resident workgroups of the kernel instance chosen
   int ti_out = 0;     // coarse planes per workgroup chosen
+  Rec *rec = nullptr; // record the launches instead (batched entry points)
+  int phase = 0;      // phase of the next recorded launch
   void check(const char *what) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess && ok) {
@@ -1891,6 +2073,66 @@ struct Ctx {
     }
   }
 };
+
+// Phases of a field's chain: level s of a decomposition takes 8s (load
+// vector), 8s+1.. (solves); its tail comes last.  A recomposition starts with
+// its tail (phase 0), then level s takes kPhaseRecLevel(s) (load vector),
+// +1.. (solves) and +4 (reconstruct).
+constexpr int kPhaseTail = 8 * (kMaxLevels + 1);
+constexpr int phase_dec_level(int s) { return 8 * s; }
+constexpr int phase_rec_level(int s) { return 8 * (kMaxLevels + 1 - s); }
+
+// Launches up to Group<J>::N recorded jobs of kernel K as one grid.
+template <typename J, void (*K)(Group<J>)>
+void group_launch(const std::vector<const RecJob *> &js, hipStream_t st, size_t lds, unsigned threads) {
+  Group<J> g;
+  std::memset(&g, 0, sizeof(g));
+  int64_t tot = 0;
+  const int n = (int)js.size();
+  for (int i = 0; i < n; ++i) {
+    std::memcpy((void *)&g.job[i], js[i]->args.data(), sizeof(J));
+    g.start[i] = (int)tot;
+    tot += js[i]->blocks;
+  }
+  g.start[n] = (int)tot;
+  g.njobs = n;
+  hipLaunchKernelGGL(K, dim3((unsigned)tot), dim3(threads), lds, st, g);
+}
+
+// Launches through `direct`, or records the job when the context records.
+template <typename J, void (*K)(Group<J>), typename F>
+void emit(Ctx &cx, const J &job, int64_t blocks, unsigned threads, size_t lds, std::string label, double bytes,
+          F &&direct) {
+  if (!cx.rec) {
+    direct();
+    return;
+  }
+  RecJob r;
+  r.phase = cx.phase;
+  r.group = &group_launch<J, K>;
+  r.gmax = Group<J>::N;
+  r.threads = threads;
+  r.lds = lds;
+  r.blocks = blocks;
+  r.args.resize(sizeof(J));
+  std::memcpy(r.args.data(), (const void *)&job, sizeof(J));
+  r.label = std::move(label);
+  r.bytes = bytes;
+  cx.rec->jobs.push_back(std::move(r));
+}
+
+// A launch with no grouped form: now, or recorded to run alone in its phase
+// (`fn` must own what it uses).
+inline void emit_direct(Ctx &cx, std::function<void(hipStream_t)> fn) {
+  if (!cx.rec) {
+    fn(cx.stream);
+    return;
+  }
+  RecJob r;
+  r.phase = cx.phase;
+  r.direct = std::move(fn);
+  cx.rec->jobs.push_back(std::move(r));
+}
 
 template <typename T>
 const char *tname() { return sizeof(T) == 8 ? "double" : "float"; }
@@ -1959,7 +2201,7 @@ void launch_loadvec_t(LoadArgs<T, TS> a, Ctx &cx) {
   a.gz = (int)((a.c0 + a.TI - 1) / a.TI);
   const dim3 grid((unsigned)(tiles * a.gz));
   double bytes = 0.0;
-  if (timing_enabled()) {
+  if (timing_enabled() || cx.rec) {
     const double nl = (double)a.m0 * a.m1 * a.m2, nc = (double)a.c0 * a.c1 * a.c2;
     // recompose: read the coefficients, write f
     // decompose: read the level grid, write the coefficients and f
@@ -1968,12 +2210,14 @@ void launch_loadvec_t(LoadArgs<T, TS> a, Ctx &cx) {
     else if (DEC) bytes = nl * sizeof(TS) + (nl - nc) * sizeof(T) + 8.0 * nc;
     else bytes = (nl - nc) * sizeof(TS) + 8.0 * nc;
   }
-  TimedLaunch tl(cx.stream,
-                 std::string("k_loadvec<") + tname<T>() + ", " + tname<TS>() + ", " + bname(DEC) + ", " +
-                     bname(NODAL) + ", " + bname(C0) + ", " + bname(C1) + ", " + bname(C2) + ">",
-                 bytes);
-  hipLaunchKernelGGL((k_loadvec<T, TS, DEC, NODAL, C0, C1, C2>), grid, dim3(kNTHR<T, DEC, NODAL>), 0, cx.stream,
-                     a);
+  std::string label = std::string("k_loadvec<") + tname<T>() + ", " + tname<TS>() + ", " + bname(DEC) + ", " +
+                      bname(NODAL) + ", " + bname(C0) + ", " + bname(C1) + ", " + bname(C2) + ">";
+  emit<LoadArgs<T, TS>, k_loadvec_group<T, TS, DEC, NODAL, C0, C1, C2>>(
+      cx, a, (int64_t)grid.x, kNTHR<T, DEC, NODAL>, 0, label, bytes, [&] {
+        TimedLaunch tl(cx.stream, label, bytes);
+        hipLaunchKernelGGL((k_loadvec<T, TS, DEC, NODAL, C0, C1, C2>), grid, dim3(kNTHR<T, DEC, NODAL>), 0,
+                           cx.stream, a);
+      });
 }
 
 // Suffix of a solve's timing label naming what its store does (the kernel
@@ -2097,10 +2341,13 @@ void launch_strided_s(double *F, const Level &L, int axis, const Epi<T> &ep, Ctx
   else { sp_ = c2; so = c1 * c2; nouter = c0; }
   dim3 grid((unsigned)(((c2 + 63) / 64) * nouter));
   const size_t lds = (size_t)4 * d.P * 64 * sizeof(double);
-  TimedLaunch tl(cx.stream, std::string("k_solve_strided<") + tname<T>() + ", " + std::to_string(S) + ">" + epi_tag(ep.mode),
-                 timing_enabled() ? solve_bytes<T>((double)c0 * c1 * c2, ep.mode) : 0.0);
-  hipLaunchKernelGGL((k_solve_strided<T, S>), grid, dim3(64 * d.P), lds, cx.stream, F, c, d.P, c2, sp_,
-                     so, axis, c1, c2, solve_dev(d), ep);
+  const StridedArgs<T> sa{F, c, c2, sp_, so, c1, c2, d.P, axis, solve_dev(d), ep};
+  std::string label = std::string("k_solve_strided<") + tname<T>() + ", " + std::to_string(S) + ">" + epi_tag(ep.mode);
+  const double bytes = solve_bytes<T>((double)c0 * c1 * c2, ep.mode);
+  emit<StridedArgs<T>, k_solve_strided_group<T, S>>(cx, sa, (int64_t)grid.x, 64 * d.P, lds, label, bytes, [&] {
+    TimedLaunch tl(cx.stream, label, timing_enabled() ? bytes : 0.0);
+    hipLaunchKernelGGL((k_solve_strided<T, S>), grid, dim3(64 * d.P), lds, cx.stream, sa);
+  });
 }
 
 template <typename T, int S>
@@ -2113,11 +2360,15 @@ void launch_rows_s(double *F, const Level &L, const Epi<T> &ep, Ctx &cx) {
   R = std::min<int64_t>(R, budget / (c + 4 * d.P));
   R = std::max(R, 1);
   const size_t lds = (size_t)(tables_size(d.P * S, d.P) + R * c + 4 * d.P * R) * sizeof(double);
-  dim3 grid((unsigned)persistent_grid((nrows + R - 1) / R));
-  TimedLaunch tl(cx.stream, std::string("k_solve_rows<") + tname<T>() + ", " + std::to_string(S) + ">" + epi_tag(ep.mode),
-                 timing_enabled() ? solve_bytes<T>((double)nrows * c, ep.mode) : 0.0);
-  hipLaunchKernelGGL((k_solve_rows<T, S>), grid, dim3(R * d.P), lds, cx.stream, F, nrows, (int)c, d.P,
-                     R, L.c[1], solve_dev(d), ep);
+  const int64_t nblocks = (nrows + R - 1) / R;
+  dim3 grid((unsigned)persistent_grid(nblocks));
+  const RowsArgs<T> ra{F, nrows, L.c[1], (int)c, d.P, R, solve_dev(d), ep};
+  std::string label = std::string("k_solve_rows<") + tname<T>() + ", " + std::to_string(S) + ">" + epi_tag(ep.mode);
+  const double bytes = solve_bytes<T>((double)nrows * c, ep.mode);
+  emit<RowsArgs<T>, k_solve_rows_group<T, S>>(cx, ra, nblocks, R * d.P, lds, label, bytes, [&] {
+    TimedLaunch tl(cx.stream, label, timing_enabled() ? bytes : 0.0);
+    hipLaunchKernelGGL((k_solve_rows<T, S>), grid, dim3(R * d.P), lds, cx.stream, ra);
+  });
 }
 
 template <typename T>
@@ -2130,11 +2381,14 @@ void launch_long(double *F, const Level &L, int axis, const Epi<T> &ep, Ctx &cx)
   else { sp_ = 1; so = 0; sk = c2; nk = c0 * c1; nouter = 1; }
   dim3 grid((unsigned)(((nk + 63) / 64) * nouter));
   const size_t lds = (size_t)4 * d.P * 64 * sizeof(double);
+  const LongArgs<T> la{F, L.c[axis], nk, sp_, so, sk, c1, d.P, axis, solve_dev(d), ep};
   // the interior solutions are written and re-read once more
-  TimedLaunch tl(cx.stream, std::string("k_solve_long<") + tname<T>() + ">" + epi_tag(ep.mode),
-                 timing_enabled() ? solve_bytes<T>((double)c0 * c1 * c2, ep.mode) : 0.0);
-  hipLaunchKernelGGL((k_solve_long<T>), grid, dim3(64 * LONG_WAVES), lds, cx.stream, F, L.c[axis], d.P, nk,
-                     sp_, so, sk, axis, c1, solve_dev(d), ep);
+  std::string label = std::string("k_solve_long<") + tname<T>() + ">" + epi_tag(ep.mode);
+  const double bytes = solve_bytes<T>((double)c0 * c1 * c2, ep.mode);
+  emit<LongArgs<T>, k_solve_long_group<T>>(cx, la, (int64_t)grid.x, 64 * LONG_WAVES, lds, label, bytes, [&] {
+    TimedLaunch tl(cx.stream, label, timing_enabled() ? bytes : 0.0);
+    hipLaunchKernelGGL((k_solve_long<T>), grid, dim3(64 * LONG_WAVES), lds, cx.stream, la);
+  });
 }
 
 template <typename T>
@@ -2148,10 +2402,15 @@ void launch_solve(double *F, const Level &L, int axis, const Epi<T> &ep, Ctx &cx
     launch_long<T>(F, L, axis, ep, cx);
   } else if (d.S == 0) {  // the plan chose one sequential partition (tables built for it)
     const int64_t nlines = L.c[0] * L.c[1] * L.c[2] / L.c[axis];
-    TimedLaunch tl(cx.stream, std::string("k_solve_seq<") + tname<T>() + ">" + epi_tag(ep.mode),
-                   timing_enabled() ? solve_bytes<T>((double)L.c[0] * L.c[1] * L.c[2], ep.mode) : 0.0);
-    hipLaunchKernelGGL((k_solve_seq<T>), dim3((unsigned)grid_1d(nlines, 64)), dim3(64), 0, cx.stream, F,
-                       nlines, L.c[axis], axis, L.c[1], L.c[2], solve_dev(d), ep);
+    const std::string label = std::string("k_solve_seq<") + tname<T>() + ">" + epi_tag(ep.mode);
+    const double bytes = timing_enabled() ? solve_bytes<T>((double)L.c[0] * L.c[1] * L.c[2], ep.mode) : 0.0;
+    const int64_t cax = L.c[axis], lc1 = L.c[1], lc2 = L.c[2];
+    const SolveDev tb = solve_dev(d);
+    emit_direct(cx, [=](hipStream_t st) {
+      TimedLaunch tl(st, label, bytes);
+      hipLaunchKernelGGL((k_solve_seq<T>), dim3((unsigned)grid_1d(nlines, 64)), dim3(64), 0, st, F, nlines, cax,
+                         axis, lc1, lc2, tb, ep);
+    });
   } else if (axis == 2) {
     switch (d.S) {
       case 8: launch_rows_s<T, 8>(F, L, ep, cx); break;
@@ -2179,18 +2438,23 @@ int last_dim(const Level &L) {
 
 // Solves along the coarsened dims in order 0, 1, 2; the last one applies
 // `last`.  `part`: 0 all of them, 1 all but the last, 2 only the last.
+// Recorded solves take phases cx.phase + 1, + 2, + 3 in order.
 template <typename T>
 void solve_all(double *F, const Level &L, const Epi<T> &last, Ctx &cx, int part = 0) {
   const int lastk = last_dim(L);
+  const int p0 = cx.phase;
+  int n = 0;
   for (int k = 0; k < kDims; ++k) {
     if (!L.co[k] || (part == 1 && k == lastk) || (part == 2 && k != lastk)) continue;
     Epi<T> ep = (k == lastk) ? last : Epi<T>{EPI_Z, nullptr, Map3{}};
+    cx.phase = p0 + 1 + n++;
     launch_solve<T>(F, L, k, ep, cx);
   }
+  cx.phase = p0;
 }
 
 template <typename T, bool NC, bool C0, bool C1, bool C2>
-void launch_reconstruct_t(ReconArgs<T> a, Ctx &cx) {
+void launch_reconstruct_t(ReconArgs<T> a, Ctx &cx, const std::string &label, double bytes) {
   static const int slots = resident_slots((const void *)k_reconstruct<T, NC, C0, C1, C2>, RC_THR);
   const int64_t tiles = (int64_t)a.gx * a.gy;
   // chunks short enough for the kernel's LDS plane window (2 TI + 2 planes)
@@ -2201,8 +2465,11 @@ void launch_reconstruct_t(ReconArgs<T> a, Ctx &cx) {
   cx.ti_out = (int)a.TI;
   if (cx.dry) return;
   a.gz = (int)((a.c0 + a.TI - 1) / a.TI);
-  hipLaunchKernelGGL((k_reconstruct<T, NC, C0, C1, C2>), dim3((unsigned)(tiles * a.gz)), dim3(RC_THR), 0,
-                     cx.stream, a);
+  emit<ReconArgs<T>, k_reconstruct_group<T, NC, C0, C1, C2>>(cx, a, tiles * a.gz, RC_THR, 0, label, bytes, [&] {
+    TimedLaunch tl(cx.stream, label, timing_enabled() ? bytes : 0.0);
+    hipLaunchKernelGGL((k_reconstruct<T, NC, C0, C1, C2>), dim3((unsigned)(tiles * a.gz)), dim3(RC_THR), 0,
+                       cx.stream, a);
+  });
 }
 
 // Whether a reconstruct tile of tj coarse rows and tk coarse columns fits the
@@ -2245,12 +2512,11 @@ void launch_reconstruct(const Level &L, const T *coef, Map3 cmap, const T *uc, T
   const int64_t n = L.m[0] * L.m[1] * L.m[2];
   const double nl = (double)n, nc = (double)L.c[0] * L.c[1] * L.c[2];
   // read the coefficients and the coarse grid, write the level grid
-  TimedLaunch tl(cx.stream,
-                 std::string("k_reconstruct<") + tname<T>() + ", " + bname(cmap.t0 != nullptr) + ", " +
-                     bname(L.co[0]) + ", " + bname(L.co[1]) + ", " + bname(L.co[2]) + ">",
-                 (timing_enabled() && !cx.dry) ? ((nl - nc) + nc + nl) * sizeof(T) : 0.0);
+  const std::string label = std::string("k_reconstruct<") + tname<T>() + ", " + bname(cmap.t0 != nullptr) + ", " +
+                            bname(L.co[0]) + ", " + bname(L.co[1]) + ", " + bname(L.co[2]) + ">";
+  const double bytes = ((nl - nc) + nc + nl) * sizeof(T);
   const int key = (cmap.t0 ? 8 : 0) | (L.co[0] ? 4 : 0) | (L.co[1] ? 2 : 0) | (L.co[2] ? 1 : 0);
-#define MGR_RECON(NC, C0, C1, C2) launch_reconstruct_t<T, NC, C0, C1, C2>(a, cx)
+#define MGR_RECON(NC, C0, C1, C2) launch_reconstruct_t<T, NC, C0, C1, C2>(a, cx, label, bytes)
   switch (key) {
     case 0: MGR_RECON(false, false, false, false); break;
     case 1: MGR_RECON(false, false, false, true); break;
@@ -2282,11 +2548,15 @@ void launch_tail_dec(const Plan &pl, const TS *src, T *dst, Ctx &cx) {
   const Level &L = pl.lev[pl.tail_start];
   const double n = (double)L.m[0] * L.m[1] * L.m[2];
   // read the level grid, write the coefficients
-  TimedLaunch tl(cx.stream, std::string("k_tail_dec<") + tname<T>() + ">",
-                 timing_enabled() ? n * (sizeof(TS) + sizeof(T)) : 0.0);
+  const std::string label = std::string("k_tail_dec<") + tname<T>() + ">";
+  const double bytes = n * (sizeof(TS) + sizeof(T));
   const TailArgs ta{pl.dev_tail, pl.dev_tail_off, pl.dev_tail_dbl, pl.tail_noff, pl.tail_ndbl,
                     pl.nlev - pl.tail_start, 0};
-  hipLaunchKernelGGL((k_tail_dec<T, TS>), dim3(1), dim3(TAIL_THR), 0, cx.stream, src, dst, ta);
+  const TailDecJob<T, TS> job{src, dst, ta};
+  emit<TailDecJob<T, TS>, k_tail_dec_group<T, TS>>(cx, job, 1, TAIL_THR, 0, label, bytes, [&] {
+    TimedLaunch tl(cx.stream, label, timing_enabled() ? bytes : 0.0);
+    hipLaunchKernelGGL((k_tail_dec<T, TS>), dim3(1), dim3(TAIL_THR), 0, cx.stream, src, dst, ta);
+  });
   cx.check("k_tail_dec launch");
 }
 
@@ -2295,10 +2565,15 @@ void launch_tail_rec(const Plan &pl, const T *src, T *dst, Ctx &cx, int t_drop) 
   const Level &L = pl.lev[pl.tail_start];
   const double n = (double)L.m[0] * L.m[1] * L.m[2];
   // read the coefficients, write the level grid
-  TimedLaunch tl(cx.stream, std::string("k_tail_rec<") + tname<T>() + ">", timing_enabled() ? 2.0 * n * sizeof(T) : 0.0);
+  const std::string label = std::string("k_tail_rec<") + tname<T>() + ">";
+  const double bytes = 2.0 * n * sizeof(T);
   const TailArgs ta{pl.dev_tail, pl.dev_tail_off, pl.dev_tail_dbl, pl.tail_noff, pl.tail_ndbl,
                     pl.nlev - pl.tail_start, t_drop};
-  hipLaunchKernelGGL((k_tail_rec<T>), dim3(1), dim3(TAIL_THR), 0, cx.stream, src, dst, ta);
+  const TailRecJob<T> job{src, dst, ta};
+  emit<TailRecJob<T>, k_tail_rec_group<T>>(cx, job, 1, TAIL_THR, 0, label, bytes, [&] {
+    TimedLaunch tl(cx.stream, label, timing_enabled() ? bytes : 0.0);
+    hipLaunchKernelGGL((k_tail_rec<T>), dim3(1), dim3(TAIL_THR), 0, cx.stream, src, dst, ta);
+  });
   cx.check("k_tail_rec launch");
 }
 
@@ -2322,10 +2597,16 @@ Workspace carve(const Plan &pl, void *ws) {
 // solve), so that an FP32 field's coefficients at every level are rounded to
 // FP32 once, when stored, and carry no rounding of the grids they came from.
 template <typename T>
-bool decompose_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t stream, std::string &err) {
+bool decompose_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t stream, std::string &err,
+                 Rec *rec = nullptr) {
   Ctx cx{stream, &err};
+  cx.rec = rec;
   const int64_t total = pl.n[0] * pl.n[1] * pl.n[2];
   if (pl.nlev == 0) {
+    if (rec) {
+      emit_direct(cx, [=](hipStream_t st) { (void)hipMemcpyAsync(out, in, total * sizeof(T), hipMemcpyDeviceToDevice, st); });
+      return true;
+    }
     if (hipMemcpyAsync(out, in, total * sizeof(T), hipMemcpyDeviceToDevice, stream) != hipSuccess) {
       err = "hipMemcpyAsync failed";
       return false;
@@ -2340,6 +2621,7 @@ bool decompose_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t stre
     const Level &L = pl.lev[s];
     double *next = (double *)w.buf[s % 2];
     cx.ti_req = s < (int)tune.size() ? tune[s].lv_ti[0] : 0;
+    cx.phase = phase_dec_level(s);
     if (s == 0) {
       LoadArgs<T> a{};
       a.src = in;
@@ -2365,6 +2647,7 @@ bool decompose_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t stre
     src = next;
   }
   if (st < pl.nlev && cx.ok) {
+    cx.phase = kPhaseTail;
     if (st == 0) launch_tail_dec<T, T>(pl, in, out, cx);
     else launch_tail_dec<T, double>(pl, src, out, cx);
   }
@@ -2383,10 +2666,15 @@ bool decompose_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t stre
 // those of the serial order.
 template <typename T>
 bool recompose_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t stream, std::string &err,
-                 int nkeep, const StreamFork *fk = nullptr) {
+                 int nkeep, const StreamFork *fk = nullptr, Rec *rec = nullptr) {
   Ctx cx{stream, &err};
+  cx.rec = rec;
   const int64_t total = pl.n[0] * pl.n[1] * pl.n[2];
   if (pl.nlev == 0) {
+    if (rec) {
+      emit_direct(cx, [=](hipStream_t st) { (void)hipMemcpyAsync(out, in, total * sizeof(T), hipMemcpyDeviceToDevice, st); });
+      return true;
+    }
     if (hipMemcpyAsync(out, in, total * sizeof(T), hipMemcpyDeviceToDevice, stream) != hipSuccess) {
       err = "hipMemcpyAsync failed";
       return false;
@@ -2397,7 +2685,7 @@ bool recompose_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t stre
   const int st = std::min(pl.tail_start, pl.nlev);
   const int drop = pl.nlev - std::max(0, std::min(nkeep, pl.nlev));  // levels below take zero coefficients
   const std::vector<LevelTune> tune0 = pl.tune_snapshot();
-  const bool split = fk != nullptr && w.F2 != nullptr && st >= 1 && drop == 0;
+  const bool split = fk != nullptr && rec == nullptr && w.F2 != nullptr && st >= 1 && drop == 0;
   double *Fc = split ? w.F2 : w.F;  // load vector of the levels on `stream`
   if (split) {
     hipStream_t hs = (hipStream_t)fk->helper;
@@ -2434,19 +2722,25 @@ bool recompose_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t stre
     const Level &Lc = pl.lev[pl.nlev];
     V = (T *)w.buf[pl.nlev % 2];
     const int64_t n = Lc.m[0] * Lc.m[1] * Lc.m[2];
-    TimedLaunch tl(stream, std::string("k_gather<") + tname<T>() + ">", 2.0 * n * sizeof(T));
-    hipLaunchKernelGGL((k_gather<T>), dim3((unsigned)grid_1d(n, 256)), dim3(256), 0, stream, in,
-                       nodal_map(Lc), V, Lc.m[0], Lc.m[1], Lc.m[2]);
+    const Map3 nm = nodal_map(Lc);
+    const int64_t g0 = Lc.m[0], g1 = Lc.m[1], g2 = Lc.m[2];
+    T *Vg = V;
+    emit_direct(cx, [=](hipStream_t st) {
+      TimedLaunch tl(st, std::string("k_gather<") + tname<T>() + ">", 2.0 * n * sizeof(T));
+      hipLaunchKernelGGL((k_gather<T>), dim3((unsigned)grid_1d(n, 256)), dim3(256), 0, st, in, nm, Vg, g0, g1, g2);
+    });
     cx.check("k_gather launch");
   }
   const std::vector<LevelTune> &tune = tune0;
   for (int s = st - 1; s >= 0 && cx.ok; --s) {
     const Level &L = pl.lev[s];
+    cx.phase = phase_rec_level(s);
     const LevelTune lt = s < (int)tune.size() ? tune[s] : LevelTune{};
     const Map3 cmap = (s == 0) ? compact_map(pl.n[1], pl.n[2]) : nodal_map(L);
     T *dst = (s == 0) ? out : (T *)w.buf[s % 2];
     if (s < drop) {  // dropped class: the level grid is the interpolant of U_c = V
       cx.ti_req = lt.rc_ti;
+      cx.phase = phase_rec_level(s) + 4;
       launch_reconstruct<T>(L, (const T *)nullptr, cmap, V, dst, cx, lt.rc_tj, lt.rc_tk);
       cx.ti_req = 0;
       V = dst;
@@ -2474,6 +2768,7 @@ bool recompose_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t stre
       solve_all<T>(Fc, L, ep, cx);
     }
     cx.ti_req = lt.rc_ti;
+    cx.phase = phase_rec_level(s) + 4;
     launch_reconstruct<T>(L, in, cmap, V, dst, cx, lt.rc_tj, lt.rc_tk);
     cx.ti_req = 0;
     V = dst;
@@ -2963,6 +3258,73 @@ bool enqueue_copy_probe(const void *src, void *dst, size_t bytes, void *stream, 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     err = std::string("k_copy_probe launch: ") + hipGetErrorString(e);
+    return false;
+  }
+  return true;
+}
+
+bool enqueue_batch(bool dec, const std::vector<BatchItem> &items, void *stream, std::string &err) {
+  hipStream_t st = (hipStream_t)stream;
+  Rec rec;
+  {
+    const PlainLoadVector plain;  // batches keep k_loadvec (see mgr_api.cpp)
+    for (const BatchItem &b : items) {
+      const bool ok = dec ? (b.f64 ? decompose_t<double>(*b.pl, (const double *)b.in, (double *)b.out, b.ws, st, err, &rec)
+                                   : decompose_t<float>(*b.pl, (const float *)b.in, (float *)b.out, b.ws, st, err, &rec))
+                          : (b.f64 ? recompose_t<double>(*b.pl, (const double *)b.in, (double *)b.out, b.ws, st, err,
+                                                         b.pl->nlev, nullptr, &rec)
+                                   : recompose_t<float>(*b.pl, (const float *)b.in, (float *)b.out, b.ws, st, err,
+                                                        b.pl->nlev, nullptr, &rec));
+      if (!ok) return false;
+    }
+  }
+  // phase by phase; within a phase, jobs of one kernel and block size share
+  // launches (in the order they first appear)
+  std::vector<const RecJob *> js;
+  js.reserve(rec.jobs.size());
+  for (const RecJob &r : rec.jobs) js.push_back(&r);
+  std::stable_sort(js.begin(), js.end(), [](const RecJob *a, const RecJob *b) { return a->phase < b->phase; });
+  size_t i = 0;
+  while (i < js.size()) {
+    size_t e = i;
+    while (e < js.size() && js[e]->phase == js[i]->phase) ++e;
+    std::vector<bool> done(e - i, false);
+    for (size_t a = i; a < e; ++a) {
+      if (done[a - i]) continue;
+      const RecJob *r = js[a];
+      if (!r->group) {
+        done[a - i] = true;
+        r->direct(st);
+        continue;
+      }
+      std::vector<const RecJob *> g;
+      size_t lds = 0;
+      double bytes = 0.0;
+      for (size_t b = a; b < e; ++b) {
+        const RecJob *q = js[b];
+        if (done[b - i] || q->group != r->group || q->threads != r->threads) continue;
+        done[b - i] = true;
+        g.push_back(q);
+        lds = std::max(lds, q->lds);
+        bytes += q->bytes;
+        if ((int)g.size() == r->gmax) {
+          TimedLaunch tl(st, r->label + " [group]", timing_enabled() ? bytes : 0.0);
+          r->group(g, st, lds, r->threads);
+          g.clear();
+          lds = 0;
+          bytes = 0.0;
+        }
+      }
+      if (!g.empty()) {
+        TimedLaunch tl(st, r->label + " [group]", timing_enabled() ? bytes : 0.0);
+        r->group(g, st, lds, r->threads);
+      }
+    }
+    i = e;
+  }
+  const hipError_t he = hipGetLastError();
+  if (he != hipSuccess) {
+    err = std::string("grouped batch launch: ") + hipGetErrorString(he);
     return false;
   }
   return true;

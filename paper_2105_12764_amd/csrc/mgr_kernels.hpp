@@ -2,6 +2,7 @@
 #pragma once
 
 #include <string>
+#include <vector>
 
 #include "mgr_plan.hpp"
 
@@ -38,6 +39,24 @@ class PlainLoadVector {
   PlainLoadVector(const PlainLoadVector &) = delete;
   PlainLoadVector &operator=(const PlainLoadVector &) = delete;
 };
+
+// One field of a batch: its plan, type and device buffers (workspace of the
+// single-field size).
+struct BatchItem {
+  const Plan *pl;
+  bool f64;
+  const void *in;
+  void *out;
+  void *ws;
+};
+
+// Decompose (recompose) every field of a batch with grouped launches: the
+// fields' launch chains are recorded, and for each step of the level loop
+// (aligned by level index, finest = 0) the launches of one kernel across
+// all fields go out as one grid over their blocks, in order on `stream`.
+// Same kernels and arithmetic as the single-field calls (bitwise the same
+// results).  Fields must have 1 to 3 dims.
+bool enqueue_batch(bool dec, const std::vector<BatchItem> &items, void *stream, std::string &err);
 
 // Reorder a nodal representation into class-contiguous order (export) or
 // back (import); src and dst hold prod(shape) elements each.

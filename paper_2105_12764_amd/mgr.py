@@ -28,6 +28,7 @@ MGR_FLOAT32 = 0
 MGR_FLOAT64 = 1
 
 MGR_BATCH_STREAMS = 4
+MGR_BATCH_PER_FIELD = 1
 # static device scratch of mgr_decompose_noalloc (include/mgr.h)
 MGR_NOALLOC_SCRATCH_BYTES = 64 << 20
 MGR_NOALLOC_TABLE_BYTES = 4 << 20
@@ -117,6 +118,9 @@ def lib() -> ctypes.CDLL:
         L.mgr_batch_workspace_size.restype = ctypes.c_int
         for fn in (L.mgr_decompose_batch, L.mgr_recompose_batch):
             fn.argtypes = [ctypes.c_int, fp, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+            fn.restype = ctypes.c_int
+        for fn in (L.mgr_decompose_batch_ex, L.mgr_recompose_batch_ex):
+            fn.argtypes = [ctypes.c_int, fp, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_int]
             fn.restype = ctypes.c_int
         L.mgr_probe_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                      ctypes.c_void_p]
@@ -358,7 +362,7 @@ class Batch:
         return torch.empty(max(self.workspace_size(), 1), dtype=torch.uint8, device=device or "cuda")
 
 
-def _call_batch(fn, batch: Batch, workspace, stream):
+def _call_batch(fn, batch: Batch, workspace, stream, flags: int = 0):
     import torch
     dev = batch.tensors[0][0].device
     made = []
@@ -370,20 +374,25 @@ def _call_batch(fn, batch: Batch, workspace, stream):
         stream = torch.cuda.current_stream(dev)
     with torch.cuda.device(dev):
         s = fn(len(batch.fields), batch.fields, ctypes.c_void_p(workspace.data_ptr()),
-               ctypes.c_size_t(wsb), ctypes.c_void_p(stream.cuda_stream))
+               ctypes.c_size_t(wsb), ctypes.c_void_p(stream.cuda_stream), int(flags))
     if s != MGR_OK:
         raise MgrError(s, last_error())
     _on_stream(made, stream, dev)
 
 
-def decompose_batch(batch: Batch, workspace=None, stream=None) -> None:
-    """mgr_decompose_batch: every field's in decomposed into its out."""
-    _call_batch(lib().mgr_decompose_batch, batch, workspace, stream)
+def decompose_batch(batch: Batch, workspace=None, stream=None, per_field: bool = False) -> None:
+    """mgr_decompose_batch_ex: every field's in decomposed into its out, with
+    grouped launches (default) or each field's own launch chain on internal
+    streams (per_field=True, MGR_BATCH_PER_FIELD)."""
+    _call_batch(lib().mgr_decompose_batch_ex, batch, workspace, stream,
+                MGR_BATCH_PER_FIELD if per_field else 0)
 
 
-def recompose_batch(batch: Batch, workspace=None, stream=None) -> None:
-    """mgr_recompose_batch: every field's in (a representation) recomposed into its out."""
-    _call_batch(lib().mgr_recompose_batch, batch, workspace, stream)
+def recompose_batch(batch: Batch, workspace=None, stream=None, per_field: bool = False) -> None:
+    """mgr_recompose_batch_ex: every field's in (a representation) recomposed
+    into its out; launch modes as for :func:`decompose_batch`."""
+    _call_batch(lib().mgr_recompose_batch_ex, batch, workspace, stream,
+                MGR_BATCH_PER_FIELD if per_field else 0)
 
 
 def recompose_partial(x, nkeep: int, coords=None, nlevels: Optional[int] = None, out=None, workspace=None,

@@ -262,3 +262,18 @@ def test_noalloc_limits_match_the_header():
     assert re.search(r"#define MGR_NOALLOC_SCRATCH_BYTES \(64u << 20\)", txt)
     assert re.search(r"#define MGR_NOALLOC_TABLE_BYTES \(4u << 20\)", txt)
     assert mgr.MGR_NOALLOC_SCRATCH_BYTES == 64 << 20 and mgr.MGR_NOALLOC_TABLE_BYTES == 4 << 20
+
+
+@pytest.mark.parametrize("fn", ["mgr_decompose_batch_ex", "mgr_recompose_batch_ex"])
+def test_batch_ex_rejects_unknown_flags_before_any_device_call(fn):
+    L = mgr.lib()
+    ok = ((9, 9, 9), mgr.MGR_FLOAT64, 2, 1 << 30, 2 << 30)
+    for flags in (2, 4, -1, 1 << 30):
+        assert getattr(L, fn)(1, _fields([ok]), ctypes.c_void_p(1 << 34), ctypes.c_size_t(1 << 30), None,
+                              flags) == mgr.MGR_ERR_INVALID_ARG
+        assert "flags" in mgr.last_error()
+    # valid flags still validate the fields first
+    bad = ((9, 1, 9), mgr.MGR_FLOAT64, 1, 3 << 30, 4 << 30)
+    for flags in (0, mgr.MGR_BATCH_PER_FIELD):
+        assert getattr(L, fn)(1, _fields([bad]), ctypes.c_void_p(1 << 34), ctypes.c_size_t(1 << 30), None,
+                              flags) == mgr.MGR_ERR_INVALID_ARG

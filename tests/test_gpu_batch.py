@@ -1,9 +1,11 @@
-"""GPU: the batched entry points (mgr_decompose_batch / mgr_recompose_batch).
+"""GPU: the batched entry points (mgr_decompose_batch / mgr_recompose_batch and
+their _ex forms), in both launch modes: grouped launches (one grid per kernel
+and level step across the fields) and per-field chains on internal streams.
 
 Each field of a batch must come out bitwise equal to the single-field call on
-the same input (the same kernels run, on internal streams), agree with the
-oracle to the usual tolerances, stay stream-ordered, and give the same result
-on every replay of a HIP graph that captured the batch.
+the same input (the same kernel bodies run), agree with the oracle to the
+usual tolerances, stay stream-ordered, and give the same result on every
+replay of a HIP graph that captured the batch.
 """
 import numpy as np
 import pytest
@@ -25,7 +27,10 @@ FIELDS = [
     ((1000,), None, True, np.float64),
     ((2, 2, 2), 0, False, np.float64),
     ((40, 150, 2), 2, True, np.float32),
+    ((2100, 5), None, True, np.float64),   # lines of 1051 unknowns: the long-line solver
+    ((4100, 3), 2, False, np.float32),     # lines of 2051: the sequential solver (launched alone)
 ]
+MODES = [False, True]  # per_field
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -52,37 +57,39 @@ def _err(got, ref, dtype):
     return float(np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-300))
 
 
-def test_batch_equals_single_calls_bitwise():
-    print("\n[case] batch of 8 mixed fields vs single calls", flush=True)
+@pytest.mark.parametrize("per_field", MODES)
+def test_batch_equals_single_calls_bitwise(per_field):
+    print(f"\n[case] batch of {len(FIELDS)} mixed fields vs single calls, per_field={per_field}", flush=True)
     ins = _inputs()
     singles = [mgr.decompose(x, coords, nlev) for (_, coords, nlev, x) in ins]
     outs = [torch.empty_like(x) for (_, _, _, x) in ins]
     batch = mgr.Batch([(x, y, coords, nlev) for (_, coords, nlev, x), y in zip(ins, outs)])
     ws = batch.alloc_workspace()
-    mgr.decompose_batch(batch, ws)
+    mgr.decompose_batch(batch, ws, per_field=per_field)
     torch.cuda.synchronize()
     for i, (a, b) in enumerate(zip(singles, outs)):
         assert torch.equal(a, b), f"field {i} {FIELDS[i][0]}: decompose batch differs from single call"
     # recompose: outs -> fields, against single recompositions
     back = [torch.empty_like(x) for (_, _, _, x) in ins]
     rb = mgr.Batch([(y, z, coords, nlev) for (_, coords, nlev, _), y, z in zip(ins, outs, back)])
-    mgr.recompose_batch(rb, ws)
+    mgr.recompose_batch(rb, ws, per_field=per_field)
     rsingles = [mgr.recompose(y, coords, nlev) for (_, coords, nlev, _), y in zip(ins, outs)]
     torch.cuda.synchronize()
     for i, (a, b) in enumerate(zip(rsingles, back)):
         assert torch.equal(a, b), f"field {i} {FIELDS[i][0]}: recompose batch differs from single call"
 
 
-def test_batch_matches_oracle():
-    print("\n[case] batch of 8 mixed fields vs the oracle", flush=True)
+@pytest.mark.parametrize("per_field", MODES)
+def test_batch_matches_oracle(per_field):
+    print(f"\n[case] batch of {len(FIELDS)} mixed fields vs the oracle, per_field={per_field}", flush=True)
     ins = _inputs(seed0=400)
     outs = [torch.empty_like(x) for (_, _, _, x) in ins]
     back = [torch.empty_like(x) for (_, _, _, x) in ins]
     batch = mgr.Batch([(x, y, coords, nlev) for (_, coords, nlev, x), y in zip(ins, outs)])
     ws = batch.alloc_workspace()
-    mgr.decompose_batch(batch, ws)
+    mgr.decompose_batch(batch, ws, per_field=per_field)
     rb = mgr.Batch([(y, z, coords, nlev) for (_, coords, nlev, _), y, z in zip(ins, outs, back)])
-    mgr.recompose_batch(rb, ws)
+    mgr.recompose_batch(rb, ws, per_field=per_field)
     torch.cuda.synchronize()
     for i, ((u, coords, nlev, _), y, z) in enumerate(zip(ins, outs, back)):
         dtype = FIELDS[i][3]
@@ -95,8 +102,9 @@ def test_batch_matches_oracle():
         assert e_rt <= tol, (i, e_rt)
 
 
-def test_batch_graph_replays_match_eager():
-    print("\n[case] batch captured in a HIP graph, three replays", flush=True)
+@pytest.mark.parametrize("per_field", MODES)
+def test_batch_graph_replays_match_eager(per_field):
+    print(f"\n[case] batch captured in a HIP graph, three replays, per_field={per_field}", flush=True)
     ins = _inputs(seed0=500)
     outs = [torch.empty_like(x) for (_, _, _, x) in ins]
     back = [torch.empty_like(x) for (_, _, _, x) in ins]
@@ -105,8 +113,8 @@ def test_batch_graph_replays_match_eager():
     ws = batch.alloc_workspace()
     ws2 = rb.alloc_workspace()
     # eager reference (also builds every plan before the capture)
-    mgr.decompose_batch(batch, ws)
-    mgr.recompose_batch(rb, ws2)
+    mgr.decompose_batch(batch, ws, per_field=per_field)
+    mgr.recompose_batch(rb, ws2, per_field=per_field)
     torch.cuda.synchronize()
     ref_d = [y.clone() for y in outs]
     ref_r = [z.clone() for z in back]
@@ -115,8 +123,8 @@ def test_batch_graph_replays_match_eager():
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
         with torch.cuda.graph(g, stream=side):
-            mgr.decompose_batch(batch, ws, stream=side)
-            mgr.recompose_batch(rb, ws2, stream=side)
+            mgr.decompose_batch(batch, ws, stream=side, per_field=per_field)
+            mgr.recompose_batch(rb, ws2, stream=side, per_field=per_field)
     torch.cuda.synchronize()
     for rep in range(3):
         for y, z in zip(outs, back):  # eager work between replays
@@ -150,6 +158,33 @@ def test_batch_is_stream_ordered():
     torch.cuda.synchronize()
     for i, (a, b) in enumerate(zip(singles, copies)):
         assert torch.equal(a, b), f"field {i}: stream order broken"
+
+
+def test_grouped_batch_of_many_fields_equals_single_calls():
+    """More jobs of one kernel in a step than one grouped launch takes (the
+    launch is split), fields of different depths, both dtypes, 2-D and 3-D."""
+    print("\n[case] grouped batch of 70 fields vs single calls", flush=True)
+    specs = [((17 + (i % 5), 19, 21 + (i % 3)), np.float64) for i in range(40)] + \
+            [((65 + 2 * (i % 7), 33 + (i % 4)), np.float32) for i in range(30)]
+    ins = []
+    for i, (shape, dt) in enumerate(specs):
+        u, coords = make_input(shape, 900 + i, nonuniform=(i % 2 == 0), dtype=dt)
+        ins.append((torch.from_numpy(u).cuda(), coords, oracle.max_levels(shape)))
+    singles = [mgr.decompose(x, c, n) for (x, c, n) in ins]
+    outs = [torch.empty_like(x) for (x, _, _) in ins]
+    back = [torch.empty_like(x) for (x, _, _) in ins]
+    batch = mgr.Batch([(x, y, c, n) for (x, c, n), y in zip(ins, outs)])
+    ws = batch.alloc_workspace()
+    mgr.decompose_batch(batch, ws)
+    rb = mgr.Batch([(y, z, c, n) for (_, c, n), y, z in zip(ins, outs, back)])
+    mgr.recompose_batch(rb, ws)
+    rsingles = [mgr.recompose(y, c, n) for (_, c, n), y in zip(ins, singles)]
+    torch.cuda.synchronize()
+    for i in range(len(specs)):
+        assert torch.equal(singles[i], outs[i]), f"field {i} {specs[i]}: decomposition differs"
+        assert torch.equal(rsingles[i], back[i]), f"field {i} {specs[i]}: recomposition differs"
+    u0 = ins[0][0].double()
+    assert float((back[0].double() - u0).abs().max() / u0.abs().max()) <= 1e-12
 
 
 @pytest.mark.parametrize("shape,nonuni,dtype", [((129, 100, 77), True, np.float64),
