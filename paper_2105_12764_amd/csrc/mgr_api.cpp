@@ -515,17 +515,7 @@ mgr_status run_batch(bool dec, int nfields, const mgr_field *fields, void *ws, s
     std::vector<std::shared_ptr<mgr::Plan>> plans;
     for (auto &j : jobs)
       if (std::find(plans.begin(), plans.end(), j.plan) == plans.end()) plans.push_back(j.plan);
-    if (!(flags & MGR_BATCH_PER_FIELD)) {
-      // grouped launches on `stream`
-      std::vector<mgr::BatchItem> items;
-      items.reserve(nfields);
-      for (int i = 0; i < nfields; ++i)
-        items.push_back(mgr::BatchItem{jobs[i].plan.get(), fields[i].dtype == MGR_FLOAT64, fields[i].in, fields[i].out,
-                                       ws ? (void *)((char *)ws + jobs[i].ws_off) : nullptr});
-      std::string err;
-      if (!mgr::enqueue_batch(dec, items, stream, err)) return fail(MGR_ERR_DEVICE, err);
-      return retain_for_capture(stream, plans);
-    }
+    const bool grouped = !(flags & MGR_BATCH_PER_FIELD);
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess) {
       const hipError_t e = hipGetLastError();
@@ -568,8 +558,21 @@ mgr_status run_batch(bool dec, int nfields, const mgr_field *fields, void *ws, s
     // in a host segmentation fault inside the graph launch once, with no
     // cause found in the kernel; until one is, batches do not use it.
     const mgr::PlainLoadVector plain;
+    if (grouped) {
+      // each stream runs its fields with grouped launches; the streams' small
+      // latency-bound launches overlap each other's large ones
+      for (int k = 0; k < MGR_BATCH_STREAMS && ok; ++k) {
+        if (!used[k]) continue;
+        std::vector<mgr::BatchItem> items;
+        for (int i : order)
+          if (lane[i] == k)
+            items.push_back(mgr::BatchItem{jobs[i].plan.get(), fields[i].dtype == MGR_FLOAT64, fields[i].in,
+                                           fields[i].out, ws ? (void *)((char *)ws + jobs[i].ws_off) : nullptr});
+        ok = mgr::enqueue_batch(dec, items, bs->s[k], err);
+      }
+    }
     for (int i : order) {
-      if (!ok) break;
+      if (!ok || grouped) break;
       const bool f64 = fields[i].dtype == MGR_FLOAT64;
       void *wsi = ws ? (void *)((char *)ws + jobs[i].ws_off) : nullptr;
       std::string e;

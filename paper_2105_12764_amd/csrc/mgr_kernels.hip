@@ -982,6 +982,13 @@ __device__ __forceinline__ void strided_body(const StridedArgs<T> &A, const int 
   extern __shared__ double xs[];
   const int lane = threadIdx.x & 63;
   const int p = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (p >= P) {  // a grouped launch sized for a job with more partitions: only meet the barriers
+    if (P > 1) {
+      __syncthreads();
+      __syncthreads();
+    }
+    return;
+  }
   const int nkb = (int)((nk + 63) / 64);
   const int64_t k = (int64_t)(blk % nkb) * 64 + lane;
   const int64_t outer = blk / nkb;
@@ -1080,7 +1087,10 @@ __device__ __forceinline__ void rows_body(const RowsArgs<T> &A, const int64_t fi
   double *tile = sm + tables_size(P * S, P);  // [R][c]
   double *ex = tile + (size_t)R * c;       // separator exchange [4][P][R]
   double *yF = ex, *yL = ex + P * R, *Fs = ex + 2 * P * R, *tt = ex + 3 * P * R;
-  const int r = t % R, p = t / R;
+  // threads past R x P (a grouped launch sized for a larger job) stage and
+  // store with the others but solve nothing
+  const bool solver = t < R * P;
+  const int r = t % R, p = solver ? t / R : 0;
   const int64_t f = (int64_t)p * S;
   const int nload = p < P - 1 ? S : (int)(c - f);
   const int nint = p < P - 1 ? S - 1 : nload;
@@ -1100,18 +1110,20 @@ __device__ __forceinline__ void rows_body(const RowsArgs<T> &A, const int64_t fi
         if (e + u * nt < n) tile[e + u * nt] = v[u];
     }
     __syncthreads();
-    const bool active = r < nr;
+    const bool active = solver && r < nr;
     double x[S];
     const double *rowp = tile + r * c + f;
 #pragma unroll
     for (int q = 0; q < S; ++q) x[q] = (active && q < nload) ? rowp[q] : 0.0;
     partition_solve<S>(x, tb, f);
     if (P > 1) {
-      yF[p * R + r] = x[0];
-      yL[p * R + r] = pick<S>(x, nint - 1);
-      Fs[p * R + r] = x[S - 1];
+      if (solver) {
+        yF[p * R + r] = x[0];
+        yL[p * R + r] = pick<S>(x, nint - 1);
+        Fs[p * R + r] = x[S - 1];
+      }
       __syncthreads();
-      if (p == 0) separator_solve(tb, S, P, yF + r, yL + r, Fs + r, tt + r, R);
+      if (solver && p == 0) separator_solve(tb, S, P, yF + r, yL + r, Fs + r, tt + r, R);
       __syncthreads();
       const double tl = p > 0 ? tt[(p - 1) * R + r] : 0.0;
       const double tr = p < P - 1 ? tt[p * R + r] : 0.0;
@@ -3278,8 +3290,10 @@ bool enqueue_batch(bool dec, const std::vector<BatchItem> &items, void *stream, 
       if (!ok) return false;
     }
   }
-  // phase by phase; within a phase, jobs of one kernel and block size share
-  // launches (in the order they first appear)
+  // phase by phase; within a phase, the jobs of one kernel share launches (in
+  // the order they first appear), each launch sized for its largest job:
+  // a solver workgroup of a job with fewer partitions leaves the extra waves
+  // idle
   std::vector<const RecJob *> js;
   js.reserve(rec.jobs.size());
   for (const RecJob &r : rec.jobs) js.push_back(&r);
@@ -3299,26 +3313,27 @@ bool enqueue_batch(bool dec, const std::vector<BatchItem> &items, void *stream, 
       }
       std::vector<const RecJob *> g;
       size_t lds = 0;
+      unsigned thr = 0;
       double bytes = 0.0;
+      auto flush = [&]() {
+        TimedLaunch tl(st, r->label + " [group]", timing_enabled() ? bytes : 0.0);
+        r->group(g, st, lds, thr);
+        g.clear();
+        lds = 0;
+        thr = 0;
+        bytes = 0.0;
+      };
       for (size_t b = a; b < e; ++b) {
         const RecJob *q = js[b];
-        if (done[b - i] || q->group != r->group || q->threads != r->threads) continue;
+        if (done[b - i] || q->group != r->group) continue;
         done[b - i] = true;
         g.push_back(q);
         lds = std::max(lds, q->lds);
+        thr = std::max(thr, q->threads);
         bytes += q->bytes;
-        if ((int)g.size() == r->gmax) {
-          TimedLaunch tl(st, r->label + " [group]", timing_enabled() ? bytes : 0.0);
-          r->group(g, st, lds, r->threads);
-          g.clear();
-          lds = 0;
-          bytes = 0.0;
-        }
+        if ((int)g.size() == r->gmax) flush();
       }
-      if (!g.empty()) {
-        TimedLaunch tl(st, r->label + " [group]", timing_enabled() ? bytes : 0.0);
-        r->group(g, st, lds, r->threads);
-      }
+      if (!g.empty()) flush();
     }
     i = e;
   }
