@@ -1646,30 +1646,61 @@ __global__ void __launch_bounds__(TF_THR) k_tfine(TfineArgs<T, TS> a) {
       int64_t K0, K1;
       nb_dim<false>(k0, a.m2, a.c2, a.co2, a.r2, K0, hi, w);
       nb_dim<false>(k1 - 1, a.m2, a.c2, a.co2, a.r2, lo, K1, w);
-      const int64_t nK = K1 - K0 + 1, nst = (J1 - J0 + 1) * nK;
-      for (int64_t e = tid; e < nst; e += TF_THR) {
-        const int64_t Jr = e / nK, Kr = e - Jr * nK;
-        const int64_t o = cpos(J0 + Jr, a.m1, a.c1, a.co1) * s1 + cpos(K0 + Kr, a.m2, a.c2, a.co2);
-        const double vl = lerp((double)cl[o], (double)cl[o + dh], w0);
-        const double vr = lerp((double)cr[o], (double)cr[o + dh], w0);
-        sR[Jr * TF_PITCH + Kr] = lerp(vl, vr, rt);
+      // coarse rows J0..J1 (TF_ROWS / 2 + 1 of them along a coarsened dim 1,
+      // up to TF_ROWS otherwise), columns K0..K1: each thread keeps its
+      // columns and walks the rows, all loads in flight
+      const int nK = (int)(K1 - K0 + 1), nJ = (int)(J1 - J0 + 1);
+      for (int kr = tid; kr < nK; kr += TF_THR) {
+        const int64_t oc = cpos(K0 + kr, a.m2, a.c2, a.co2);
+        TS v[4][TF_ROWS];
+#pragma unroll
+        for (int jr = 0; jr < TF_ROWS; ++jr) {
+          const int64_t o = cpos(J0 + min(jr, nJ - 1), a.m1, a.c1, a.co1) * s1 + oc;
+          v[0][jr] = cl[o];
+          v[1][jr] = cl[o + dh];
+          v[2][jr] = cr[o];
+          v[3][jr] = cr[o + dh];
+        }
+#pragma unroll
+        for (int jr = 0; jr < TF_ROWS; ++jr)
+          if (jr < nJ)
+            sR[jr * TF_PITCH + kr] =
+                lerp(lerp((double)v[0][jr], (double)v[1][jr], w0), lerp((double)v[2][jr], (double)v[3][jr], w0), rt);
       }
       __syncthreads();
-      const int64_t nk = k1 - k0, nfine = (j1 - j0) * nk;
-      for (int64_t e = tid; e < nfine; e += TF_THR) {
-        const int64_t jr = e / nk, j = j0 + jr, k = k0 + (e - jr * nk);
-        int64_t jl, jh, kl, kh;
-        double wj, wk;
-        nb_dim<false>(j, a.m1, a.c1, a.co1, a.r1, jl, jh, wj);
+      // fine nodes: each thread keeps its columns (neighbours, weight, offset)
+      // and walks the rows, whose neighbours are the same for every thread
+      const int nk = (int)(k1 - k0), nr = (int)(j1 - j0);
+      for (int kk = tid; kk < nk; kk += TF_THR) {
+        const int64_t k = k0 + kk;
+        int64_t kl, kh;
+        double wk;
         nb_dim<false>(k, a.m2, a.c2, a.co2, a.r2, kl, kh, wk);
-        const double *rl = sR + (jl - J0) * TF_PITCH - K0, *rh = sR + (jh - J0) * TF_PITCH - K0;
-        const double pi = lerp(lerp(rl[kl], rl[kh], wk), lerp(rh[kl], rh[kh], wk), wj);
-        const int64_t fo = frow + moff(a.fmap, i, j, k);
-        const int64_t lv = t * sm + (i * a.m1 + j) * a.m2 + k;
-        if (DEC)
-          a.dst[fo] = (T)((double)a.src[lv] - pi);
-        else
-          a.dst[lv] = (T)((double)a.src[fo] + pi);
+        const int ql = (int)(kl - K0), qh = (int)(kh - K0);
+        const int64_t fcol = a.fmap.t0 ? a.fmap.t2[k] : k;
+        const int64_t frowi = frow + (a.fmap.t0 ? a.fmap.t0[i] : i * a.fmap.s0);
+        TS x[TF_ROWS];
+        int64_t fo[TF_ROWS], lv[TF_ROWS];
+#pragma unroll
+        for (int jr = 0; jr < TF_ROWS; ++jr) {
+          const int64_t j = j0 + min(jr, nr - 1);
+          fo[jr] = frowi + (a.fmap.t0 ? a.fmap.t1[j] : j * a.fmap.s1) + fcol;
+          lv[jr] = t * sm + (i * a.m1 + j) * a.m2 + k;
+          x[jr] = a.src[DEC ? lv[jr] : fo[jr]];
+        }
+#pragma unroll
+        for (int jr = 0; jr < TF_ROWS; ++jr) {
+          if (jr >= nr) break;
+          int64_t jl, jh;
+          double wj;
+          nb_dim<false>(j0 + jr, a.m1, a.c1, a.co1, a.r1, jl, jh, wj);
+          const double *rl = sR + (jl - J0) * TF_PITCH, *rh = sR + (jh - J0) * TF_PITCH;
+          const double pi = lerp(lerp(rl[ql], rl[qh], wk), lerp(rh[ql], rh[qh], wk), wj);
+          if (DEC)
+            a.dst[fo[jr]] = (T)((double)x[jr] - pi);
+          else
+            a.dst[lv[jr]] = (T)((double)x[jr] + pi);
+        }
       }
       __syncthreads();
     }
@@ -2066,6 +2097,12 @@ struct Rec {
   std::vector<RecJob> jobs;
 };
 
+// Launches recorded jobs on `st`: phase by phase; within a phase, the jobs
+// of one kernel share launches (in the order they first appear), each launch
+// sized for its largest job (a solver workgroup of a job with fewer
+// partitions leaves the extra waves idle); jobs with no grouped form run alone.
+bool launch_recorded(const Rec &rec, hipStream_t st, std::string &err);
+
 struct Ctx {
   hipStream_t stream;
   std::string *err;
@@ -2262,8 +2299,11 @@ void launch_loadvec_ring(LoadArgs<T, TS> a, Ctx &cx) {
   a.gx = ring_tiles(a.c2, TK);
   a.gy = ring_tiles(a.c1, TJ);
   const int64_t tiles = (int64_t)a.gx * a.gy;
+  // built-in rule: long marches (the pipeline fills and drains once per
+  // chunk), as many chunks as one round of resident workgroups holds
+  const int64_t nch = std::max<int64_t>(1, std::min<int64_t>(a.c0, slots / std::max<int64_t>(tiles, 1)));
   a.TI = cx.ti_req > 0 ? std::min<int64_t>(std::min<int64_t>(cx.ti_req, RING_MAXTI), a.c0)
-                       : pick_chunk(a.c0, tiles, slots, 2, RING_MAXTI);
+                       : std::min<int64_t>((a.c0 + nch - 1) / nch, RING_MAXTI);
   cx.slots_out = slots;
   cx.ti_out = (int)a.TI;
   if (cx.dry) return;
@@ -2289,10 +2329,24 @@ thread_local int g_plain_lv = 0;  // PlainLoadVector guards active on this threa
 // ring workgroup's 147 KB of LDS leaves none of; measured at 513^3 FP64 the
 // ring took 0.388 ms there against 0.352, and the coarser levels' load
 // vectors beside it 0.479 against 0.297.)
+//
+// It also needs a tiling that fills the device: one ring workgroup per CU,
+// chunks of at least 32 coarse planes (the pipeline fills and drains once
+// per chunk), and at least 90% of the CUs busy in one round (measured: 513^3
+// FP64 fills all 256 CUs with 128 tiles x 2 chunks and gains, 0.551 -> 0.530
+// ms; 400^3 gets 91 tiles x 2 chunks, 71% of the CUs, and loses, 0.65 ->
+// 0.79 ms).
+bool ring_fills(const Level &L) {
+  const int64_t tiles = (int64_t)ring_tiles(L.c[2], TK) * ring_tiles(L.c[1], 16);
+  const int64_t cus = device_cus();
+  const int64_t nch = std::max<int64_t>(1, std::min<int64_t>(L.c[0], cus / std::max<int64_t>(tiles, 1)));
+  const int64_t ti = (L.c[0] + nch - 1) / nch;
+  return ti >= 32 && ti <= RING_MAXTI && 10 * tiles * nch >= 9 * cus;
+}
 template <typename T, typename TS, bool DEC>
 bool ring_applies(const Level &L, const LoadArgs<T, TS> &a) {
   return DEC && g_plain_lv == 0 && sizeof(TS) == 8 && a.omap.t0 == nullptr && L.co[0] && L.co[1] && L.co[2] &&
-         a.out != nullptr;
+         a.out != nullptr && ring_fills(L);
 }
 
 template <typename T, typename TS, bool DEC>
@@ -2303,7 +2357,8 @@ void launch_loadvec(const Level &L, LoadArgs<T, TS> a, Ctx &cx) {
   a.W0 = L.d[0].W; a.W1 = L.d[1].W; a.W2 = L.d[2].W;
   a.gx = (int)((a.c2 + TK - 1) / TK);  // a.gy: by the kernel's tile, in launch_loadvec_t
   if constexpr (DEC && sizeof(T) == 8 && sizeof(TS) == 8) {
-    if (ring_applies<T, TS, DEC>(L, a)) {
+    // recorded launches (4-D slices, batches) take the grouped k_loadvec
+    if (!cx.rec && ring_applies<T, TS, DEC>(L, a)) {
       launch_loadvec_ring<T, TS, 16>(a, cx);
       cx.check("k_loadvec_ring launch");
       return;
@@ -2839,18 +2894,30 @@ void solve_all4(double *F, const Level &L, const Level &Lt, const Epi<T> &last, 
     w.v.d[0] = Lt.d[2];
     views.push_back(w);
   }
+  // recorded solves take phases cx.phase + 2, + 3, ... (after the load vectors
+  // and the time load vector)
+  const int p0 = cx.phase;
   for (size_t q = 0; q < views.size() && cx.ok; ++q) {
     const Epi<T> ep = (q + 1 == views.size()) ? last : Epi<T>{EPI_Z, nullptr, Map3{}};
+    cx.phase = p0 + 2 + (int)q;
     launch_solve<T>(F, views[q].v, views[q].axis, ep, cx);
   }
+  cx.phase = p0;
 }
 
 void launch_tload(const double *G, const Level &Lt, double *F, int64_t ncs, Ctx &cx) {
   const int64_t tm = Lt.m[2], ct = Lt.c[2];
   const int64_t nrun = (ct + TL_JC - 1) / TL_JC;
   const dim3 grid((unsigned)((ncs + 255) / 256), (unsigned)std::min<int64_t>(nrun, 65535));
-  TimedLaunch tl(cx.stream, "k_tload", timing_enabled() ? 8.0 * (double)(tm + ct) * (double)ncs : 0.0);
-  hipLaunchKernelGGL(k_tload, grid, dim3(256), 0, cx.stream, G, tm, Lt.d[2].W, F, ct, ncs);
+  const double bytes = timing_enabled() ? 8.0 * (double)(tm + ct) * (double)ncs : 0.0;
+  const double *W = Lt.d[2].W;
+  const int p0 = cx.phase;
+  cx.phase = p0 + 1;
+  emit_direct(cx, [=](hipStream_t st) {
+    TimedLaunch tl(st, "k_tload", bytes);
+    hipLaunchKernelGGL(k_tload, grid, dim3(256), 0, st, G, tm, W, F, ct, ncs);
+  });
+  cx.phase = p0;
   cx.check("k_tload launch");
 }
 
@@ -2871,9 +2938,12 @@ void launch_tfine(const Plan &pl, const Level &L, const Level &Lt, const TS *src
   const int64_t sm = L.m[0] * L.m[1] * L.m[2];
   const int64_t jobs = nf * L.m[0] * ((L.m[1] + TF_ROWS - 1) / TF_ROWS);  // row groups of the time-fine slices
   const dim3 grid((unsigned)std::min<int64_t>(jobs, (int64_t)1 << 20));
-  TimedLaunch tl(cx.stream, std::string("k_tfine<") + tname<T>() + ", " + bname(DEC) + ">",
-                 timing_enabled() ? (double)nf * (double)sm * (sizeof(T) + sizeof(TS)) : 0.0);
-  hipLaunchKernelGGL((k_tfine<T, TS, DEC>), grid, dim3(TF_THR), 0, cx.stream, a);
+  const std::string label = std::string("k_tfine<") + tname<T>() + ", " + bname(DEC) + ">";
+  const double bytes = timing_enabled() ? (double)nf * (double)sm * (sizeof(T) + sizeof(TS)) : 0.0;
+  emit_direct(cx, [=](hipStream_t st) {
+    TimedLaunch tl(st, label, bytes);
+    hipLaunchKernelGGL((k_tfine<T, TS, DEC>), grid, dim3(TF_THR), 0, st, a);
+  });
   cx.check("k_tfine launch");
 }
 
@@ -2882,10 +2952,16 @@ void launch_nodal4(const Plan &pl, const TS *src, TD *dst, Ctx &cx) {
   const Level &L = pl.lev[pl.nlev];
   const Level &Lt = pl.time->lev[pl.nlev];
   const int64_t n = Lt.m[2] * L.m[0] * L.m[1] * L.m[2];
-  TimedLaunch tl(cx.stream, std::string("k_nodal4<") + tname<TD>() + ", " + bname(TO_NODAL) + ">",
-                 timing_enabled() ? (double)n * (sizeof(TS) + sizeof(TD)) : 0.0);
-  hipLaunchKernelGGL((k_nodal4<TS, TD, TO_NODAL>), dim3((unsigned)grid_1d(n, 256)), dim3(256), 0, cx.stream, src, dst,
-                     nodal_map(L), Lt.d[2].nodal, pl.n[0] * pl.n[1] * pl.n[2], Lt.m[2], L.m[0], L.m[1], L.m[2]);
+  const std::string label = std::string("k_nodal4<") + tname<TD>() + ", " + bname(TO_NODAL) + ">";
+  const double bytes = timing_enabled() ? (double)n * (sizeof(TS) + sizeof(TD)) : 0.0;
+  const Map3 nm = nodal_map(L);
+  const int64_t *tnod = Lt.d[2].nodal, S0 = pl.n[0] * pl.n[1] * pl.n[2], tm = Lt.m[2];
+  const int64_t m0 = L.m[0], m1 = L.m[1], m2 = L.m[2];
+  emit_direct(cx, [=](hipStream_t st) {
+    TimedLaunch tl(st, label, bytes);
+    hipLaunchKernelGGL((k_nodal4<TS, TD, TO_NODAL>), dim3((unsigned)grid_1d(n, 256)), dim3(256), 0, st, src, dst,
+                       nm, tnod, S0, tm, m0, m1, m2);
+  });
   cx.check("k_nodal4 launch");
 }
 
@@ -2918,12 +2994,22 @@ void decompose4_level(const Plan &pl, int s, const TS *src, T *out, double *next
   }
   if (cot && cx.ok) launch_tload(w.G, Lt, w.F, cs, cx);
   solve_all4<double>(w.F, L, Lt, Epi<double>{EPI_STORE_COMPACT, next, Map3{}}, cx);
+  const int p0 = cx.phase;
+  cx.phase = p0 + 6;
   if (cot && cx.ok) launch_tfine<T, TS, true>(pl, L, Lt, src, out, src, omap, cx);
+  cx.phase = p0;
 }
 
+// The 4-D drivers record their launches (per level: the time slices' space
+// load vectors at phase 8s, the time load vector +1, the solves +2.., the
+// time-fine slices +6; a recomposition's reconstructs +6 and time-fine
+// slices +7) and launch them grouped: the slices' load vectors and
+// reconstructs of one level go out as one grid each (Sec. III-D).
 template <typename T>
 bool decompose4_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t stream, std::string &err) {
+  Rec rec;
   Ctx cx{stream, &err};
+  cx.rec = &rec;
   const int64_t S0 = pl.n[0] * pl.n[1] * pl.n[2];
   if (pl.nlev == 0) {
     if (hipMemcpyAsync(out, in, pl.nt * S0 * sizeof(T), hipMemcpyDeviceToDevice, stream) != hipSuccess) {
@@ -2936,12 +3022,14 @@ bool decompose4_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t str
   const double *src = nullptr;
   for (int s = 0; s < pl.nlev && cx.ok; ++s) {
     double *next = (double *)w.buf[s % 2];
+    cx.phase = phase_dec_level(s);
     if (s == 0) decompose4_level<T, T>(pl, s, in, out, next, w, cx);
     else decompose4_level<T, double>(pl, s, src, out, next, w, cx);
     src = next;
   }
+  cx.phase = kPhaseTail;
   if (cx.ok) launch_nodal4<double, T, true>(pl, src, out, cx);
-  return cx.ok;
+  return cx.ok && launch_recorded(rec, stream, err);
 }
 
 // One level of a 4-D recomposition: the load vector of the stored
@@ -2951,7 +3039,9 @@ bool decompose4_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t str
 // space reconstruct from their coarse slice, time-fine slices by k_tfine.
 template <typename T>
 bool recompose4_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t stream, std::string &err) {
+  Rec rec;
   Ctx cx{stream, &err};
+  cx.rec = &rec;
   const int64_t S0 = pl.n[0] * pl.n[1] * pl.n[2];
   if (pl.nlev == 0) {
     if (hipMemcpyAsync(out, in, pl.nt * S0 * sizeof(T), hipMemcpyDeviceToDevice, stream) != hipSuccess) {
@@ -2963,10 +3053,13 @@ bool recompose4_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t str
   const Plan &tp = *pl.time;
   Workspace4 w = carve4(pl, ws);
   T *V = (T *)w.buf[pl.nlev % 2];
+  cx.phase = 0;
   launch_nodal4<T, T, false>(pl, in, V, cx);
   for (int s = pl.nlev - 1; s >= 0 && cx.ok; --s) {
     const Level &L = pl.lev[s];
     const Level &Lt = tp.lev[s];
+    const int p0 = phase_rec_level(s);
+    cx.phase = p0;
     const int64_t tm = Lt.m[2], ct = Lt.c[2];
     const bool cot = Lt.co[2];
     const int64_t sm = L.m[0] * L.m[1] * L.m[2], cs = L.c[0] * L.c[1] * L.c[2];
@@ -2983,15 +3076,17 @@ bool recompose4_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t str
     }
     if (cot && cx.ok) launch_tload(w.G, Lt, w.F, cs, cx);
     solve_all4<T>(w.F, L, Lt, Epi<T>{EPI_SUB_COMPACT, V, Map3{}}, cx);
+    cx.phase = p0 + 6;
     for (int64_t t = 0; t < tm && cx.ok; ++t) {
       if (cot && !tcoarse(t, tm)) continue;
       const int64_t J = cot ? tcoarse_idx(t, tm, ct) : t;
       launch_reconstruct<T>(L, in + pl.tpos[s][t] * S0, cmap, V + J * cs, dst + t * sm, cx);
     }
+    cx.phase = p0 + 7;
     if (cot && cx.ok) launch_tfine<T, T, false>(pl, L, Lt, in, dst, V, cmap, cx);
     V = dst;
   }
-  return cx.ok;
+  return cx.ok && launch_recorded(rec, stream, err);
 }
 
 // ------------------------------------------------------------ autotuner
@@ -3111,7 +3206,8 @@ bool autotune_t(Plan &pl, const T *in, T *out, void *ws, hipStream_t stream, std
       // the finest FP64 level runs the ring kernel (its tiles absorb a single
       // left-over row or column); other levels k_loadvec, whose field-side
       // array is nodal below level 0
-      const bool ring = dec && s == 0 && sizeof(T) == 8 && L.co[0] && L.co[1] && L.co[2] && g_plain_lv == 0;
+      const bool ring = dec && s == 0 && sizeof(T) == 8 && L.co[0] && L.co[1] && L.co[2] && g_plain_lv == 0 &&
+                        ring_fills(L);
       const int tj = ring ? 16 : tile_rows<T>(dec != 0, s > 0);
       const int64_t tiles_lv = ring ? (int64_t)ring_tiles(L.c[2], TK) * ring_tiles(L.c[1], tj)
                                     : ((L.c[2] + TK - 1) / TK) * ((L.c[1] + tj - 1) / tj);
@@ -3290,10 +3386,11 @@ bool enqueue_batch(bool dec, const std::vector<BatchItem> &items, void *stream, 
       if (!ok) return false;
     }
   }
-  // phase by phase; within a phase, the jobs of one kernel share launches (in
-  // the order they first appear), each launch sized for its largest job:
-  // a solver workgroup of a job with fewer partitions leaves the extra waves
-  // idle
+  return launch_recorded(rec, st, err);
+}
+
+namespace {
+bool launch_recorded(const Rec &rec, hipStream_t st, std::string &err) {
   std::vector<const RecJob *> js;
   js.reserve(rec.jobs.size());
   for (const RecJob &r : rec.jobs) js.push_back(&r);
@@ -3344,6 +3441,7 @@ bool enqueue_batch(bool dec, const std::vector<BatchItem> &items, void *stream, 
   }
   return true;
 }
+}  // namespace
 
 PlainLoadVector::PlainLoadVector() { ++g_plain_lv; }
 PlainLoadVector::~PlainLoadVector() { --g_plain_lv; }
