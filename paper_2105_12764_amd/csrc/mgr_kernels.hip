@@ -3124,7 +3124,7 @@ double model_march(int64_t c0, int64_t tiles, int slots, int halo, int64_t ti, d
 // rows' coefficient reads and level-grid writes, line by line per tile
 // (nodal coefficients use half of every line), and the coarse tiles.
 double recon_bytes_per_plane(const Level &L, bool nodal, size_t es, int64_t tj, int64_t tk) {
-  const int64_t SJ = L.co[1] ? 2 : 1, SK = L.co[2] ? 2 : 1, s0 = L.co[0] ? 2 : 1;
+  const int64_t SK = L.co[2] ? 2 : 1, s0 = L.co[0] ? 2 : 1;
   const int64_t gx = (L.c[2] + tk - 1) / tk, gy = (L.c[1] + tj - 1) / tj;
   int64_t fine = 0;
   for (int64_t j = 0; j < L.m[1]; ++j)
