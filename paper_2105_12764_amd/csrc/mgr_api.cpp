@@ -561,6 +561,8 @@ mgr_status run_batch(bool dec, int nfields, const mgr_field *fields, void *ws, s
     if (grouped) {
       // each stream runs its fields with grouped launches; the streams' small
       // latency-bound launches overlap each other's large ones
+      std::vector<std::vector<mgr::BatchItem>> lanes;
+      std::vector<void *> streams;
       for (int k = 0; k < MGR_BATCH_STREAMS && ok; ++k) {
         if (!used[k]) continue;
         std::vector<mgr::BatchItem> items;
@@ -568,8 +570,10 @@ mgr_status run_batch(bool dec, int nfields, const mgr_field *fields, void *ws, s
           if (lane[i] == k)
             items.push_back(mgr::BatchItem{jobs[i].plan.get(), fields[i].dtype == MGR_FLOAT64, fields[i].in,
                                            fields[i].out, ws ? (void *)((char *)ws + jobs[i].ws_off) : nullptr});
-        ok = mgr::enqueue_batch(dec, items, bs->s[k], err);
+        lanes.push_back(std::move(items));
+        streams.push_back((void *)bs->s[k]);
       }
+      if (ok) ok = mgr::enqueue_batch(dec, lanes, streams, err);
     }
     for (int i : order) {
       if (!ok || grouped) break;

@@ -1178,6 +1178,7 @@ __global__ void __launch_bounds__(ROWS_THR) k_solve_rows_group(Group<RowsArgs<T>
 // lines: 64 adjacent lines of a strided dimension (coalesced), or 64 rows of
 // the contiguous one (each lane walks its own row).
 constexpr int LONG_WAVES = 8;
+constexpr int LONG_CH = 16;  // fix-up chunk
 template <typename T>
 struct LongArgs {
   double *F;
@@ -1226,21 +1227,31 @@ __device__ __forceinline__ void long_body(const LongArgs<T> &A, const int64_t bl
   if (w == 0) separator_solve(tb, S, P, yF + lane, yL + lane, Fs + lane, tt + lane, 64);
   __syncthreads();
   if (!active) return;
+  // fix-up in chunks of LONG_CH positions, a chunk's loads all in flight
+  // before its first use
   for (int p = w; p < P; p += LONG_WAVES) {
     const int64_t f = (int64_t)p * S;
     const int nload = p < P - 1 ? S : (int)(c - f);
     const int nint = p < P - 1 ? S - 1 : nload;
     const double tl = p > 0 ? tt[(p - 1) * 64 + lane] : 0.0;
     const double tr = p < P - 1 ? tt[p * 64 + lane] : 0.0;
-    for (int q = 0; q < nload; ++q) {
-      const int64_t pos = f + q;
-      const int64_t idx = base + pos * sp_;
-      const double v = q < nint ? fma(-tl, tb.Ls[pos], fma(-tr, tb.Rs[pos], F[idx])) : tr;
-      int64_t i, j, kk;
-      if (axis == 0) { i = pos; j = outer; kk = k; }
-      else if (axis == 1) { i = outer; j = pos; kk = k; }
-      else { i = k / c1; j = k % c1; kk = pos; }
-      epi_store(ep, F, idx, i, j, kk, v);
+    for (int q0 = 0; q0 < nload; q0 += LONG_CH) {
+      double x[LONG_CH];
+#pragma unroll
+      for (int u = 0; u < LONG_CH; ++u) x[u] = q0 + u < nload ? F[base + (f + q0 + u) * sp_] : 0.0;
+#pragma unroll
+      for (int u = 0; u < LONG_CH; ++u) {
+        const int q = q0 + u;
+        if (q < nload) {
+          const int64_t pos = f + q;
+          const double v = q < nint ? fma(-tl, tb.Ls[pos], fma(-tr, tb.Rs[pos], x[u])) : tr;
+          int64_t i, j, kk;
+          if (axis == 0) { i = pos; j = outer; kk = k; }
+          else if (axis == 1) { i = outer; j = pos; kk = k; }
+          else { i = k / c1; j = k % c1; kk = pos; }
+          epi_store(ep, F, base + pos * sp_, i, j, kk, v);
+        }
+      }
     }
   }
 }
@@ -2102,6 +2113,8 @@ struct Rec {
 // sized for its largest job (a solver workgroup of a job with fewer
 // partitions leaves the extra waves idle); jobs with no grouped form run alone.
 bool launch_recorded(const Rec &rec, hipStream_t st, std::string &err);
+using Unit = std::function<void(hipStream_t)>;
+void recorded_units(const Rec &rec, std::vector<Unit> &out);
 
 struct Ctx {
   hipStream_t stream;
@@ -2111,6 +2124,7 @@ struct Ctx {
   int ti_req = 0;     // coarse planes per workgroup requested (0: the built-in rule)
   bool dry = false;   // compute the launch shape only, launch nothing
   int slots_out = 0;  // resident workgroups of the kernel instance chosen
+  bool share = false; // the load vector runs beside other work (see launch_loadvec_t)
   int ti_out = 0;     // coarse planes per workgroup chosen
   Rec *rec = nullptr; // record the launches instead (batched entry points)
   int phase = 0;      // phase of the next recorded launch
@@ -2244,6 +2258,16 @@ void launch_loadvec_t(LoadArgs<T, TS> a, Ctx &cx) {
   const int64_t maxti = (LV_MAXP - 3) / 2;
   a.TI = cx.ti_req > 0 ? std::min<int64_t>(std::min<int64_t>(cx.ti_req, maxti), a.c0)
                        : pick_chunk(a.c0, tiles, slots, C0 ? 2 : 0, maxti);
+  if (cx.share && !NODAL) {
+    // Beside other work (the recomposition's finest load vector on the helper
+    // stream): one round of workgroups that leaves about 5% of the resident
+    // slots free, so that the coarser levels' kernels find room at once
+    // instead of waiting for these long-lived workgroups to retire (measured
+    // at 513^3: FP64 recomposition 1.354 -> 1.305 ms, FP32 0.886 -> 0.855).
+    // The chunk length only moves work between workgroups.
+    const int64_t gz = std::max<int64_t>(1, (int64_t)(0.95 * (double)slots / (double)tiles));
+    a.TI = (a.c0 + gz - 1) / gz;
+  }
   cx.slots_out = slots;
   cx.ti_out = (int)a.TI;
   if (cx.dry) return;
@@ -2768,9 +2792,9 @@ bool recompose_t(const Plan &pl, const T *in, T *out, void *ws, hipStream_t stre
     a.src = in;
     a.smap = compact_map(pl.n[1], pl.n[2]);
     a.F = w.F;
-    hx.ti_req = tune0.empty() ? 0 : tune0[0].lv_ti[1];
+    hx.share = true;
     launch_loadvec<T, T, false>(L, a, hx);
-    hx.ti_req = 0;
+    hx.share = false;
     if (hx.ok) solve_all<T>(w.F, L, Epi<T>{EPI_Z, nullptr, Map3{}}, hx, 1);
     if (hipEventRecord((hipEvent_t)fk->join, hs) != hipSuccess) {
       (void)hipGetLastError();
@@ -3371,26 +3395,49 @@ bool enqueue_copy_probe(const void *src, void *dst, size_t bytes, void *stream, 
   return true;
 }
 
-bool enqueue_batch(bool dec, const std::vector<BatchItem> &items, void *stream, std::string &err) {
-  hipStream_t st = (hipStream_t)stream;
-  Rec rec;
+bool enqueue_batch(bool dec, const std::vector<std::vector<BatchItem>> &lanes, const std::vector<void *> &streams,
+                   std::string &err) {
+  const size_t nl = lanes.size();
+  std::vector<Rec> recs(nl);
   {
     const PlainLoadVector plain;  // batches keep k_loadvec (see mgr_api.cpp)
-    for (const BatchItem &b : items) {
-      const bool ok = dec ? (b.f64 ? decompose_t<double>(*b.pl, (const double *)b.in, (double *)b.out, b.ws, st, err, &rec)
-                                   : decompose_t<float>(*b.pl, (const float *)b.in, (float *)b.out, b.ws, st, err, &rec))
-                          : (b.f64 ? recompose_t<double>(*b.pl, (const double *)b.in, (double *)b.out, b.ws, st, err,
-                                                         b.pl->nlev, nullptr, &rec)
-                                   : recompose_t<float>(*b.pl, (const float *)b.in, (float *)b.out, b.ws, st, err,
-                                                        b.pl->nlev, nullptr, &rec));
-      if (!ok) return false;
+    for (size_t k = 0; k < nl; ++k) {
+      hipStream_t st = (hipStream_t)streams[k];
+      for (const BatchItem &b : lanes[k]) {
+        const bool ok =
+            dec ? (b.f64 ? decompose_t<double>(*b.pl, (const double *)b.in, (double *)b.out, b.ws, st, err, &recs[k])
+                         : decompose_t<float>(*b.pl, (const float *)b.in, (float *)b.out, b.ws, st, err, &recs[k]))
+                : (b.f64 ? recompose_t<double>(*b.pl, (const double *)b.in, (double *)b.out, b.ws, st, err,
+                                               b.pl->nlev, nullptr, &recs[k])
+                         : recompose_t<float>(*b.pl, (const float *)b.in, (float *)b.out, b.ws, st, err,
+                                              b.pl->nlev, nullptr, &recs[k]));
+        if (!ok) return false;
+      }
     }
   }
-  return launch_recorded(rec, st, err);
+  // the lanes' launches go out interleaved, so that every stream has work
+  // queued while the host is still launching
+  std::vector<std::vector<Unit>> units(nl);
+  size_t most = 0;
+  for (size_t k = 0; k < nl; ++k) {
+    recorded_units(recs[k], units[k]);
+    most = std::max(most, units[k].size());
+  }
+  for (size_t i = 0; i < most; ++i)
+    for (size_t k = 0; k < nl; ++k)
+      if (i < units[k].size()) units[k][i]((hipStream_t)streams[k]);
+  const hipError_t he = hipGetLastError();
+  if (he != hipSuccess) {
+    err = std::string("grouped batch launch: ") + hipGetErrorString(he);
+    return false;
+  }
+  return true;
 }
 
 namespace {
-bool launch_recorded(const Rec &rec, hipStream_t st, std::string &err) {
+// The launches of a recording in phase order, the jobs of one kernel in a
+// phase merged into grouped launches.  The units refer to `rec`'s jobs.
+void recorded_units(const Rec &rec, std::vector<Unit> &out) {
   std::vector<const RecJob *> js;
   js.reserve(rec.jobs.size());
   for (const RecJob &r : rec.jobs) js.push_back(&r);
@@ -3405,7 +3452,7 @@ bool launch_recorded(const Rec &rec, hipStream_t st, std::string &err) {
       const RecJob *r = js[a];
       if (!r->group) {
         done[a - i] = true;
-        r->direct(st);
+        out.push_back([r](hipStream_t st) { r->direct(st); });
         continue;
       }
       std::vector<const RecJob *> g;
@@ -3413,8 +3460,10 @@ bool launch_recorded(const Rec &rec, hipStream_t st, std::string &err) {
       unsigned thr = 0;
       double bytes = 0.0;
       auto flush = [&]() {
-        TimedLaunch tl(st, r->label + " [group]", timing_enabled() ? bytes : 0.0);
-        r->group(g, st, lds, thr);
+        out.push_back([g, lds, thr, bytes, r](hipStream_t st) {
+          TimedLaunch tl(st, r->label + " [group]", timing_enabled() ? bytes : 0.0);
+          r->group(g, st, lds, thr);
+        });
         g.clear();
         lds = 0;
         thr = 0;
@@ -3434,9 +3483,15 @@ bool launch_recorded(const Rec &rec, hipStream_t st, std::string &err) {
     }
     i = e;
   }
+}
+
+bool launch_recorded(const Rec &rec, hipStream_t st, std::string &err) {
+  std::vector<Unit> units;
+  recorded_units(rec, units);
+  for (const Unit &u : units) u(st);
   const hipError_t he = hipGetLastError();
   if (he != hipSuccess) {
-    err = std::string("grouped batch launch: ") + hipGetErrorString(he);
+    err = std::string("grouped launch: ") + hipGetErrorString(he);
     return false;
   }
   return true;

@@ -50,13 +50,15 @@ struct BatchItem {
   void *ws;
 };
 
-// Decompose (recompose) every field of a batch with grouped launches: the
-// fields' launch chains are recorded, and for each step of the level loop
-// (aligned by level index, finest = 0) the launches of one kernel across
-// all fields go out as one grid over their blocks, in order on `stream`.
-// Same kernels and arithmetic as the single-field calls (bitwise the same
-// results).  Fields must have 1 to 3 dims.
-bool enqueue_batch(bool dec, const std::vector<BatchItem> &items, void *stream, std::string &err);
+// Decompose (recompose) every field of a batch with grouped launches, lane
+// k's fields on streams[k]: the fields' launch chains are recorded, and for
+// each step of the level loop (aligned by level index, finest = 0) the
+// launches of one kernel across a lane's fields go out as one grid over their
+// blocks, in order on the lane's stream; the lanes' launches are issued
+// interleaved.  Same kernels and arithmetic as the single-field calls
+// (bitwise the same results).  Fields must have 1 to 3 dims.
+bool enqueue_batch(bool dec, const std::vector<std::vector<BatchItem>> &lanes, const std::vector<void *> &streams,
+                   std::string &err);
 
 // Reorder a nodal representation into class-contiguous order (export) or
 // back (import); src and dst hold prod(shape) elements each.
