@@ -3338,6 +3338,31 @@ bool autotune_t(Plan &pl, const T *in, T *out, void *ws, hipStream_t stream, std
         tune[s].rc_tk = shapes[best].second;
         report += "level " + std::to_string(s) + " reconstruct tile " + std::to_string(tune[s].rc_tj) + " x " +
                   std::to_string(tune[s].rc_tk) + " coarse rows x columns\n";
+        // then its coarse planes per workgroup: the built-in rule against
+        // the chunks that cut dim 0 into 1 to 8 pieces
+        const int tj = tune[s].rc_tj, tk = tune[s].rc_tk;
+        cx.dry = true;
+        launch_reconstruct<T>(L, in, cmap, uc, dst, cx, tj, tk);
+        cx.dry = false;
+        const int ti0 = cx.ti_out, slots = cx.slots_out;
+        const int64_t tiles = ((L.c[2] + tk - 1) / tk) * ((L.c[1] + tj - 1) / tj);
+        const int64_t maxti = (LV_MAXP - 2) / 2;
+        const double bpp = recon_bytes_per_plane(L, nodal, es, tj, tk);
+        const int halo = L.co[0] ? 1 : 0;
+        std::vector<std::pair<double, int>> tcand = {{model_march(L.c[0], tiles, slots, halo, ti0, bpp), ti0}};
+        for (int k = 1; k <= 8; ++k) {
+          const int64_t ti = (L.c[0] + k - 1) / k;
+          if (ti < 1 || ti > maxti) continue;
+          bool dup = false;
+          for (auto &c : tcand) dup |= c.second == (int)ti;
+          if (!dup) tcand.push_back({model_march(L.c[0], tiles, slots, halo, ti, bpp), (int)ti});
+        }
+        const int bti = choose(tcand, ti0, [&](int ti) {
+          cx.ti_req = ti;
+          launch_reconstruct<T>(L, in, cmap, uc, dst, cx, tj, tk);
+          cx.ti_req = 0;
+        }, "reconstruct planes per workgroup", s);
+        tune[s].rc_ti = bti > 0 ? bti : 0;
       }
     }
   }
