@@ -1625,13 +1625,16 @@ struct TfineArgs {
 // time lerp (weight rt[t] of the later slice) of the coarse values of slices
 // t - 1 and t + 1.  Decompose: coefficient = value - interpolant; recompose:
 // value = coefficient + interpolant.  A workgroup takes TF_ROWS fine rows of
-// one plane i of one such slice at a time: it stages in LDS, for the coarse
-// rows and columns they need, the lerp in time and along dim 0 (four loads
-// per coarse node), then each fine node interpolates along dims 1 and 2 from
-// LDS.
+// one plane i of one such slice at a time.  Each thread first loads the values
+// of its fine columns (TF_KPT per pass of TF_CH columns, all rows), then
+// stages in LDS, for the coarse rows and columns they need, the lerp in time
+// and along dim 0 (four loads per coarse node), so that both sets of loads
+// are in flight together; then each fine node interpolates along dims 1 and 2
+// from LDS.
 constexpr int TF_THR = 256;
 constexpr int TF_ROWS = 8;   // fine rows (dim 1) per workgroup
 constexpr int TF_CH = 512;   // fine columns (dim 2) per pass
+constexpr int TF_KPT = TF_CH / TF_THR;  // fine columns per thread per pass
 constexpr int TF_PITCH = TF_CH + 2;
 template <typename T, typename TS, bool DEC>
 __global__ void __launch_bounds__(TF_THR) k_tfine(TfineArgs<T, TS> a) {
@@ -1650,6 +1653,7 @@ __global__ void __launch_bounds__(TF_THR) k_tfine(TfineArgs<T, TS> a) {
     const int64_t q = job / (a.m0 * ngr), rem = job - q * (a.m0 * ngr);
     const int64_t i = rem / ngr, j0 = (rem - i * ngr) * TF_ROWS, j1 = min(j0 + TF_ROWS, a.m1);
     const int64_t t = 2 * q + 1;
+    const int nr = (int)(j1 - j0);
     int64_t l0, h0, J0, J1, lo, hi;
     double w0, w;
     nb_dim<DEC>(i, a.m0, a.c0, a.co0, a.r0, l0, h0, w0);
@@ -1659,9 +1663,30 @@ __global__ void __launch_bounds__(TF_THR) k_tfine(TfineArgs<T, TS> a) {
     // the earlier and later coarse slices (level positions t -/+ 1, or coarse indices q, q + 1)
     const TS *cl = a.crs + (DEC ? t - 1 : q) * ss + l0 * s0, *cr = a.crs + (DEC ? t + 1 : q + 1) * ss + l0 * s0;
     const int64_t dh = (h0 - l0) * s0;
-    const int64_t frow = a.tnod[t] * a.S0;  // this slice in the finest layout
+    // this slice's rows in the finest layout, and in the compact level grid
+    const int64_t frowi = a.tnod[t] * a.S0 + (a.fmap.t0 ? a.fmap.t0[i] : i * a.fmap.s0);
+    const int64_t lrow = t * sm + (i * a.m1 + j0) * a.m2;
+    int64_t frw[TF_ROWS];
+#pragma unroll
+    for (int jr = 0; jr < TF_ROWS; ++jr) {
+      const int64_t j = j0 + min(jr, nr - 1);
+      frw[jr] = frowi + (a.fmap.t0 ? a.fmap.t1[j] : j * a.fmap.s1);
+    }
     for (int64_t k0 = 0; k0 < a.m2; k0 += TF_CH) {
       const int64_t k1 = min(k0 + TF_CH, a.m2);
+      const int nk = (int)(k1 - k0);
+      // this thread's fine values first (branch-free: a column past the end
+      // reads the last one and is not stored)
+      TS x[TF_KPT][TF_ROWS];
+      int64_t fcol[TF_KPT];
+#pragma unroll
+      for (int u = 0; u < TF_KPT; ++u) {
+        const int64_t k = k0 + min(tid + u * TF_THR, nk - 1);
+        fcol[u] = a.fmap.t0 ? a.fmap.t2[k] : k;
+#pragma unroll
+        for (int jr = 0; jr < TF_ROWS; ++jr)
+          x[u][jr] = a.src[DEC ? lrow + min(jr, nr - 1) * a.m2 + k : frw[jr] + fcol[u]];
+      }
       int64_t K0, K1;
       nb_dim<false>(k0, a.m2, a.c2, a.co2, a.r2, K0, hi, w);
       nb_dim<false>(k1 - 1, a.m2, a.c2, a.co2, a.r2, lo, K1, w);
@@ -1687,26 +1712,17 @@ __global__ void __launch_bounds__(TF_THR) k_tfine(TfineArgs<T, TS> a) {
                 lerp(lerp((double)v[0][jr], (double)v[1][jr], w0), lerp((double)v[2][jr], (double)v[3][jr], w0), rt);
       }
       __syncthreads();
-      // fine nodes: each thread keeps its columns (neighbours, weight, offset)
-      // and walks the rows, whose neighbours are the same for every thread
-      const int nk = (int)(k1 - k0), nr = (int)(j1 - j0);
-      for (int kk = tid; kk < nk; kk += TF_THR) {
+      // fine nodes: each thread keeps its columns (neighbours, weight) and
+      // walks the rows, whose neighbours are the same for every thread
+#pragma unroll
+      for (int u = 0; u < TF_KPT; ++u) {
+        const int kk = tid + u * TF_THR;
+        if (kk >= nk) break;
         const int64_t k = k0 + kk;
         int64_t kl, kh;
         double wk;
         nb_dim<false>(k, a.m2, a.c2, a.co2, a.r2, kl, kh, wk);
         const int ql = (int)(kl - K0), qh = (int)(kh - K0);
-        const int64_t fcol = a.fmap.t0 ? a.fmap.t2[k] : k;
-        const int64_t frowi = frow + (a.fmap.t0 ? a.fmap.t0[i] : i * a.fmap.s0);
-        TS x[TF_ROWS];
-        int64_t fo[TF_ROWS], lv[TF_ROWS];
-#pragma unroll
-        for (int jr = 0; jr < TF_ROWS; ++jr) {
-          const int64_t j = j0 + min(jr, nr - 1);
-          fo[jr] = frowi + (a.fmap.t0 ? a.fmap.t1[j] : j * a.fmap.s1) + fcol;
-          lv[jr] = t * sm + (i * a.m1 + j) * a.m2 + k;
-          x[jr] = a.src[DEC ? lv[jr] : fo[jr]];
-        }
 #pragma unroll
         for (int jr = 0; jr < TF_ROWS; ++jr) {
           if (jr >= nr) break;
@@ -1716,9 +1732,9 @@ __global__ void __launch_bounds__(TF_THR) k_tfine(TfineArgs<T, TS> a) {
           const double *rl = sR + (jl - J0) * TF_PITCH, *rh = sR + (jh - J0) * TF_PITCH;
           const double pi = lerp(lerp(rl[ql], rl[qh], wk), lerp(rh[ql], rh[qh], wk), wj);
           if (DEC)
-            a.dst[fo[jr]] = (T)((double)x[jr] - pi);
+            a.dst[frw[jr] + fcol[u]] = (T)((double)x[u][jr] - pi);
           else
-            a.dst[lv[jr]] = (T)((double)x[jr] + pi);
+            a.dst[lrow + jr * a.m2 + k] = (T)((double)x[u][jr] + pi);
         }
       }
       __syncthreads();
