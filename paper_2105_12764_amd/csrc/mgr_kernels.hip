@@ -514,6 +514,10 @@ typedef __attribute__((address_space(3))) void *lds_ptr;
 // such load in flight before reading any staged plane whose independence it
 // cannot prove.  The kernel's own vmcnt waits and LDS barriers order the
 // loads with the reads.  One wait state between writing M0 and the load.
+// M0 is a reserved register: the compiler warns that it may not honour the
+// clobber, so this is safe only while compiled code keeps nothing of its own
+// in M0 in the kernels that use it (in the ring kernels every instruction
+// naming M0 is this block's write; a CPU test checks the assembly).
 __device__ __forceinline__ void lds_dma_dword(const void *src, unsigned lds) {
   asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dword %1, off" : : "s"(lds), "v"(src) : "memory", "m0");
 }
