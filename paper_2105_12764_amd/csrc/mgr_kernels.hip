@@ -1629,119 +1629,153 @@ struct TfineArgs {
 // time lerp (weight rt[t] of the later slice) of the coarse values of slices
 // t - 1 and t + 1.  Decompose: coefficient = value - interpolant; recompose:
 // value = coefficient + interpolant.  A workgroup takes TF_ROWS fine rows of
-// one plane i of one such slice at a time.  Each thread first loads the values
-// of its fine columns (TF_KPT per pass of TF_CH columns, all rows), then
-// stages in LDS, for the coarse rows and columns they need, the lerp in time
-// and along dim 0 (four loads per coarse node), so that both sets of loads
-// are in flight together; then each fine node interpolates along dims 1 and 2
-// from LDS.
+// TF_PI consecutive planes of one such slice, TF_CH columns at a time, and
+// marches along dim 0: the time lerp of each coarse plane it needs is staged
+// once in one of two LDS slots (the coarse rows and columns the fine rows
+// need), and a fine plane between two coarse planes lerps the two slots along
+// dim 0 before the bilinear interpolation in dims 1 and 2.  Each thread takes
+// one fine column of every row.
 constexpr int TF_THR = 256;
 constexpr int TF_ROWS = 8;   // fine rows (dim 1) per workgroup
-constexpr int TF_CH = 512;   // fine columns (dim 2) per pass
-constexpr int TF_KPT = TF_CH / TF_THR;  // fine columns per thread per pass
+constexpr int TF_CH = 256;   // fine columns (dim 2) per pass, one per thread
+constexpr int TF_PI = 16;    // fine planes (dim 0) per workgroup
 constexpr int TF_PITCH = TF_CH + 2;
 template <typename T, typename TS, bool DEC>
 __global__ void __launch_bounds__(TF_THR) k_tfine(TfineArgs<T, TS> a) {
-  __shared__ double sR[TF_ROWS * TF_PITCH];
+  __shared__ double sT[2][TF_ROWS * TF_PITCH];
   const int tid = threadIdx.x;
   const int64_t sm = a.m0 * a.m1 * a.m2;
   const int64_t nf = (a.tm - 1) / 2;  // odd positions below the last
   const int64_t ngr = (a.m1 + TF_ROWS - 1) / TF_ROWS;
+  const int64_t npc = (a.m0 + TF_PI - 1) / TF_PI;
   // strides of the array holding the coarse values (DEC: the level grid)
   const int64_t s1 = DEC ? a.m2 : a.c2, s0 = s1 * (DEC ? a.m1 : a.c1), ss = s0 * (DEC ? a.m0 : a.c0);
   // array position of coarse index X along a dim (DEC: its level position)
   auto cpos = [](int64_t X, int64_t m, int64_t c, int co) -> int64_t {
     return (DEC && co) ? (X == c - 1 ? m - 1 : 2 * X) : X;
   };
-  for (int64_t job = blockIdx.x; job < nf * a.m0 * ngr; job += gridDim.x) {
-    const int64_t q = job / (a.m0 * ngr), rem = job - q * (a.m0 * ngr);
-    const int64_t i = rem / ngr, j0 = (rem - i * ngr) * TF_ROWS, j1 = min(j0 + TF_ROWS, a.m1);
+  for (int64_t job = blockIdx.x; job < nf * npc * ngr; job += gridDim.x) {
+    const int64_t q = job / (npc * ngr), rem = job - q * (npc * ngr);
+    const int64_t pc = rem / ngr, g = rem - pc * ngr;
+    const int64_t j0 = g * TF_ROWS, j1 = min(j0 + TF_ROWS, a.m1);
+    const int64_t i0 = pc * TF_PI, i1 = min(i0 + TF_PI, a.m0);
     const int64_t t = 2 * q + 1;
     const int nr = (int)(j1 - j0);
-    int64_t l0, h0, J0, J1, lo, hi;
-    double w0, w;
-    nb_dim<DEC>(i, a.m0, a.c0, a.co0, a.r0, l0, h0, w0);
+    int64_t J0, J1, lo, hi;
+    double w;
     nb_dim<false>(j0, a.m1, a.c1, a.co1, a.r1, J0, hi, w);
     nb_dim<false>(j1 - 1, a.m1, a.c1, a.co1, a.r1, lo, J1, w);
+    const int nJ = (int)(J1 - J0 + 1);
     const double rt = a.rt[t];
     // the earlier and later coarse slices (level positions t -/+ 1, or coarse indices q, q + 1)
-    const TS *cl = a.crs + (DEC ? t - 1 : q) * ss + l0 * s0, *cr = a.crs + (DEC ? t + 1 : q + 1) * ss + l0 * s0;
-    const int64_t dh = (h0 - l0) * s0;
-    // this slice's rows in the finest layout, and in the compact level grid
-    const int64_t frowi = a.tnod[t] * a.S0 + (a.fmap.t0 ? a.fmap.t0[i] : i * a.fmap.s0);
-    const int64_t lrow = t * sm + (i * a.m1 + j0) * a.m2;
-    int64_t frw[TF_ROWS];
-#pragma unroll
-    for (int jr = 0; jr < TF_ROWS; ++jr) {
-      const int64_t j = j0 + min(jr, nr - 1);
-      frw[jr] = frowi + (a.fmap.t0 ? a.fmap.t1[j] : j * a.fmap.s1);
-    }
+    const TS *cl = a.crs + (DEC ? t - 1 : q) * ss, *cr = a.crs + (DEC ? t + 1 : q + 1) * ss;
+    const int64_t fslice = a.tnod[t] * a.S0;  // this slice in the finest layout
     for (int64_t k0 = 0; k0 < a.m2; k0 += TF_CH) {
       const int64_t k1 = min(k0 + TF_CH, a.m2);
       const int nk = (int)(k1 - k0);
-      // this thread's fine values first (branch-free: a column past the end
-      // reads the last one and is not stored)
-      TS x[TF_KPT][TF_ROWS];
-      int64_t fcol[TF_KPT];
-#pragma unroll
-      for (int u = 0; u < TF_KPT; ++u) {
-        const int64_t k = k0 + min(tid + u * TF_THR, nk - 1);
-        fcol[u] = a.fmap.t0 ? a.fmap.t2[k] : k;
-#pragma unroll
-        for (int jr = 0; jr < TF_ROWS; ++jr)
-          x[u][jr] = a.src[DEC ? lrow + min(jr, nr - 1) * a.m2 + k : frw[jr] + fcol[u]];
-      }
       int64_t K0, K1;
       nb_dim<false>(k0, a.m2, a.c2, a.co2, a.r2, K0, hi, w);
       nb_dim<false>(k1 - 1, a.m2, a.c2, a.co2, a.r2, lo, K1, w);
-      // coarse rows J0..J1 (TF_ROWS / 2 + 1 of them along a coarsened dim 1,
-      // up to TF_ROWS otherwise), columns K0..K1: each thread keeps its
-      // columns and walks the rows, all loads in flight
-      const int nK = (int)(K1 - K0 + 1), nJ = (int)(J1 - J0 + 1);
-      for (int kr = tid; kr < nK; kr += TF_THR) {
-        const int64_t oc = cpos(K0 + kr, a.m2, a.c2, a.co2);
-        TS v[4][TF_ROWS];
+      const int nK = (int)(K1 - K0 + 1);
+      // this thread's column (a column past the end reads the last one and is not stored)
+      const int64_t k = k0 + min(tid, nk - 1);
+      const int64_t fcol = a.fmap.t0 ? a.fmap.t2[k] : k;
+      int64_t kl, kh;
+      double wk;
+      nb_dim<false>(k, a.m2, a.c2, a.co2, a.r2, kl, kh, wk);
+      const int ql = (int)(kl - K0), qh = (int)(kh - K0);
+      const int64_t oc = cpos(K0 + min(tid, nK - 1), a.m2, a.c2, a.co2);  // staged coarse column
+      int64_t slot[2] = {-1, -1};  // coarse plane held by each LDS slot (the same in every thread)
+      // row jr of plane i in the finest layout, and in the compact level grid
+      auto frow = [&](int64_t i, int jr) -> int64_t {
+        const int64_t j = j0 + min(jr, nr - 1);
+        return fslice + (a.fmap.t0 ? a.fmap.t0[i] + a.fmap.t1[j] : i * a.fmap.s0 + j * a.fmap.s1);
+      };
+      auto lrow = [&](int64_t i, int jr) -> int64_t { return t * sm + (i * a.m1 + j0 + min(jr, nr - 1)) * a.m2; };
+      // fine values of a plane; the recomposition loads the next plane's
+      // while this one is interpolated (measured faster there, not in the
+      // decomposition, whose staging then also waits for them)
+      constexpr bool PF = !DEC;
+      auto loadx = [&](int64_t i, TS (&xx)[TF_ROWS]) {
 #pragma unroll
-        for (int jr = 0; jr < TF_ROWS; ++jr) {
-          const int64_t o = cpos(J0 + min(jr, nJ - 1), a.m1, a.c1, a.co1) * s1 + oc;
-          v[0][jr] = cl[o];
-          v[1][jr] = cl[o + dh];
-          v[2][jr] = cr[o];
-          v[3][jr] = cr[o + dh];
+        for (int jr = 0; jr < TF_ROWS; ++jr) xx[jr] = a.src[DEC ? lrow(i, jr) + k : frow(i, jr) + fcol];
+      };
+      TS x[TF_ROWS];
+      if constexpr (PF) loadx(i0, x);
+      for (int64_t i = i0; i < i1; ++i) {
+        int64_t l0, h0;
+        double w0;
+        nb_dim<DEC>(i, a.m0, a.c0, a.co0, a.r0, l0, h0, w0);
+        TS xn[TF_ROWS];
+        if constexpr (PF) {
+          if (i + 1 < i1) {
+            loadx(i + 1, xn);
+          } else {
+#pragma unroll
+            for (int jr = 0; jr < TF_ROWS; ++jr) xn[jr] = x[jr];
+          }
+        } else {
+          loadx(i, x);
         }
+        // coarse planes l0 and h0 into the slots (a slot is refilled only
+        // after the previous plane's barrier: nothing reads it any more)
+        int sl = slot[0] == l0 ? 0 : (slot[1] == l0 ? 1 : -1);
+        int sh = slot[0] == h0 ? 0 : (slot[1] == h0 ? 1 : -1);
+        auto stage = [&](int sidx, int64_t p) {
+          if (tid < nK) {
+            TS vl[TF_ROWS], vr[TF_ROWS];
 #pragma unroll
-        for (int jr = 0; jr < TF_ROWS; ++jr)
-          if (jr < nJ)
-            sR[jr * TF_PITCH + kr] =
-                lerp(lerp((double)v[0][jr], (double)v[1][jr], w0), lerp((double)v[2][jr], (double)v[3][jr], w0), rt);
-      }
-      __syncthreads();
-      // fine nodes: each thread keeps its columns (neighbours, weight) and
-      // walks the rows, whose neighbours are the same for every thread
+            for (int jr = 0; jr < TF_ROWS; ++jr) {
+              const int64_t o = p * s0 + cpos(J0 + min(jr, nJ - 1), a.m1, a.c1, a.co1) * s1 + oc;
+              vl[jr] = cl[o];
+              vr[jr] = cr[o];
+            }
 #pragma unroll
-      for (int u = 0; u < TF_KPT; ++u) {
-        const int kk = tid + u * TF_THR;
-        if (kk >= nk) break;
-        const int64_t k = k0 + kk;
-        int64_t kl, kh;
-        double wk;
-        nb_dim<false>(k, a.m2, a.c2, a.co2, a.r2, kl, kh, wk);
-        const int ql = (int)(kl - K0), qh = (int)(kh - K0);
+            for (int jr = 0; jr < TF_ROWS; ++jr)
+              if (jr < nJ) sT[sidx][jr * TF_PITCH + tid] = lerp((double)vl[jr], (double)vr[jr], rt);
+          }
+          slot[sidx] = p;
+        };
+        if (sl < 0) {
+          sl = sh == 0 ? 1 : 0;
+          stage(sl, l0);
+        }
+        if (sh < 0) {
+          if (h0 == l0) {
+            sh = sl;
+          } else {
+            sh = 1 - sl;
+            stage(sh, h0);
+          }
+        }
+        __syncthreads();
+        if (tid < nk) {
+          const double *Tl = sT[sl], *Th = sT[sh];
+          const bool mid = h0 != l0;  // between two coarse planes: lerp along dim 0
+          auto val = [&](int jj, int qq) -> double {
+            const double v = Tl[jj * TF_PITCH + qq];
+            return mid ? lerp(v, Th[jj * TF_PITCH + qq], w0) : v;
+          };
 #pragma unroll
-        for (int jr = 0; jr < TF_ROWS; ++jr) {
-          if (jr >= nr) break;
-          int64_t jl, jh;
-          double wj;
-          nb_dim<false>(j0 + jr, a.m1, a.c1, a.co1, a.r1, jl, jh, wj);
-          const double *rl = sR + (jl - J0) * TF_PITCH, *rh = sR + (jh - J0) * TF_PITCH;
-          const double pi = lerp(lerp(rl[ql], rl[qh], wk), lerp(rh[ql], rh[qh], wk), wj);
-          if (DEC)
-            a.dst[frw[jr] + fcol[u]] = (T)((double)x[u][jr] - pi);
-          else
-            a.dst[lrow + jr * a.m2 + k] = (T)((double)x[u][jr] + pi);
+          for (int jr = 0; jr < TF_ROWS; ++jr) {
+            if (jr >= nr) break;
+            int64_t jl, jh;
+            double wj;
+            nb_dim<false>(j0 + jr, a.m1, a.c1, a.co1, a.r1, jl, jh, wj);
+            const int rl = (int)(jl - J0), rh = (int)(jh - J0);
+            const double pi = lerp(lerp(val(rl, ql), val(rl, qh), wk), lerp(val(rh, ql), val(rh, qh), wk), wj);
+            if (DEC)
+              a.dst[frow(i, jr) + fcol] = (T)((double)x[jr] - pi);
+            else
+              a.dst[lrow(i, jr) + k] = (T)((double)x[jr] + pi);
+          }
+        }
+        __syncthreads();
+        if constexpr (PF) {
+#pragma unroll
+          for (int jr = 0; jr < TF_ROWS; ++jr) x[jr] = xn[jr];
         }
       }
-      __syncthreads();
     }
   }
 }
@@ -2996,7 +3030,8 @@ void launch_tfine(const Plan &pl, const Level &L, const Level &Lt, const TS *src
   a.co0 = L.co[0]; a.co1 = L.co[1]; a.co2 = L.co[2];
   a.r0 = L.d[0].r; a.r1 = L.d[1].r; a.r2 = L.d[2].r;
   const int64_t sm = L.m[0] * L.m[1] * L.m[2];
-  const int64_t jobs = nf * L.m[0] * ((L.m[1] + TF_ROWS - 1) / TF_ROWS);  // row groups of the time-fine slices
+  // (row group, plane chunk) jobs of the time-fine slices
+  const int64_t jobs = nf * ((L.m[0] + TF_PI - 1) / TF_PI) * ((L.m[1] + TF_ROWS - 1) / TF_ROWS);
   const dim3 grid((unsigned)std::min<int64_t>(jobs, (int64_t)1 << 20));
   const std::string label = std::string("k_tfine<") + tname<T>() + ", " + bname(DEC) + ">";
   const double bytes = timing_enabled() ? (double)nf * (double)sm * (sizeof(T) + sizeof(TS)) : 0.0;
