@@ -477,6 +477,83 @@ bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
   return x < y + nb && y < x + na;
 }
 
+// Streams of a batch's fields.  Per-field chains: largest first, each to the
+// least loaded stream (by bytes).  Grouped launches: the fields of one class
+// (rank and element type) share their kernels' launches, so a class stays on
+// as few streams as it can: every class gets one stream, the streams left
+// over go one at a time to the class with the most bytes per stream (no
+// more streams than fields), and a class's fields go largest first to the
+// least loaded of its streams; with more classes than streams, whole
+// classes go largest first to the least loaded stream.  (A 64-field batch of
+// four classes: 4.3 -> 3.5 ms from a graph against the per-field rule.)
+void batch_lanes(int nfields, const mgr_field *fields, const std::vector<FieldJob> &jobs, const std::vector<int> &order,
+                 bool grouped, std::vector<int> &lane) {
+  constexpr int S = MGR_BATCH_STREAMS;
+  double load[S] = {};
+  auto least = [&](const std::vector<int> &ks) {
+    int k = ks[0];
+    for (int q : ks)
+      if (load[q] < load[k]) k = q;
+    return k;
+  };
+  std::vector<int> all(S);
+  for (int k = 0; k < S; ++k) all[k] = k;
+  if (!grouped) {
+    for (int i : order) {
+      const int k = least(all);
+      lane[i] = k;
+      load[k] += (double)jobs[i].bytes;
+    }
+    return;
+  }
+  // classes, most bytes first
+  std::vector<int> key(nfields), ckey;
+  std::vector<double> cbytes;
+  std::vector<int> cfields;
+  for (int i = 0; i < nfields; ++i) {
+    key[i] = fields[i].ndim * 2 + (fields[i].dtype == MGR_FLOAT64 ? 1 : 0);
+    const auto it = std::find(ckey.begin(), ckey.end(), key[i]);
+    if (it == ckey.end()) {
+      ckey.push_back(key[i]);
+      cbytes.push_back((double)jobs[i].bytes);
+      cfields.push_back(1);
+    } else {
+      cbytes[it - ckey.begin()] += (double)jobs[i].bytes;
+      ++cfields[it - ckey.begin()];
+    }
+  }
+  const int nc = (int)ckey.size();
+  std::vector<int> corder(nc);
+  for (int c = 0; c < nc; ++c) corder[c] = c;
+  std::stable_sort(corder.begin(), corder.end(), [&](int a, int b) { return cbytes[a] > cbytes[b]; });
+  std::vector<std::vector<int>> lanes_of(nc);
+  if (nc >= S) {
+    for (int c : corder) {
+      const int k = least(all);
+      lanes_of[c].push_back(k);
+      load[k] += cbytes[c];
+    }
+  } else {
+    std::vector<int> nl(nc, 1);
+    for (int r = nc; r < S; ++r) {
+      int best = -1;
+      for (int c : corder)
+        if (nl[c] < cfields[c] && (best < 0 || cbytes[c] / nl[c] > cbytes[best] / nl[best])) best = c;
+      if (best < 0) break;
+      ++nl[best];
+    }
+    int next = 0;
+    for (int c : corder)
+      for (int j = 0; j < nl[c]; ++j) lanes_of[c].push_back(next++);
+  }
+  for (int i : order) {
+    const int c = (int)(std::find(ckey.begin(), ckey.end(), key[i]) - ckey.begin());
+    const int k = nc >= S ? lanes_of[c][0] : least(lanes_of[c]);
+    lane[i] = k;
+    if (nc < S) load[k] += (double)jobs[i].bytes;
+  }
+}
+
 mgr_status run_batch(bool dec, int nfields, const mgr_field *fields, void *ws, size_t ws_bytes,
                      void *stream, int flags) {
   g_last_error.clear();
@@ -521,20 +598,12 @@ mgr_status run_batch(bool dec, int nfields, const mgr_field *fields, void *ws, s
       const hipError_t e = hipGetLastError();
       return fail(MGR_ERR_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
     }
-    // largest fields first, each to the least loaded stream
     std::vector<int> order(nfields);
     for (int i = 0; i < nfields; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(),
                      [&](int a, int b) { return jobs[a].bytes > jobs[b].bytes; });
     std::vector<int> lane(nfields);
-    double load[MGR_BATCH_STREAMS] = {};
-    for (int i : order) {
-      int k = 0;
-      for (int q = 1; q < MGR_BATCH_STREAMS; ++q)
-        if (load[q] < load[k]) k = q;
-      lane[i] = k;
-      load[k] += (double)jobs[i].bytes;
-    }
+    batch_lanes(nfields, fields, jobs, order, grouped, lane);
     std::lock_guard<std::mutex> lk(g_bmu);
     BatchStreams *bs = nullptr;
     s = batch_streams(dev, bs);
