@@ -2176,9 +2176,9 @@ struct RecJob {
 };
 struct Rec {
   std::vector<RecJob> jobs;
-  // plane-marching kernels take the longest chunks their LDS window allows
-  // (batches: a grouped grid of many fields' workgroups fills the device
-  // without short chunks, and long ones re-read the fewest halo planes)
+  // plane-marching kernels take chunks of at least 8 coarse planes (batches:
+  // a grouped grid of many fields' workgroups fills the device without the
+  // short chunks one field alone needs, which re-read 1 or 2 halo planes each)
   bool long_chunks = false;
 };
 
@@ -2332,7 +2332,7 @@ void launch_loadvec_t(LoadArgs<T, TS> a, Ctx &cx) {
   const int64_t maxti = (LV_MAXP - 3) / 2;
   a.TI = cx.ti_req > 0 ? std::min<int64_t>(std::min<int64_t>(cx.ti_req, maxti), a.c0)
                        : pick_chunk(a.c0, tiles, slots, C0 ? 2 : 0, maxti);
-  if (cx.rec && cx.rec->long_chunks && cx.ti_req <= 0) a.TI = std::min<int64_t>(maxti, a.c0);
+  if (cx.rec && cx.rec->long_chunks && cx.ti_req <= 0) a.TI = std::max<int64_t>(a.TI, std::min<int64_t>(8, a.c0));
   if (cx.share && !NODAL) {
     // Beside other work (the recomposition's finest load vector on the helper
     // stream): one round of workgroups that leaves about 5% of the resident
@@ -2627,7 +2627,7 @@ void launch_reconstruct_t(ReconArgs<T> a, Ctx &cx, const std::string &label, dou
   const int64_t maxti = (LV_MAXP - 2) / 2;
   a.TI = cx.ti_req > 0 ? std::min<int64_t>(std::min<int64_t>(cx.ti_req, maxti), a.c0)
                        : pick_chunk(a.c0, tiles, slots, C0 ? 1 : 0, maxti);
-  if (cx.rec && cx.rec->long_chunks && cx.ti_req <= 0) a.TI = std::min<int64_t>(maxti, a.c0);
+  if (cx.rec && cx.rec->long_chunks && cx.ti_req <= 0) a.TI = std::max<int64_t>(a.TI, std::min<int64_t>(8, a.c0));
   cx.slots_out = slots;
   cx.ti_out = (int)a.TI;
   if (cx.dry) return;
@@ -3501,8 +3501,9 @@ bool enqueue_batch(bool dec, const std::vector<std::vector<BatchItem>> &lanes, c
                    std::string &err) {
   const size_t nl = lanes.size();
   std::vector<Rec> recs(nl);
-  // (64-field batch 3.56 -> 3.16 ms from a graph; the 4-D drivers' grouped
-  // slices keep the single-field rule: 400^3 x 16 was 913 -> 842 GB/s with it)
+  // (64-field batch 3.5 -> 2.95 ms from a graph; the 4-D drivers' grouped
+  // slices keep the single-field rule: 400^3 x 16 was 913 -> 842 GB/s with
+  // the longest chunks)
   for (Rec &r : recs) r.long_chunks = true;
   {
     const PlainLoadVector plain;  // batches keep k_loadvec (see mgr_api.cpp)
