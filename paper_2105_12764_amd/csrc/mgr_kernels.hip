@@ -2176,9 +2176,10 @@ struct RecJob {
 };
 struct Rec {
   std::vector<RecJob> jobs;
-  // plane-marching kernels take chunks of at least 8 coarse planes (batches:
-  // a grouped grid of many fields' workgroups fills the device without the
-  // short chunks one field alone needs, which re-read 1 or 2 halo planes each)
+  // plane-marching kernels take chunks of at least 8 coarse planes, also
+  // where a field's tuned shape has shorter ones (batches: a grouped grid of
+  // many fields' workgroups fills the device without the short chunks one
+  // field alone needs, which re-read 1 or 2 halo planes each)
   bool long_chunks = false;
 };
 
@@ -2332,7 +2333,7 @@ void launch_loadvec_t(LoadArgs<T, TS> a, Ctx &cx) {
   const int64_t maxti = (LV_MAXP - 3) / 2;
   a.TI = cx.ti_req > 0 ? std::min<int64_t>(std::min<int64_t>(cx.ti_req, maxti), a.c0)
                        : pick_chunk(a.c0, tiles, slots, C0 ? 2 : 0, maxti);
-  if (cx.rec && cx.rec->long_chunks && cx.ti_req <= 0) a.TI = std::max<int64_t>(a.TI, std::min<int64_t>(8, a.c0));
+  if (cx.rec && cx.rec->long_chunks) a.TI = std::max<int64_t>(a.TI, std::min<int64_t>(8, a.c0));
   if (cx.share && !NODAL) {
     // Beside other work (the recomposition's finest load vector on the helper
     // stream): one round of workgroups that leaves about 5% of the resident
@@ -2627,7 +2628,7 @@ void launch_reconstruct_t(ReconArgs<T> a, Ctx &cx, const std::string &label, dou
   const int64_t maxti = (LV_MAXP - 2) / 2;
   a.TI = cx.ti_req > 0 ? std::min<int64_t>(std::min<int64_t>(cx.ti_req, maxti), a.c0)
                        : pick_chunk(a.c0, tiles, slots, C0 ? 1 : 0, maxti);
-  if (cx.rec && cx.rec->long_chunks && cx.ti_req <= 0) a.TI = std::max<int64_t>(a.TI, std::min<int64_t>(8, a.c0));
+  if (cx.rec && cx.rec->long_chunks) a.TI = std::max<int64_t>(a.TI, std::min<int64_t>(8, a.c0));
   cx.slots_out = slots;
   cx.ti_out = (int)a.TI;
   if (cx.dry) return;
