@@ -27,6 +27,11 @@ CASES = [
     ((3, 5, 5, 5), 1, False, np.float64),
     ((9, 33, 33, 33), None, True, np.float32),
     ((16, 20, 30, 41), 3, False, np.float32),
+    # rows longer than one 256-column pass of the time-fine kernel (ragged
+    # last pass), dim-0 extents not a multiple of its 16-plane chunks
+    ((5, 20, 6, 300), None, True, np.float64),
+    ((7, 35, 4, 270), None, True, np.float64),
+    ((3, 17, 5, 520), None, False, np.float32),
 ]
 
 
