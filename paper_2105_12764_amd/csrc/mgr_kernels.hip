@@ -1184,11 +1184,18 @@ __global__ void __launch_bounds__(ROWS_THR) k_solve_rows_group(Group<RowsArgs<T>
 }
 
 // Lines of more than kMaxBlocks partitions of 64 (up to kLongBlocks): the
-// same partitioned solve, with each wave taking partitions w, w + LONG_WAVES,
-// ... in turn.  The interior solutions wait in F between the elimination and
-// the separator fix-up, so such a line is read and written twice.  Lanes are
-// lines: 64 adjacent lines of a strided dimension (coalesced), or 64 rows of
-// the contiguous one (each lane walks its own row).
+// same partitioned solve.  A workgroup takes a block of LB lines; the lanes
+// of a wave hold 64 / LB partition groups of those lines, and group g of
+// wave w takes partitions v, v + NV, ... (v = w * 64 / LB + g, NV the groups
+// of the workgroup) in turn.  The interior solutions wait
+// in F between the elimination and the separator fix-up, so such a line is
+// read and written twice.  LB = 64: a wave takes one partition of 64 lines
+// (its solve-table reads are uniform); LB = 16 gives four times the
+// workgroups, for launches that would leave most CUs idle (a 2-D field's
+// lines: 4097 lines of level 0 at 8193^2 are 65 blocks of 64), at the cost
+// of per-lane table reads.  Adjacent lines of a strided dimension are read
+// in whole 128-byte lines; rows of the contiguous one have each lane walk
+// its own row.
 constexpr int LONG_WAVES = 8;
 constexpr int LONG_CH = 16;  // fix-up chunk
 template <typename T>
@@ -1200,8 +1207,8 @@ struct LongArgs {
   Epi<T> ep;
 };
 
-// Blocks of 64 lines in (outer, k-block) order; this workgroup takes block `blk`.
-template <typename T>
+// Blocks of LB lines in (outer, k-block) order; this workgroup takes block `blk`.
+template <typename T, int LB>
 __device__ __forceinline__ void long_body(const LongArgs<T> &A, const int64_t blk) {
   double *F = A.F;
   const int64_t c = A.c, nk = A.nk, sp_ = A.sp, so = A.so, sk = A.sk, c1 = A.c1;
@@ -1209,16 +1216,21 @@ __device__ __forceinline__ void long_body(const LongArgs<T> &A, const int64_t bl
   const SolveDev &tb = A.tb;
   const Epi<T> &ep = A.ep;
   constexpr int S = 64;
-  extern __shared__ double xs[];  // yF, yL, Fs, t: [P][64] each
+  constexpr int NG = 64 / LB;       // partition groups per wave
+  constexpr int NV = LONG_WAVES * NG;    // partition groups per workgroup
+  extern __shared__ double xs[];  // yF, yL, Fs, t: [P][LB] each
   const int lane = threadIdx.x & 63;
-  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t nkb = (nk + 63) / 64;
-  const int64_t k = (blk % nkb) * 64 + lane;
+  const int l = lane % LB;
+  // this thread's partition group (LB = 64: the wave, made uniform so that
+  // the table reads are scalar)
+  const int v = LB == 64 ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : (threadIdx.x >> 6) * NG + lane / LB;
+  const int64_t nkb = (nk + LB - 1) / LB;
+  const int64_t k = (blk % nkb) * LB + l;
   const int64_t outer = blk / nkb;
   const bool active = k < nk;
   const int64_t base = outer * so + (active ? k : 0) * sk;
-  double *yF = xs, *yL = xs + P * 64, *Fs = xs + 2 * P * 64, *tt = xs + 3 * P * 64;
-  for (int p = w; p < P; p += LONG_WAVES) {
+  double *yF = xs, *yL = xs + P * LB, *Fs = xs + 2 * P * LB, *tt = xs + 3 * P * LB;
+  for (int p = v; p < P; p += NV) {
     const int64_t f = (int64_t)p * S;
     const int nload = p < P - 1 ? S : (int)(c - f);
     const int nint = p < P - 1 ? S - 1 : nload;
@@ -1226,9 +1238,9 @@ __device__ __forceinline__ void long_body(const LongArgs<T> &A, const int64_t bl
 #pragma unroll
     for (int q = 0; q < S; ++q) x[q] = (active && q < nload) ? F[base + (f + q) * sp_] : 0.0;
     partition_solve<S>(x, tb, f);
-    yF[p * 64 + lane] = x[0];
-    yL[p * 64 + lane] = pick<S>(x, nint - 1);
-    Fs[p * 64 + lane] = x[S - 1];
+    yF[p * LB + l] = x[0];
+    yL[p * LB + l] = pick<S>(x, nint - 1);
+    Fs[p * LB + l] = x[S - 1];
     if (active) {
 #pragma unroll
       for (int q = 0; q < S; ++q)
@@ -1236,17 +1248,17 @@ __device__ __forceinline__ void long_body(const LongArgs<T> &A, const int64_t bl
     }
   }
   __syncthreads();
-  if (w == 0) separator_solve(tb, S, P, yF + lane, yL + lane, Fs + lane, tt + lane, 64);
+  if (v == 0) separator_solve(tb, S, P, yF + l, yL + l, Fs + l, tt + l, LB);
   __syncthreads();
   if (!active) return;
   // fix-up in chunks of LONG_CH positions, a chunk's loads all in flight
   // before its first use
-  for (int p = w; p < P; p += LONG_WAVES) {
+  for (int p = v; p < P; p += NV) {
     const int64_t f = (int64_t)p * S;
     const int nload = p < P - 1 ? S : (int)(c - f);
     const int nint = p < P - 1 ? S - 1 : nload;
-    const double tl = p > 0 ? tt[(p - 1) * 64 + lane] : 0.0;
-    const double tr = p < P - 1 ? tt[p * 64 + lane] : 0.0;
+    const double tl = p > 0 ? tt[(p - 1) * LB + l] : 0.0;
+    const double tr = p < P - 1 ? tt[p * LB + l] : 0.0;
     for (int q0 = 0; q0 < nload; q0 += LONG_CH) {
       double x[LONG_CH];
 #pragma unroll
@@ -1256,27 +1268,27 @@ __device__ __forceinline__ void long_body(const LongArgs<T> &A, const int64_t bl
         const int q = q0 + u;
         if (q < nload) {
           const int64_t pos = f + q;
-          const double v = q < nint ? fma(-tl, tb.Ls[pos], fma(-tr, tb.Rs[pos], x[u])) : tr;
+          const double val = q < nint ? fma(-tl, tb.Ls[pos], fma(-tr, tb.Rs[pos], x[u])) : tr;
           int64_t i, j, kk;
           if (axis == 0) { i = pos; j = outer; kk = k; }
           else if (axis == 1) { i = outer; j = pos; kk = k; }
           else { i = k / c1; j = k % c1; kk = pos; }
-          epi_store(ep, F, base + pos * sp_, i, j, kk, v);
+          epi_store(ep, F, base + pos * sp_, i, j, kk, val);
         }
       }
     }
   }
 }
 
-template <typename T>
+template <typename T, int LB>
 __global__ void __launch_bounds__(64 * LONG_WAVES) k_solve_long(LongArgs<T> a) {
-  long_body<T>(a, blockIdx.x);
+  long_body<T, LB>(a, blockIdx.x);
 }
-template <typename T>
+template <typename T, int LB>
 __global__ void __launch_bounds__(64 * LONG_WAVES) k_solve_long_group(Group<LongArgs<T>> g) {
   int j, b;
   group_locate(g, j, b);
-  long_body<T>(g.job[j], b);
+  long_body<T, LB>(g.job[j], b);
 }
 
 // Sequential Thomas per line (lines longer than kLongBlocks partitions of
@@ -2538,24 +2550,41 @@ void launch_rows_s(double *F, const Level &L, const Epi<T> &ep, Ctx &cx) {
   });
 }
 
-template <typename T>
-void launch_long(double *F, const Level &L, int axis, const Epi<T> &ep, Ctx &cx) {
+template <typename T, int LB>
+void launch_long_lb(double *F, const Level &L, int axis, const Epi<T> &ep, Ctx &cx) {
   const DimTabs &d = L.d[axis];
   const int64_t c0 = L.c[0], c1 = L.c[1], c2 = L.c[2];
   int64_t sp_, so, sk, nk, nouter;
   if (axis == 0) { sp_ = c1 * c2; so = c2; sk = 1; nk = c2; nouter = c1; }
   else if (axis == 1) { sp_ = c2; so = c1 * c2; sk = 1; nk = c2; nouter = c0; }
   else { sp_ = 1; so = 0; sk = c2; nk = c0 * c1; nouter = 1; }
-  dim3 grid((unsigned)(((nk + 63) / 64) * nouter));
-  const size_t lds = (size_t)4 * d.P * 64 * sizeof(double);
+  dim3 grid((unsigned)(((nk + LB - 1) / LB) * nouter));
+  const size_t lds = (size_t)4 * d.P * LB * sizeof(double);
   const LongArgs<T> la{F, L.c[axis], nk, sp_, so, sk, c1, d.P, axis, solve_dev(d), ep};
   // the interior solutions are written and re-read once more
-  std::string label = std::string("k_solve_long<") + tname<T>() + ">" + epi_tag(ep.mode);
+  std::string label = std::string("k_solve_long<") + tname<T>() + ", " + std::to_string(LB) + ">" + epi_tag(ep.mode);
   const double bytes = solve_bytes<T>((double)c0 * c1 * c2, ep.mode);
-  emit<LongArgs<T>, k_solve_long_group<T>>(cx, la, (int64_t)grid.x, 64 * LONG_WAVES, lds, label, bytes, [&] {
+  emit<LongArgs<T>, k_solve_long_group<T, LB>>(cx, la, (int64_t)grid.x, 64 * LONG_WAVES, lds, label, bytes, [&] {
     TimedLaunch tl(cx.stream, label, timing_enabled() ? bytes : 0.0);
-    hipLaunchKernelGGL((k_solve_long<T>), grid, dim3(64 * LONG_WAVES), lds, cx.stream, la);
+    hipLaunchKernelGGL((k_solve_long<T, LB>), grid, dim3(64 * LONG_WAVES), lds, cx.stream, la);
   });
+}
+
+// Blocks of 16 lines for lines of more than 32 partitions (the separator
+// data of 64 lines would not fit in 64 KB of LDS) and where blocks of 64
+// would not give every CU a workgroup (2-D fields: 8193^2 FP64 54 -> 258
+// GB/s with the first two); 64 otherwise, also in batches, whose grouped
+// launches hold many fields' blocks (the mixed 64-field batch measured 3%
+// slower with 16).
+template <typename T>
+void launch_long(double *F, const Level &L, int axis, const Epi<T> &ep, Ctx &cx) {
+  const int64_t nk = axis == 2 ? L.c[0] * L.c[1] : L.c[2];
+  const int64_t nouter = axis == 0 ? L.c[1] : (axis == 1 ? L.c[0] : 1);
+  const bool batch = cx.rec && cx.rec->long_chunks;
+  if (L.d[axis].P > 32 || (!batch && ((nk + 63) / 64) * nouter < 256))
+    launch_long_lb<T, 16>(F, L, axis, ep, cx);
+  else
+    launch_long_lb<T, 64>(F, L, axis, ep, cx);
 }
 
 template <typename T>

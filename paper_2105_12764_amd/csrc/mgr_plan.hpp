@@ -15,7 +15,7 @@ namespace mgr {
 constexpr int kDims = 3;        // internal rank: leading dims of size 1 pad 1-D/2-D
 constexpr int kTaps = 5;        // load-vector row: fine positions 2J-2 .. 2J+2
 constexpr int kMaxBlocks = 16;  // partitions per line in the register solvers
-constexpr int kLongBlocks = 32; // partitions of 64 per line in the long-line solver
+constexpr int kLongBlocks = 128; // partitions of 64 per line in the long-line solver (its LDS: 64 KB)
 constexpr int kMaxLevels = 62;
 
 // Device pointers of the tables of one dimension at one level.

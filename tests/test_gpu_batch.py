@@ -28,7 +28,8 @@ FIELDS = [
     ((2, 2, 2), 0, False, np.float64),
     ((40, 150, 2), 2, True, np.float32),
     ((2100, 5), None, True, np.float64),   # lines of 1051 unknowns: the long-line solver
-    ((4100, 3), 2, False, np.float32),     # lines of 2051: the sequential solver (launched alone)
+    ((4100, 3), 2, False, np.float32),     # lines of 2051: the long-line solver, 33 partitions
+    ((16500, 3), 2, True, np.float64),     # lines of 8251: the sequential solver (launched alone)
 ]
 MODES = [False, True]  # per_field
 

@@ -122,7 +122,10 @@ SMALL = [
     ((300, 41), None, True, np.float64),
     ((1000,), None, True, np.float64),          # 1-D
     ((65,), 3, False, np.float64),
-    ((5000,), 4, True, np.float64),             # line > 2048 unknowns: sequential solver
+    ((5000,), 4, True, np.float64),             # line of 2501 unknowns: long-line solver, 40 partitions
+    ((17000,), 2, True, np.float64),            # line > 8192 unknowns: sequential solver
+    ((9000, 20), 2, True, np.float32),          # strided lines of 4501: long-line solver, 71 partitions
+    ((20, 6000), 2, True, np.float64),          # rows of 3001: long-line solver, 47 partitions
     ((3000, 40), 2, True, np.float64),          # strided line of 1501: long-line solver
     ((40, 3000), 2, True, np.float64),          # row of 1501: long-line solver
     ((2049, 9), 1, False, np.float64),          # 1025 unknowns: 17 partitions of 64
